@@ -1,0 +1,197 @@
+/*
+ * dog.h - C ABI of the MI355X (gfx950) Difference-of-Gaussians blob detector.
+ *
+ * The method is the DoG blob detector of arXiv:2010.08486 ("Towards Online
+ * Steering of Flame Spray Pyrolysis Nanoparticle Synthesis"):
+ *   - scale space L(x, y, sigma) = g(sigma) * I                  (Sec. 3)
+ *   - a ladder of standard deviations sigma_i, here geometric:
+ *     k = floor(ln(sigma_max/sigma_min)/ln(sigma_ratio)) + 1 DoG planes,
+ *     sigma_i = sigma_min * sigma_ratio^i, i = 0..k               (Sec. 4, Eq. 1
+ *                                                                  in geometric form)
+ *   - Gaussian kernels sampled out to radius floor(truncate*sigma + 0.5),
+ *     normalised to sum 1, reflect (half-sample symmetric) borders (Sec. 4.1)
+ *   - D_i = sigma_i * (L_i - L_{i+1})                              (Sec. 4, Eq. 2-3;
+ *     sign chosen so bright blobs give positive maxima)
+ *   - a voxel (i, y, x) is a blob iff D_i(y, x) equals the maximum of its
+ *     3x3x3 neighbourhood over (x, y, scale) (neighbours outside the cube
+ *     ignored, every tied voxel kept) and D_i(y, x) > threshold (strict)
+ *                                                                 (Sec. 4 local-maximum
+ *                                                                  heuristic, Sec. 4.1 Thresh)
+ *   - blob radius sqrt(2)*sigma_i (Sec. 3); overlap pruning (Sec. 4.1): for
+ *     blobs in (y, x, scale) order, pairs whose disk intersection exceeds
+ *     `overlap` times the smaller disk's area lose the blob with the smaller
+ *     sigma (the later one on a tie).  overlap >= 1 disables pruning.
+ *
+ * Conventions for every entry point:
+ *   - Return value: DOG_OK (0) or a negative DOG_E* code.  On error nothing
+ *     is returned through output pointers (they are set to NULL / 0) and
+ *     dog_last_error() describes the failure (thread-local string).
+ *   - Images are fp32, row-major, `height` rows of `width` pixels, rows
+ *     `row_stride` elements apart (row_stride >= width).  Pixels must be
+ *     finite.  1 <= height, width <= 32768, height * row_stride < 2^29 and
+ *     width * (height + 63) < 2^29 (every plane stays below 2 GiB).
+ *   - Blob lists are sorted by (y, x, scale), allocated with malloc by the
+ *     library and released with dog_blobs_free().
+ *   - Streams are hipStream_t values passed as void* (NULL = the context's
+ *     own stream).  Device entry points are synchronous with respect to the
+ *     host: they return after the results have been copied back.
+ */
+#ifndef DOG_H
+#define DOG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DOG_OK 0
+#define DOG_EINVAL (-1)   /* invalid argument                                  */
+#define DOG_ENOMEM (-2)   /* footprint exceeds the HBM budget / allocation failed */
+#define DOG_EDEVICE (-3)  /* HIP runtime error (message in dog_last_error)      */
+#define DOG_EBUSY (-4)    /* server queue full                                  */
+#define DOG_EAGAIN (-5)   /* server result not ready yet                        */
+#define DOG_ENOTFOUND (-6)/* unknown server ticket                              */
+
+/* One detected blob.  y = row, x = column (0-based, the pixel of the DoG
+ * maximum); scale = ladder index i (0..k-1); sigma = sigma_i (the lower
+ * sigma of the pair, Sec. 4 Eq. 3); response = D_i(y, x) as computed in fp32;
+ * the blob radius is sqrt(2)*sigma (Sec. 3). */
+typedef struct {
+    int32_t y;
+    int32_t x;
+    int32_t scale;
+    float sigma;
+    float response;
+} dog_blob;
+
+/* Detector hyper-parameters (Sec. 4: min_sigma, max_sigma; Sec. 4.1:
+ * truncate, threshold default 0.1, overlap default 0.5).  truncate == 0
+ * selects 4.0.  Valid: 0 < sigma_min <= sigma_max, sigma_ratio > 1, at most
+ * 63 DoG planes, finite threshold, 0 <= overlap <= 1, truncate >= 0. */
+typedef struct {
+    double sigma_min;
+    double sigma_max;
+    double sigma_ratio;
+    double threshold;
+    double overlap;
+    double truncate;
+} dog_params;
+
+/* A frame of a batch or a server request.  on_device = 1: `data` is a device
+ * pointer on the context's GPU; 0: a host pointer. */
+typedef struct {
+    const float* data;
+    int64_t height;
+    int64_t width;
+    int64_t row_stride;
+    int32_t on_device;
+    int32_t reserved;
+} dog_frame;
+
+/* Per-frame result of a batch or a server request. */
+typedef struct {
+    dog_blob* blobs;     /* malloc'd, sorted; release with dog_blobs_free   */
+    int64_t count;       /* blobs after pruning                            */
+    int64_t raw_count;   /* local maxima above threshold, before pruning   */
+    int32_t status;      /* DOG_OK or a DOG_E* code for this frame         */
+    int32_t reserved;
+    int64_t t_arrive_ns; /* server only: submit time (CLOCK_MONOTONIC ns)  */
+    int64_t t_done_ns;   /* server only: time the blob list was ready      */
+} dog_result;
+
+typedef struct dog_context dog_context;
+typedef struct dog_server dog_server;
+
+/* ------------------------------------------------------------ one frame */
+
+/* Whole detector on a HOST image, on device 0 through a library-owned
+ * context (created on first use, kept until process exit; calls are
+ * serialised).  The image is borrowed for the duration of the call.
+ * *blobs_out receives a malloc'd array of *count_out blobs (NULL if 0). */
+int dog_detect(const float* image, int64_t height, int64_t width, int64_t row_stride,
+               double sigma_min, double sigma_max, double sigma_ratio, double threshold,
+               double overlap, dog_blob** blobs_out, int64_t* count_out);
+
+/* Release a blob array returned by the library (NULL is allowed). */
+void dog_blobs_free(dog_blob* blobs);
+
+/* Host step on its own: sort blobs[0..n) by (y, x, scale) and apply the
+ * overlap pruning above in place, with sigma taken as the FP64 ladder value
+ * of each blob's scale index under `params` (the fp32 sigma field is
+ * ignored and rewritten).  *n_out receives the surviving count. */
+int dog_prune(const dog_params* params, dog_blob* blobs, int64_t n, int64_t* n_out);
+
+/* Description of the last error on the calling thread ("" if none). */
+const char* dog_last_error(void);
+
+/* Library and kernel version string. */
+const char* dog_version(void);
+
+/* ------------------------------------------------------------ contexts */
+
+/* A context owns device workspace (scale-space planes, candidate buffer,
+ * launch tables), pinned host staging and a stream on GPU `device`.
+ * hbm_budget_bytes caps the device memory it allocates (0 = 90% of the free
+ * memory at creation).  A context is not thread-safe. */
+int dog_context_create(int device, uint64_t hbm_budget_bytes, dog_context** ctx);
+void dog_context_destroy(dog_context* ctx);
+
+/* The ladder these parameters produce: *k_out DoG planes, and (when the
+ * arrays are non-NULL and cap >= k+1) the k+1 sigmas and kernel radii. */
+int dog_plan_info(const dog_params* params, int32_t* k_out, double* sigmas_out,
+                  int32_t* radii_out, int32_t cap);
+
+/* Device bytes the context would need to hold a batch of n_frames frames of
+ * the given shapes at these parameters (planes + tables + candidates). */
+int dog_footprint(const dog_params* params, int32_t n_frames, const int64_t* heights,
+                  const int64_t* widths, uint64_t* bytes_out);
+
+/* Whole detector on a DEVICE image (d_image on the context's GPU, valid until
+ * the call returns).  Work is issued on `stream` (hipStream_t, NULL = the
+ * context stream); the call returns after the blob list is on the host. */
+int dog_detect_device(dog_context* ctx, const float* d_image, int64_t height, int64_t width,
+                      int64_t row_stride, const dog_params* params, void* stream,
+                      dog_blob** blobs_out, int64_t* count_out);
+
+/* Whole detector on n_frames frames of any sizes in one launch sequence
+ * (three persistent kernels over a work table built for the batch).  Frames
+ * larger than the budget allows together are processed in consecutive
+ * launch sequences.  results[f] receives frame f's blob list; the return
+ * value is DOG_OK if every frame succeeded, else the first frame error. */
+int dog_detect_batch(dog_context* ctx, int32_t n_frames, const dog_frame* frames,
+                     const dog_params* params, void* stream, dog_result* results);
+
+/* Release the blob arrays of n results (sets them to NULL). */
+void dog_results_free(dog_result* results, int32_t n);
+
+/* Intermediate planes of the same kernels for one device image, row-major
+ * fp32 into caller-owned DEVICE buffers: L_out (k+1) x height x width
+ * Gaussian planes, D_out k x height x width DoG planes (either may be NULL),
+ * and *k_out = k.  Used by parity tests. */
+int dog_debug_planes(dog_context* ctx, const float* d_image, int64_t height, int64_t width,
+                     int64_t row_stride, const dog_params* params, float* L_out, float* D_out,
+                     int32_t* k_out);
+
+/* Unpruned candidate list (local maxima above threshold) of one device
+ * image, sorted by (y, x, scale).  Used by parity tests. */
+int dog_debug_candidates(dog_context* ctx, const float* d_image, int64_t height, int64_t width,
+                         int64_t row_stride, const dog_params* params, dog_blob** blobs_out,
+                         int64_t* count_out);
+
+/* Kernel variant (tile geometry) selection.  variant < 0 restores the
+ * autotuned choice.  dog_num_variants() variants exist; dog_variant_info
+ * describes one: S outputs per lane, waves per workgroup, strips per wave,
+ * local-maximum rows per wave. */
+int dog_num_variants(void);
+int dog_variant_info(int variant, int32_t* S, int32_t* waves, int32_t* strips, int32_t* nms_rows);
+int dog_set_variant(dog_context* ctx, int variant);
+
+/* Persistent-grid size (workgroups per kernel); 0 = automatic. */
+int dog_set_grid(dog_context* ctx, int32_t workgroups);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DOG_H */

@@ -1,0 +1,323 @@
+"""Python binding of libdog.so, the MI355X Difference-of-Gaussians blob detector.
+
+Argument marshalling only: every step of the detector runs in the library's
+HIP kernels and host runtime (see include/dog.h).  The names mirror the C ABI.
+PyTorch is used for device memory and streams when device tensors are passed.
+
+    import paper_2010_08486_amd as dog
+    blobs = dog.detect(img, 1.0, 30.0, 1.6, threshold=0.05, overlap=0.5)
+    ctx = dog.Context()
+    blobs = ctx.detect_device(cuda_tensor, dog.Params(1, 30, 1.6, 0.05, 0.5))
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdog.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "dog.h")
+
+DOG_OK, DOG_EINVAL, DOG_ENOMEM, DOG_EDEVICE, DOG_EBUSY, DOG_EAGAIN, DOG_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
+
+BLOB_DTYPE = np.dtype([("y", np.int32), ("x", np.int32), ("scale", np.int32),
+                       ("sigma", np.float32), ("response", np.float32)])
+
+
+class DogError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (code %d)" % (msg, code))
+        self.code = code
+
+
+class dog_params(ctypes.Structure):
+    _fields_ = [("sigma_min", ctypes.c_double), ("sigma_max", ctypes.c_double),
+                ("sigma_ratio", ctypes.c_double), ("threshold", ctypes.c_double),
+                ("overlap", ctypes.c_double), ("truncate", ctypes.c_double)]
+
+
+class dog_blob(ctypes.Structure):
+    _fields_ = [("y", ctypes.c_int32), ("x", ctypes.c_int32), ("scale", ctypes.c_int32),
+                ("sigma", ctypes.c_float), ("response", ctypes.c_float)]
+
+
+class dog_frame(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("height", ctypes.c_int64), ("width", ctypes.c_int64),
+                ("row_stride", ctypes.c_int64), ("on_device", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class dog_result(ctypes.Structure):
+    _fields_ = [("blobs", ctypes.POINTER(dog_blob)), ("count", ctypes.c_int64),
+                ("raw_count", ctypes.c_int64), ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("t_arrive_ns", ctypes.c_int64),
+                ("t_done_ns", ctypes.c_int64)]
+
+
+@dataclass
+class Params:
+    """Detector hyper-parameters; defaults follow Sec. 4.1 (threshold 0.1,
+    overlap 0.5) and the geometric ladder ratio 1.6 with truncate 4."""
+    sigma_min: float = 1.0
+    sigma_max: float = 30.0
+    sigma_ratio: float = 1.6
+    threshold: float = 0.1
+    overlap: float = 0.5
+    truncate: float = 4.0
+
+    def c(self) -> dog_params:
+        return dog_params(self.sigma_min, self.sigma_max, self.sigma_ratio, self.threshold,
+                          self.overlap, self.truncate)
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libdog.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libdog.so is not built: run `python -m paper_2010_08486_amd.build` "
+                           "(the detector has no non-HIP fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    i32, i64, u64, vp, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_double
+    pblob = ctypes.POINTER(ctypes.POINTER(dog_blob))
+    pi64 = ctypes.POINTER(i64)
+    sig = {
+        "dog_detect": (i32, [vp, i64, i64, i64, dbl, dbl, dbl, dbl, dbl, pblob, pi64]),
+        "dog_blobs_free": (None, [vp]),
+        "dog_last_error": (ctypes.c_char_p, []),
+        "dog_version": (ctypes.c_char_p, []),
+        "dog_context_create": (i32, [ctypes.c_int, u64, ctypes.POINTER(vp)]),
+        "dog_context_destroy": (None, [vp]),
+        "dog_footprint": (i32, [ctypes.POINTER(dog_params), i32, pi64, pi64, ctypes.POINTER(u64)]),
+        "dog_detect_device": (i32, [vp, vp, i64, i64, i64, ctypes.POINTER(dog_params), vp, pblob, pi64]),
+        "dog_detect_batch": (i32, [vp, i32, ctypes.POINTER(dog_frame), ctypes.POINTER(dog_params), vp,
+                                   ctypes.POINTER(dog_result)]),
+        "dog_results_free": (None, [ctypes.POINTER(dog_result), i32]),
+        "dog_debug_planes": (i32, [vp, vp, i64, i64, i64, ctypes.POINTER(dog_params), vp, vp,
+                                   ctypes.POINTER(i32)]),
+        "dog_debug_candidates": (i32, [vp, vp, i64, i64, i64, ctypes.POINTER(dog_params), pblob, pi64]),
+        "dog_plan_info": (i32, [ctypes.POINTER(dog_params), ctypes.POINTER(i32),
+                                ctypes.POINTER(dbl), ctypes.POINTER(i32), i32]),
+        "dog_prune": (i32, [ctypes.POINTER(dog_params), vp, i64, pi64]),
+        "dog_num_variants": (ctypes.c_int, []),
+        "dog_variant_info": (ctypes.c_int, [ctypes.c_int] + [ctypes.POINTER(i32)] * 4),
+        "dog_set_variant": (ctypes.c_int, [vp, ctypes.c_int]),
+        "dog_set_grid": (ctypes.c_int, [vp, i32]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/dog.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(dog_[a-z0-9_]+)\s*\(", txt)))
+
+
+def _check(rc: int) -> None:
+    if rc != DOG_OK:
+        raise DogError(rc, lib().dog_last_error().decode())
+
+
+def _blobs(ptr, n: int) -> np.ndarray:
+    out = np.empty(n, BLOB_DTYPE)
+    if n:
+        ctypes.memmove(out.ctypes.data, ptr, n * BLOB_DTYPE.itemsize)
+    lib().dog_blobs_free(ctypes.cast(ptr, ctypes.c_void_p))
+    return out
+
+
+def version() -> str:
+    return lib().dog_version().decode()
+
+
+def detect(image: np.ndarray, sigma_min: float, sigma_max: float, sigma_ratio: float = 1.6,
+           threshold: float = 0.1, overlap: float = 0.5) -> np.ndarray:
+    """dog_detect on a host fp32 image (2-D, row stride taken from the array)."""
+    a = np.asarray(image)
+    if a.dtype != np.float32 or a.ndim != 2:
+        raise TypeError("image must be a 2-D float32 array")
+    if a.strides[1] != 4 or a.strides[0] % 4:
+        a = np.ascontiguousarray(a)
+    H, W = a.shape
+    p = ctypes.POINTER(dog_blob)()
+    n = ctypes.c_int64(0)
+    _check(lib().dog_detect(a.ctypes.data, H, W, a.strides[0] // 4, sigma_min, sigma_max, sigma_ratio,
+                            threshold, overlap, ctypes.byref(p), ctypes.byref(n)))
+    return _blobs(p, n.value)
+
+
+def num_variants() -> int:
+    return int(lib().dog_num_variants())
+
+
+def variant_info(v: int) -> dict:
+    vals = [ctypes.c_int32() for _ in range(4)]
+    _check(lib().dog_variant_info(v, *[ctypes.byref(x) for x in vals]))
+    return dict(zip(("S", "waves", "strips", "nms_rows"), (x.value for x in vals)))
+
+
+def _tensor_image(t):
+    """(pointer, H, W, row_stride) of a 2-D float32 CUDA tensor."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA tensor")
+    if t.dtype != torch.float32 or t.dim() != 2 or t.stride(1) != 1:
+        raise TypeError("expected a 2-D float32 tensor with unit column stride")
+    return t.data_ptr(), t.shape[0], t.shape[1], t.stride(0)
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """dog_context: device workspace, pinned staging and a stream."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0):
+        self._h = ctypes.c_void_p()
+        _check(lib().dog_context_create(device, budget_bytes, ctypes.byref(self._h)))
+        self.device = device
+
+    def close(self) -> None:
+        if self._h:
+            lib().dog_context_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_variant(self, v: int) -> None:
+        _check(lib().dog_set_variant(self._h, v))
+
+    def set_grid(self, workgroups: int) -> None:
+        _check(lib().dog_set_grid(self._h, workgroups))
+
+    def detect_device(self, image, params: Params, stream=None) -> np.ndarray:
+        ptr, H, W, st = _tensor_image(image)
+        p = ctypes.POINTER(dog_blob)()
+        n = ctypes.c_int64(0)
+        prm = params.c()
+        _check(lib().dog_detect_device(self._h, ptr, H, W, st, ctypes.byref(prm), _stream_ptr(stream),
+                                       ctypes.byref(p), ctypes.byref(n)))
+        return _blobs(p, n.value)
+
+    def debug_candidates(self, image, params: Params) -> np.ndarray:
+        import torch
+        ptr, H, W, st = _tensor_image(image)
+        torch.cuda.synchronize(image.device)
+        p = ctypes.POINTER(dog_blob)()
+        n = ctypes.c_int64(0)
+        prm = params.c()
+        _check(lib().dog_debug_candidates(self._h, ptr, H, W, st, ctypes.byref(prm),
+                                          ctypes.byref(p), ctypes.byref(n)))
+        return _blobs(p, n.value)
+
+    def debug_planes(self, image, params: Params):
+        """(L, D) as CUDA tensors: (k+1, H, W) and (k, H, W) fp32."""
+        import torch
+        ptr, H, W, st = _tensor_image(image)
+        k = plan_info(params)["k"]
+        L = torch.empty((k + 1, H, W), dtype=torch.float32, device=image.device)
+        D = torch.empty((k, H, W), dtype=torch.float32, device=image.device)
+        kk = ctypes.c_int32(0)
+        prm = params.c()
+        torch.cuda.synchronize(image.device)
+        _check(lib().dog_debug_planes(self._h, ptr, H, W, st, ctypes.byref(prm), L.data_ptr(),
+                                      D.data_ptr(), ctypes.byref(kk)))
+        assert kk.value == k
+        return L, D
+
+    def detect_batch(self, frames, params: Params, stream=None):
+        """dog_detect_batch over a list of 2-D float32 numpy arrays (host) or
+        CUDA tensors (device).  Returns (list of blob arrays, list of raw counts)."""
+        n = len(frames)
+        arr = (dog_frame * max(n, 1))()
+        keep = []
+        for i, fr in enumerate(frames):
+            if isinstance(fr, np.ndarray):
+                a = fr
+                if a.dtype != np.float32 or a.ndim != 2:
+                    raise TypeError("frames must be 2-D float32")
+                if a.strides[1] != 4 or a.strides[0] % 4:
+                    a = np.ascontiguousarray(a)
+                keep.append(a)
+                arr[i] = dog_frame(a.ctypes.data, a.shape[0], a.shape[1], a.strides[0] // 4, 0, 0)
+            else:
+                ptr, H, W, st = _tensor_image(fr)
+                arr[i] = dog_frame(ptr, H, W, st, 1, 0)
+        res = (dog_result * max(n, 1))()
+        prm = params.c()
+        s = _stream_ptr(stream) if any(not isinstance(f, np.ndarray) for f in frames) else None
+        rc = lib().dog_detect_batch(self._h, n, arr, ctypes.byref(prm), s, res)
+        out, raw = [], []
+        for i in range(n):
+            if res[i].status != DOG_OK:
+                lib().dog_results_free(res, n)
+                _check(rc if rc != DOG_OK else res[i].status)
+            b = np.empty(res[i].count, BLOB_DTYPE)
+            if res[i].count:
+                ctypes.memmove(b.ctypes.data, res[i].blobs, res[i].count * BLOB_DTYPE.itemsize)
+            out.append(b)
+            raw.append(int(res[i].raw_count))
+        lib().dog_results_free(res, n)
+        _check(rc)
+        return out, raw
+
+
+def prune(params: Params, blobs: np.ndarray) -> np.ndarray:
+    """dog_prune: sort and overlap-prune a blob array (host step)."""
+    b = np.ascontiguousarray(np.array(blobs, dtype=BLOB_DTYPE))
+    n = ctypes.c_int64(0)
+    prm = params.c()
+    _check(lib().dog_prune(ctypes.byref(prm), b.ctypes.data, len(b), ctypes.byref(n)))
+    return b[:n.value].copy()
+
+
+def plan_info(params: Params) -> dict:
+    """The library's ladder for these parameters: k, sigmas (k+1), radii (k+1)."""
+    cap = 64
+    k = ctypes.c_int32(0)
+    sig = (ctypes.c_double * cap)()
+    rad = (ctypes.c_int32 * cap)()
+    prm = params.c()
+    _check(lib().dog_plan_info(ctypes.byref(prm), ctypes.byref(k), sig, rad, cap))
+    n = k.value + 1
+    return {"k": k.value, "sigmas": np.array(sig[:n]), "radii": np.array(rad[:n])}
+
+
+def footprint(params: Params, shapes) -> int:
+    hs = (ctypes.c_int64 * max(len(shapes), 1))(*[s[0] for s in shapes])
+    ws = (ctypes.c_int64 * max(len(shapes), 1))(*[s[1] for s in shapes])
+    out = ctypes.c_uint64(0)
+    prm = params.c()
+    _check(lib().dog_footprint(ctypes.byref(prm), len(shapes), hs, ws, ctypes.byref(out)))
+    return int(out.value)

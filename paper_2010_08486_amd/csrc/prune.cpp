@@ -1,0 +1,99 @@
+// Host post-processing of a frame's candidate list: sort by (y, x, scale)
+// and overlap pruning (Sec. 4.1: blobs whose normalised overlap exceeds a
+// threshold are pruned; blob radius sqrt(2)*sigma, Sec. 3).
+//
+// Pruning rule: blobs are visited in (y, x, scale) order; for each surviving
+// blob a, every later surviving blob b is compared; when the disk
+// intersection exceeds `overlap` times the smaller disk's area, the blob
+// with the smaller sigma is removed (b on a tie) and, if a was removed, a's
+// scan stops.  Pairs whose disks cannot touch (centre distance >= sum of
+// radii) are skipped without evaluation, using the row order to stop each
+// scan early; skipping them does not change the outcome because their
+// overlap is 0 and overlap >= 0.
+#include <algorithm>
+#include <cmath>
+
+#include "runtime.h"
+
+namespace dog {
+
+namespace {
+
+// Area of the intersection of disks of radii a and b whose centres are dist apart.
+double disk_intersection(double dist, double a, double b)
+{
+    if (dist >= a + b)
+        return 0.0;
+    const double small = std::min(a, b);
+    if (dist <= std::fabs(a - b))
+        return M_PI * small * small;
+    const double d2 = dist * dist, a2 = a * a, b2 = b * b;
+    const double ca = std::clamp((d2 + a2 - b2) / (2.0 * dist * a), -1.0, 1.0);
+    const double cb = std::clamp((d2 + b2 - a2) / (2.0 * dist * b), -1.0, 1.0);
+    const double kite = std::max(0.0, (-dist + a + b) * (dist + a - b) * (dist - a + b) * (dist + a + b));
+    return a2 * std::acos(ca) + b2 * std::acos(cb) - 0.5 * std::sqrt(kite);
+}
+
+}  // namespace
+
+double overlap_fraction(int y1, int x1, double s1, int y2, int x2, double s2)
+{
+    const double ra = std::sqrt(2.0) * s1, rb = std::sqrt(2.0) * s2;
+    const double dy = (double)y1 - (double)y2, dx = (double)x1 - (double)x2;
+    const double dist = std::sqrt(dy * dy + dx * dx);
+    const double small = std::min(ra, rb);
+    return disk_intersection(dist, ra, rb) / (M_PI * small * small);
+}
+
+void sort_blobs(std::vector<dog_blob>& v)
+{
+    std::sort(v.begin(), v.end(), [](const dog_blob& a, const dog_blob& b) {
+        if (a.y != b.y)
+            return a.y < b.y;
+        if (a.x != b.x)
+            return a.x < b.x;
+        return a.scale < b.scale;
+    });
+}
+
+// sigma64[i] is the FP64 sigma of ladder index i (the fp32 copy in dog_blob
+// is for output only).
+void prune_blobs(std::vector<dog_blob>& v, const std::vector<double>& sigma64, double overlap)
+{
+    const size_t n = v.size();
+    if (overlap >= 1.0 || n < 2)
+        return;
+    double smax = 0.0;
+    for (const dog_blob& b : v)
+        smax = std::max(smax, sigma64[b.scale]);
+    const double rmax = std::sqrt(2.0) * smax;
+    std::vector<char> alive(n, 1);
+    for (size_t a = 0; a < n; ++a) {
+        if (!alive[a])
+            continue;
+        const double sa = sigma64[v[a].scale];
+        const double reach = std::sqrt(2.0) * sa + rmax;  // no later blob beyond this row distance can touch a
+        for (size_t b = a + 1; b < n; ++b) {
+            if ((double)(v[b].y - v[a].y) >= reach)
+                break;
+            if (!alive[b])
+                continue;
+            const double sb = sigma64[v[b].scale];
+            const double f = overlap_fraction(v[a].y, v[a].x, sa, v[b].y, v[b].x, sb);
+            if (f > overlap) {
+                if (sa < sb) {
+                    alive[a] = 0;
+                    break;
+                }
+                alive[b] = 0;
+            }
+        }
+    }
+    size_t o = 0;
+    for (size_t i = 0; i < n; ++i)
+        if (alive[i])
+            v[o++] = v[i];
+    v.resize(o);
+}
+
+}  // namespace dog

@@ -1,0 +1,129 @@
+// Host runtime of the detector: plans, device workspace, launch sequences.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "dog.h"
+#include "dog_internal.h"
+
+namespace dog {
+
+// ---------------------------------------------------------------- plan
+struct Plan {
+    dog_params prm;
+    int k = 0;      // DoG planes
+    int n_g = 0;    // Gaussian planes (k+1)
+    std::vector<double> sigma;
+    std::vector<int> r;
+    std::vector<float> weights;  // per-plane vectors, zero-padded
+    LadderDesc desc;
+};
+
+bool validate_params(const dog_params& p, std::string* err);
+int build_plan(const dog_params& p, Plan* plan, std::string* err);
+bool same_params(const dog_params& a, const dog_params& b);
+int dog_planes_for(double smin, double smax, double ratio);
+
+// ---------------------------------------------------------------- prune
+double overlap_fraction(int y1, int x1, double s1, int y2, int x2, double s2);
+void sort_blobs(std::vector<dog_blob>& v);
+void prune_blobs(std::vector<dog_blob>& v, const std::vector<double>& sigma64, double overlap);
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define DOG_HIP(call)                                  \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess)                          \
+            return ::dog::hip_fail(e_, #call);         \
+    } while (0)
+
+// ---------------------------------------------------------------- memory
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct PinBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+// A frame ready for a launch: device pixels.
+struct FrameIn {
+    const float* d;
+    int H, W;
+    long long stride;
+};
+
+// Geometry of one tiling variant.
+struct Variant {
+    int S, NW, BI, BN, NWN;
+    int band() const { return S * NW * BI; }
+    int nms_band() const { return BN * NWN; }
+};
+
+}  // namespace dog
+
+// Kernel launchers (kernels.hip).
+extern "C" {
+int dogk_num_variants();
+void dogk_variant_geometry(int v, int* S, int* NW, int* BI, int* BN, int* NWN);
+hipError_t dogk_launch_sequence(int variant, const dog::LaunchArgs* args, int grid1, int grid2,
+                                int grid3, hipStream_t stream);
+hipError_t dogk_launch_nms(int variant, const dog::LaunchArgs* args, int grid3, hipStream_t stream);
+hipError_t dogk_untranspose(const float* src, float* dst, int n_planes, int H, int W,
+                            long long pitch, hipStream_t stream);
+hipError_t dogk_fill_u32(uint32_t* p, int n, uint32_t v, hipStream_t stream);
+hipError_t dogk_occupancy(int variant, int* wg1, int* wg2, int* wg3);
+}
+
+struct dog_context {
+    int device = 0;
+    uint64_t budget = 0;
+    uint64_t used = 0;             // bytes allocated on the device
+    hipStream_t stream = nullptr;
+    int n_cu = 0;
+    int variant = 0;               // active kernel variant
+    int variant_auto = 0;          // autotuned choice
+    int grid_override = 0;
+    int occ[3] = {0, 0, 0};        // workgroups per CU of each kernel (active variant)
+
+    dog::DevBuf planes;            // T, L (and debug D) planes of all frames
+    dog::DevBuf input;             // device copies of host frames
+    dog::DevBuf tables;            // frames, ladder, weights, units
+    dog::DevBuf cand;              // CandHeader + records
+    dog::DevBuf counters;          // dog::Counters
+    uint32_t cap = 0;              // record capacity of `cand`
+
+    dog::PinBuf h_tables;          // staging of the launch tables
+    dog::PinBuf h_cand;            // readback of header + records
+    dog::PinBuf h_input;           // staging of host frames
+
+    bool have_plan = false;
+    dog::Plan plan;
+    uint32_t last_count = 0;       // candidates found by the previous launch (readback guess)
+};
+
+namespace dog {
+
+int ctx_alloc(dog_context* c, DevBuf* b, size_t bytes, const char* what);
+int ctx_pin(PinBuf* b, size_t bytes);
+int ctx_plan(dog_context* c, const dog_params* prm, const Plan** out);
+int ctx_set_variant(dog_context* c, int v);
+
+// Run the three kernels over `frames` (device pixels) with plan P and read
+// back the candidate records, grouped per frame and sorted by (y, x, scale).
+// If dbg_D is true the first frame's DoG planes are also written to the
+// workspace (debug layout).
+int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames,
+               hipStream_t s, std::vector<std::vector<dog_blob>>* out, bool dbg_D,
+               long long* pitch0, float** L0, float** D0);
+
+}  // namespace dog

@@ -1,0 +1,192 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Planes within 1e-5 relative (scaled, see parity.py); blob lists identical
+except voxels within the fp32/FP64 decision margin of a tie or of the
+threshold; pruned lists equal.  Also edge shapes (1x1, thin, ragged tiles,
+radius larger than the image, row stride > width), candidate overflow,
+determinism, kernel-variant invariance and batch == single frame.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import check_candidates, check_planes, check_pruned
+
+pytestmark = pytest.mark.gpu
+
+SMALL = dict(sigma_min=1.0, sigma_max=8.0, sigma_ratio=1.6, threshold=0.1, overlap=0.5)
+CAMERA = dict(sigma_min=1.0, sigma_max=30.0, sigma_ratio=1.6, threshold=0.05, overlap=0.5)
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    assert torch.cuda.is_available(), "gpu tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def dog():
+    import paper_2010_08486_amd as d
+    return d
+
+
+@pytest.fixture(scope="module")
+def ctx(dog, torch_mod):
+    c = dog.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(torch, img):
+    return torch.from_numpy(np.ascontiguousarray(img)).cuda()
+
+
+def _full_parity(dog, ctx, torch, img, prm_kw, check_plane=True):
+    prm = dog.Params(**prm_kw)
+    t = _dev(torch, img)
+    L_o, D_o, sig = oracle.planes(img, prm.sigma_min, prm.sigma_max, prm.sigma_ratio, 4.0)
+    max_abs = float(np.abs(img).max())
+    if check_plane:
+        L_g, D_g = ctx.debug_planes(t, prm)
+        torch.cuda.synchronize()
+        check_planes(L_g.cpu().numpy(), D_g.cpu().numpy(), L_o, D_o, sig, max_abs)
+    raw = ctx.debug_candidates(t, prm)
+    exempt = check_candidates(raw, D_o, prm.threshold, sig, max_abs)
+    pruned = ctx.detect_device(t, prm)
+    check_pruned(pruned, raw, D_o, prm.threshold, sig, prm.overlap, exempt)
+    return raw, pruned, exempt
+
+
+def test_small_frame_parity(dog, ctx, torch_mod):
+    img = synth.small_frame(seed=0)
+    raw, pruned, exempt = _full_parity(dog, ctx, torch_mod, img, SMALL)
+    print("small: raw %d pruned %d exempt %d" % (len(raw), len(pruned), exempt))
+    assert len(pruned) >= 10
+
+
+def test_camera_frame_parity_full_size(dog, ctx, torch_mod):
+    img = synth.camera_frame(seed=1)
+    raw, pruned, exempt = _full_parity(dog, ctx, torch_mod, img, CAMERA)
+    print("camera 1024^2: raw %d pruned %d exempt %d" % (len(raw), len(pruned), exempt))
+    assert len(pruned) >= 100
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 9), (3, 1), (7, 5), (2, 130), (97, 131), (64, 64),
+                                   (65, 63), (130, 257), (33, 300)])
+def test_edge_shapes_parity(dog, ctx, torch_mod, shape):
+    H, W = shape
+    img = synth.small_frame(seed=H * 1000 + W, H=H, W=W, n_blobs=max(1, H * W // 800))
+    _full_parity(dog, ctx, torch_mod, img, SMALL)
+
+
+def test_radius_larger_than_image(dog, ctx, torch_mod):
+    # sigma up to ~43 (radius 172) on a 20 x 300 crop: rows reflect many times
+    img = synth.camera_frame(seed=5, H=20, W=300, n_blobs=3)
+    _full_parity(dog, ctx, torch_mod, img, CAMERA)
+
+
+def test_row_stride_greater_than_width(dog, ctx, torch_mod):
+    torch = torch_mod
+    img = synth.small_frame(seed=12, H=90, W=70, n_blobs=6)
+    wide = np.zeros((90, 101), np.float32)
+    wide[:, :70] = img
+    wide[:, 70:] = 7.0          # must never be read
+    t = _dev(torch, wide)[:, :70]
+    assert t.stride(0) == 101
+    prm = dog.Params(**SMALL)
+    got = ctx.detect_device(t, prm)
+    ref = ctx.detect_device(_dev(torch, img), prm)
+    assert got.tobytes() == ref.tobytes()
+    L_o, D_o, sig = oracle.planes(img, 1, 8, 1.6)
+    L_g, D_g = ctx.debug_planes(t, prm)
+    check_planes(L_g.cpu().numpy(), D_g.cpu().numpy(), L_o, D_o, sig, float(img.max()))
+
+
+def test_candidate_overflow_all_ties(dog, ctx, torch_mod):
+    # a zero image has D == 0 everywhere: with a negative threshold every
+    # voxel ties with its neighbourhood, far beyond the initial capacity
+    torch = torch_mod
+    img = np.zeros((256, 256), np.float32)
+    prm = dog.Params(1, 8, 1.6, -1.0, 1.0)
+    raw = ctx.debug_candidates(_dev(torch, img), prm)
+    assert len(raw) == 256 * 256 * 5
+    exp = np.array([(y, x, i) for y in range(256) for x in range(256) for i in range(5)])
+    got = np.stack([raw["y"], raw["x"], raw["scale"]], 1)
+    assert np.array_equal(got, exp)
+    assert np.all(raw["response"] == 0)
+    # and a normal frame right after still matches
+    test_small_frame_parity(dog, ctx, torch)
+
+
+def test_repeat_runs_bitwise_identical(dog, ctx, torch_mod):
+    img = synth.camera_frame(seed=3, H=512, W=384, n_blobs=120)
+    t = _dev(torch_mod, img)
+    prm = dog.Params(**CAMERA)
+    a = ctx.debug_candidates(t, prm)
+    b = ctx.debug_candidates(t, prm)
+    assert a.tobytes() == b.tobytes()
+    La, Da = ctx.debug_planes(t, prm)
+    Lb, Db = ctx.debug_planes(t, prm)
+    assert torch_mod.equal(La, Lb) and torch_mod.equal(Da, Db)
+
+
+def test_all_variants_bitwise_identical(dog, ctx, torch_mod):
+    img = synth.camera_frame(seed=4, H=200, W=300, n_blobs=40)
+    t = _dev(torch_mod, img)
+    prm = dog.Params(**CAMERA)
+    ctx.set_variant(0)
+    L0, D0 = ctx.debug_planes(t, prm)
+    c0 = ctx.debug_candidates(t, prm)
+    try:
+        for v in range(1, dog.num_variants()):
+            ctx.set_variant(v)
+            L, D = ctx.debug_planes(t, prm)
+            c = ctx.debug_candidates(t, prm)
+            assert torch_mod.equal(L, L0) and torch_mod.equal(D, D0), dog.variant_info(v)
+            assert c.tobytes() == c0.tobytes(), dog.variant_info(v)
+    finally:
+        ctx.set_variant(-1)
+
+
+def test_grid_size_does_not_change_results(dog, ctx, torch_mod):
+    img = synth.camera_frame(seed=8, H=300, W=260, n_blobs=50)
+    t = _dev(torch_mod, img)
+    prm = dog.Params(**CAMERA)
+    ref = ctx.debug_candidates(t, prm)
+    try:
+        for g in (1, 3, 17):
+            ctx.set_grid(g)
+            assert ctx.debug_candidates(t, prm).tobytes() == ref.tobytes()
+    finally:
+        ctx.set_grid(0)
+
+
+def test_batch_equals_single_frames(dog, ctx, torch_mod):
+    shapes = [(256, 256), (128, 512), (300, 200), (64, 64), (512, 256)]
+    frames = [synth.camera_frame(seed=50 + i, H=h, W=w, n_blobs=h * w // 2000 + 1)
+              for i, (h, w) in enumerate(shapes)]
+    prm = dog.Params(**CAMERA)
+    singles = [ctx.detect_device(_dev(torch_mod, f), prm) for f in frames]
+    host_batch, raw_counts = ctx.detect_batch(frames, prm)
+    dev_batch, _ = ctx.detect_batch([_dev(torch_mod, f) for f in frames], prm)
+    for s, hb, db in zip(singles, host_batch, dev_batch):
+        assert s.tobytes() == hb.tobytes() == db.tobytes()
+    assert all(r >= len(s) for r, s in zip(raw_counts, singles))
+
+
+def test_host_entry_point_matches_device(dog, ctx, torch_mod):
+    img = synth.small_frame(seed=21)
+    got = dog.detect(img, 1.0, 8.0, 1.6, 0.1, 0.5)
+    ref = ctx.detect_device(_dev(torch_mod, img), dog.Params(**SMALL))
+    assert got.tobytes() == ref.tobytes()
+
+
+def test_invalid_device_arguments(dog, ctx, torch_mod):
+    t = _dev(torch_mod, np.zeros((8, 8), np.float32))
+    with pytest.raises(dog.DogError) as e:
+        ctx.detect_device(t, dog.Params(sigma_min=0.0))
+    assert e.value.code == dog.DOG_EINVAL
+    with pytest.raises(dog.DogError):
+        dog.detect(np.zeros((0, 5), np.float32), 1, 8)

@@ -1,0 +1,86 @@
+"""CPU tests of the library boundary: it loads, exports every symbol the
+header declares, validates arguments, and its host steps (ladder plan,
+pruning) agree with the oracle.  No kernel is launched."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2010_08486_amd as dog
+
+
+def test_library_exports_every_header_symbol():
+    L = dog.lib()
+    names = dog.header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+        assert ctypes.cast(getattr(L, n), ctypes.c_void_p).value
+
+
+@pytest.mark.parametrize("p", [(1, 8, 1.6), (1, 30, 1.6), (2.0, 2.0, 1.6), (0.7, 13.0, 1.25),
+                               (1.0, 1.6 ** 4 * 0.999, 1.6)])
+def test_plan_matches_oracle_ladder(p):
+    info = dog.plan_info(dog.Params(p[0], p[1], p[2], 0.1, 0.5, 4.0))
+    s = oracle.sigmas_geometric(*p)
+    assert info["k"] == oracle.num_dog_planes(*p) == len(s) - 1
+    assert np.array_equal(info["sigmas"], s)
+    assert info["radii"].tolist() == [oracle.radius(x, 4.0) for x in s]
+
+
+@pytest.mark.parametrize("bad", [dict(sigma_min=0.0), dict(sigma_min=-1.0), dict(sigma_max=0.5),
+                                 dict(sigma_ratio=1.0), dict(sigma_ratio=0.9),
+                                 dict(threshold=float("nan")), dict(overlap=1.5),
+                                 dict(overlap=-0.1), dict(truncate=-1.0),
+                                 dict(sigma_min=1.0, sigma_max=1e9, sigma_ratio=1.01)])
+def test_invalid_params_rejected(bad):
+    kw = dict(sigma_min=1.0, sigma_max=8.0, sigma_ratio=1.6, threshold=0.1, overlap=0.5, truncate=4.0)
+    kw.update(bad)
+    with pytest.raises(dog.DogError) as e:
+        dog.plan_info(dog.Params(**kw))
+    assert e.value.code == dog.DOG_EINVAL
+
+
+@pytest.mark.parametrize("seed,overlap", [(0, 0.5), (1, 0.5), (2, 0.0), (3, 0.9), (4, 1.0)])
+def test_prune_matches_oracle(seed, overlap):
+    rng = np.random.default_rng(seed)
+    n = 400
+    prm = dog.Params(1, 30, 1.6, 0.05, overlap)
+    sig = dog.plan_info(prm)["sigmas"]
+    b = np.zeros(n, dog.BLOB_DTYPE)
+    b["y"] = rng.integers(0, 120, n)
+    b["x"] = rng.integers(0, 120, n)
+    b["scale"] = rng.integers(0, 8, n)
+    # unique voxels, as the detector produces
+    _, u = np.unique(b[["y", "x", "scale"]], return_index=True)
+    b = b[np.sort(u)]
+    rng.shuffle(b)
+    got = dog.prune(prm, b)
+    order = np.lexsort((b["scale"], b["x"], b["y"]))
+    s = b[order]
+    keep = oracle.prune(s["y"], s["x"], sig[s["scale"]], overlap)
+    exp = s[keep]
+    assert got[["y", "x", "scale"]].tolist() == exp[["y", "x", "scale"]].tolist()
+    assert np.all(got["sigma"] == sig[got["scale"]].astype(np.float32))
+
+
+def test_footprint_grows_with_frames():
+    prm = dog.Params(1, 30, 1.6, 0.05, 0.5)
+    one = dog.footprint(prm, [(1024, 1024)])
+    two = dog.footprint(prm, [(1024, 1024), (512, 2048)])
+    assert one >= 2 * 9 * 1024 * 1024 * 4
+    assert two > one
+
+
+def test_no_gpu_context_fails_cleanly():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("GPU present")
+    except ImportError:
+        pass
+    with pytest.raises(dog.DogError) as e:
+        dog.Context()
+    assert e.value.code in (dog.DOG_EDEVICE, dog.DOG_EINVAL)
+    assert dog.lib().dog_last_error()
