@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X Difference-of-Gaussians blob detector.
+
+Headline: Mpixel-scales/s of the whole detector path (blur stack, DoG,
+3x3x3 local maxima with threshold, compaction, readback, host sort and
+pruning) on one 1024x1024 fp32 camera frame (500 blobs, sigma 1..30, ratio
+1.6 -> 8 DoG planes, threshold 0.05, overlap 0.5) already resident in HBM.
+Mpixel-scales = H * W * k per frame.
+
+Also printed in the same JSON line:
+  * roofline of the dominant kernel, from HIP events recorded around each
+    kernel on its own stream during the timed steps;
+  * per-frame latency p50/p99 of the timed steps;
+  * the same 64-frame uniform batch through the batched entry point vs one
+    frame at a time (throughput ratio and latency);
+  * the FP64 CPU oracle timed on this host on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-batch] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X figures used for the roofline (see the design notes for the derivation)
+N_CU = 256
+CLOCK_HZ = 2.4e9
+FP32_FMA_PER_CU_CLK = 64          # 4 SIMD x 16 lanes, one v_fma_f32 each per clock
+PEAK_FP32_TFLOPS = N_CU * CLOCK_HZ * FP32_FMA_PER_CU_CLK * 2 / 1e12   # 78.6: unpacked FP32
+PEAK_FP32_PACKED_TFLOPS = 157.3   # needs v_pk_fma_f32, which this build does not emit
+PEAK_HBM_GBS = 8000.0
+
+PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "pass2_frame1k_counters.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2010_08486_amd", "csrc", "kernels.hip")
+
+
+def pct(a, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(a), q))
+
+
+def kernel_source_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source (else None)."""
+    if not os.path.exists(PROFILE_COUNTERS):
+        return None
+    vals = {}
+    for line in open(PROFILE_COUNTERS):
+        line = line.strip()
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    key = "%s_hbm_bytes_per_launch" % kernel
+    return float(vals[key]) if key in vals else None
+
+
+def cpu_baseline(img, prm, k, budget_s=12.0):
+    import oracle
+    oracle.build()
+    n_threads = oracle.get_threads()
+    reps, t_total = 0, 0.0
+    while t_total < budget_s and reps < 50:
+        t0 = time.perf_counter()
+        oracle.detect_c(img, prm.sigma_min, prm.sigma_max, prm.sigma_ratio, prm.threshold,
+                        prm.overlap, 4.0)
+        t_total += time.perf_counter() - t0
+        reps += 1
+    H, W = img.shape
+    return {"value": round(H * W * k * reps / t_total / 1e6, 3), "unit": "Mpixel-scales/s",
+            "cores": n_threads, "kind": "oracle",
+            "sample": "%d full run(s) of the FP64 C oracle (OpenMP over rows) on the same "
+                      "1024x1024 frame, %.1f s total" % (reps, t_total)}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--variant", type=int, default=-1)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the detector's frames are independent and this "
+              "build runs on a single MI355X (multi-GPU sharding is described in the design "
+              "notes, not run). Use --gpus 1.", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2010_08486_amd as dog
+    import synth
+
+    dev = torch.device("cuda:0")
+    prm = dog.Params(1.0, 30.0, 1.6, 0.05, 0.5)
+    info = dog.plan_info(prm)
+    k = info["k"]
+    radii = info["radii"]
+    img = synth.camera_frame(seed=1)
+    H, W = img.shape
+    t_img = torch.from_numpy(img).to(dev)
+    ctx = dog.Context(0)
+    if args.variant >= 0:
+        ctx.set_variant(args.variant)
+
+    for _ in range(args.warmup):
+        ctx.detect_device(t_img, prm)
+    torch.cuda.synchronize()
+
+    # ---- timed region: K whole-path steps, kernel events on the library stream
+    ctx.set_profiling(True)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        blobs = ctx.detect_device(t_img, prm)
+        lat.append(time.perf_counter() - s0)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kms, nseq = ctx.kernel_times()
+    ctx.set_profiling(False)
+
+    mpx = H * W * k / 1e6
+    value = mpx * args.steps / dt
+    names = ["pass1", "pass2", "nms"]
+    avg_ms = [m / max(nseq, 1) for m in kms]
+    taps = int(np.sum(2 * radii + 1))
+    flops = {"pass1": 2.0 * taps * H * W, "pass2": 2.0 * taps * H * W,
+             "nms": 0.0}
+    dom = int(np.argmax(avg_ms[:2]))
+    dname = names[dom]
+    achieved = flops[dname] / (avg_ms[dom] * 1e-3) / 1e12
+    traffic = measured_traffic(dname)
+    roofline = {"bound": "alu", "kernel": dname, "achieved": round(achieved, 3),
+                "peak": round(PEAK_FP32_TFLOPS, 1), "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
+                "peak_packed_fp32": PEAK_FP32_PACKED_TFLOPS,
+                "frac_of_packed_peak": round(achieved / PEAK_FP32_PACKED_TFLOPS, 4),
+                "kernel_avg_us": {n: round(m * 1e3, 2) for n, m in zip(names, avg_ms)},
+                "algorithmic_flop_per_launch": flops[dname]}
+    kernel_sum_ms = sum(avg_ms)
+
+    out = {"metric": "Mpixel-scales/s for DoG+NMS on 1 GPU; p99 frame latency, batched vs per-frame",
+           "value": round(value, 1), "unit": "Mpixel-scales/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(dt / args.steps * 1e3, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "frame1k: one 1024x1024 fp32 camera frame (Poisson counts, "
+                                  "500 blobs), sigma 1..30 ratio 1.6 (8 DoG planes), threshold "
+                                  "0.05, overlap 0.5", "frames_per_step": 1, "height": H,
+                      "width": W, "dog_planes": k, "parallelism": "single GPU"},
+           "roofline": roofline,
+           "latency_ms": {"p50": round(pct(lat, 50) * 1e3, 4), "p99": round(pct(lat, 99) * 1e3, 4)},
+           "kernel_ms_per_frame": round(kernel_sum_ms, 4),
+           "kernel_only_mpx_scales_per_s": round(mpx / (kernel_sum_ms * 1e-3), 1),
+           "blobs": int(len(blobs))}
+
+    # ---- uniform batch of 64 frames: batched entry point vs frame by frame
+    if not args.no_batch:
+        frames = synth.batch64()
+        dfr = [torch.from_numpy(f).to(dev) for f in frames]
+        torch.cuda.synchronize()
+        ctx.detect_batch(dfr, prm)
+        for f in dfr[:4]:
+            ctx.detect_device(f, prm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.batch_steps):
+            res, _ = ctx.detect_batch(dfr, prm)
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - t0) / args.batch_steps
+        t0 = time.perf_counter()
+        per = []
+        for f in dfr:
+            s0 = time.perf_counter()
+            ctx.detect_device(f, prm)
+            per.append(time.perf_counter() - s0)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        tot = sum(f.shape[0] * f.shape[1] for f in frames) * k / 1e6
+        out["batch64"] = {"batched_mpx_scales_per_s": round(tot / tb, 1),
+                          "per_frame_mpx_scales_per_s": round(tot / tp, 1),
+                          "batched_over_per_frame": round(tp / tb, 3),
+                          "batched_ms_per_batch": round(tb * 1e3, 3),
+                          "per_frame_p50_ms": round(pct(per, 50) * 1e3, 4),
+                          "per_frame_p99_ms": round(pct(per, 99) * 1e3, 4),
+                          "batched_frame_latency_ms": round(tb * 1e3, 3)}
+        del dfr
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(img, prm, k)
+    ctx.close()
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

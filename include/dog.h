@@ -187,6 +187,15 @@ int dog_num_variants(void);
 int dog_variant_info(int variant, int32_t* S, int32_t* waves, int32_t* strips, int32_t* nms_rows);
 int dog_set_variant(dog_context* ctx, int variant);
 
+/* Per-kernel timing: when on, every launch sequence of the context records
+ * HIP events around each of its three kernels (pass 1, pass 2, local
+ * maxima) on the stream they run on; dog_kernel_times returns the summed
+ * milliseconds of each kernel (ms_out[3]) and the number of sequences since
+ * profiling was last switched on.  Timing adds three event records per
+ * sequence and is off by default. */
+int dog_set_profiling(dog_context* ctx, int32_t on);
+int dog_kernel_times(dog_context* ctx, double* ms_out, int64_t* launches_out);
+
 /* Persistent-grid size (workgroups per kernel); 0 = automatic. */
 int dog_set_grid(dog_context* ctx, int32_t workgroups);
 

@@ -111,6 +111,8 @@ def lib() -> ctypes.CDLL:
         "dog_variant_info": (ctypes.c_int, [ctypes.c_int] + [ctypes.POINTER(i32)] * 4),
         "dog_set_variant": (ctypes.c_int, [vp, ctypes.c_int]),
         "dog_set_grid": (ctypes.c_int, [vp, i32]),
+        "dog_set_profiling": (ctypes.c_int, [vp, i32]),
+        "dog_kernel_times": (ctypes.c_int, [vp, ctypes.POINTER(dbl), pi64]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -220,6 +222,16 @@ class Context:
 
     def set_grid(self, workgroups: int) -> None:
         _check(lib().dog_set_grid(self._h, workgroups))
+
+    def set_profiling(self, on: bool) -> None:
+        _check(lib().dog_set_profiling(self._h, 1 if on else 0))
+
+    def kernel_times(self):
+        """(ms per kernel summed [pass1, pass2, nms], number of launch sequences)."""
+        ms = (ctypes.c_double * 3)()
+        n = ctypes.c_int64(0)
+        _check(lib().dog_kernel_times(self._h, ms, ctypes.byref(n)))
+        return list(ms), n.value
 
     def detect_device(self, image, params: Params, stream=None) -> np.ndarray:
         ptr, H, W, st = _tensor_image(image)

@@ -83,6 +83,9 @@ void free_context(dog_context* c)
     for (PinBuf* b : {&c->h_tables, &c->h_cand, &c->h_input})
         if (b->p)
             (void)hipHostFree(b->p);
+    for (hipEvent_t& e : c->ev)
+        if (e)
+            (void)hipEventDestroy(e);
     if (c->stream)
         (void)hipStreamDestroy(c->stream);
     delete c;
@@ -186,6 +189,32 @@ int dog_set_variant(dog_context* ctx, int variant)
     if (rc != DOG_OK)
         return rc;
     return ctx_set_variant(ctx, variant);
+}
+
+int dog_set_profiling(dog_context* ctx, int32_t on)
+{
+    if (!ctx) {
+        set_error("ctx is NULL");
+        return DOG_EINVAL;
+    }
+    ctx->profiling = on != 0;
+    for (double& m : ctx->kernel_ms)
+        m = 0.0;
+    ctx->kernel_launches = 0;
+    return DOG_OK;
+}
+
+int dog_kernel_times(dog_context* ctx, double* ms_out, int64_t* launches_out)
+{
+    if (!ctx || !ms_out) {
+        set_error("invalid argument");
+        return DOG_EINVAL;
+    }
+    for (int i = 0; i < 3; ++i)
+        ms_out[i] = ctx->kernel_ms[i];
+    if (launches_out)
+        *launches_out = ctx->kernel_launches;
+    return DOG_OK;
 }
 
 int dog_set_grid(dog_context* ctx, int32_t workgroups)

@@ -47,15 +47,30 @@ struct LadderDesc {
     float sigma[DOG_MAX_GAUSS];   // sigma_p rounded to fp32 (DoG scale factor)
 };
 
-// A unit of blur work: one (frame, plane), tiled into column blocks x row bands.
-// For the local-maximum kernel the plane field is unused (one unit per frame).
+// A unit of work of one kernel: one (frame, plane) for the blur passes or one
+// frame for the local-maximum kernel, restricted to the column blocks
+// [cb0, cb0 + n_cb) and tiled into n_cb x n_band tiles.
 struct WorkUnit {
     int frame;
     int plane;
-    int n_cb;          // column blocks
+    int cb0;           // first column block of this slice
+    int n_cb;          // column blocks in this slice
     int n_band;        // row bands
-    int first_tile;    // prefix sum of tiles over the preceding units
-    int pad_[3];
+    int first_tile;    // prefix sum of tiles over the preceding units of the same list
+    int pad_[2];
+};
+
+#define DOG_NXCD 8     // accelerator complex dies (each with its own L2)
+
+// One kernel's work split into DOG_NXCD lists, one per XCD: list c holds the
+// column slices meant to stay in XCD c's L2 and is drained first by the
+// workgroups dispatched to XCD c (workgroup id mod 8); idle workgroups then
+// steal from the other lists.
+struct Queue {
+    const WorkUnit* units;     // all lists back to back
+    int off[DOG_NXCD];         // first unit of list c
+    int n[DOG_NXCD];           // units in list c
+    int total[DOG_NXCD];       // tiles in list c
 };
 
 // Candidate record written by the local-maximum kernel.
@@ -73,13 +88,12 @@ struct CandHeader {
     uint32_t pad_[3];
 };
 
-// Work counters of the three persistent kernels.  Each kernel clears the
-// counter of the kernel two steps ahead in the launch sequence; see kernels.hip.
+// Tile counters of the three persistent kernels, one per XCD list.  Block 0
+// of each kernel clears the counters of the kernel two steps ahead in the
+// launch sequence (pass 1 -> local maxima, pass 2 -> pass 1, local maxima ->
+// pass 2), which are never in use at that time.
 struct Counters {
-    uint32_t pass1;
-    uint32_t pass2;
-    uint32_t nms;
-    uint32_t pad_;
+    uint32_t c[3][DOG_NXCD];
 };
 
 // Arguments of one launch sequence (all pointers are device pointers).
@@ -87,23 +101,12 @@ struct LaunchArgs {
     const FrameDesc* frames;
     const LadderDesc* ladders;
     const float* weights;
-    const WorkUnit* units1;     // pass 1 units
-    const WorkUnit* units2;     // pass 2 units
-    const WorkUnit* units3;     // local-maximum units (one per frame)
+    const Queue* queues;        // [3]: pass 1, pass 2, local maxima
     Counters* counters;
     CandHeader* cand;           // header; records at (CandRec*)(cand + 1)
-    int n_units1, n_units2, n_units3;
-    int total1, total2, total3; // tiles of each kernel
     uint32_t cap;               // record capacity
     int pad_;
 };
 
-// Kernel tile geometry (compile-time variants, chosen per size class).
-struct Geometry {
-    int S;           // outputs per thread along the walking direction
-    int NW;          // waves per workgroup
-    int BI;          // strips per wave per tile
-    int band() const { return S * NW * BI; }
-};
 
 }  // namespace dog

@@ -16,16 +16,15 @@
 // on the FP32 vector ALUs: each lane owns one column and S consecutive outputs
 // along the walking direction, streams its input column once per tap chunk,
 // and takes the (wave-uniform) weights from scalar registers, so each loaded
-// value feeds S fused multiply-adds.  Reflection at the borders only ever
-// applies to the walking direction, where the row index is uniform, so the
-// interior path has no per-lane boundary logic at all.
+// value feeds S fused multiply-adds.  A ring of R row buffers keeps R-1 chunks
+// of loads in flight ahead of the multiply-adds.  Reflection at the borders
+// only ever applies to the walking direction, where the row index is uniform,
+// so the interior path has no per-lane boundary logic at all.
 //
 // All three kernels are persistent: a fixed grid of workgroups pulls tiles
-// from an atomic counter, so one captured launch sequence serves batches of
-// any composition.  Each kernel clears the counter of the kernel two steps
-// ahead in the sequence (pass 1 clears the nms counter and the candidate
-// count, pass 2 clears pass 1's, nms clears pass 2's); a kernel never touches
-// its own counter while it runs.
+// from per-XCD atomic counters (home list first, then the other XCDs' lists),
+// so one captured launch sequence serves batches of any composition and each
+// XCD's L2 mostly sees its own column slices.
 #include <hip/hip_runtime.h>
 
 #include "dog_internal.h"
@@ -61,10 +60,11 @@ __device__ __forceinline__ const DOG_CONSTANT_AS T* cst(const T* p)
     return (const DOG_CONSTANT_AS T*)p;
 }
 
+typedef const DOG_CONSTANT_AS float* cptr_t;
+
 // Last unit whose first_tile <= tile (units sorted by first_tile).
-__device__ __forceinline__ int find_unit(const WorkUnit* units, int n, int tile)
+__device__ __forceinline__ int find_unit(const DOG_CONSTANT_AS WorkUnit* u, int n, int tile)
 {
-    const DOG_CONSTANT_AS WorkUnit* u = cst(units);
     int lo = 0, hi = n - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -76,10 +76,6 @@ __device__ __forceinline__ int find_unit(const WorkUnit* units, int n, int tile)
     return lo;
 }
 
-// Scalar (SMEM) view of the wave-uniform weight vectors.
-typedef const DOG_CONSTANT_AS float* cptr_t;
-
-
 // Buffer resource over one plane: raw (unswizzled) dword loads with a scalar
 // row offset and a per-lane column offset; the hardware range check returns 0
 // for any byte offset at or beyond `bytes` instead of touching memory.
@@ -87,6 +83,11 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float* base, 
 {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, (int)bytes,
                                              0x00020000);
+}
+
+__device__ __forceinline__ float load_f32(__amdgpu_buffer_rsrc_t rs, unsigned voff, int soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff, soff, 0));
 }
 
 // v[m] = column c of row (row0 + m), m = 0..S-1.  Interior rows: vo[m] =
@@ -99,13 +100,10 @@ __device__ __forceinline__ void load_rows(float (&v)[S], __amdgpu_buffer_rsrc_t 
 {
 #pragma unroll
     for (int m = 0; m < S; ++m) {
-        unsigned bits;
         if (INTERIOR)
-            bits = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)vo[m], row0 * stride4, 0);
+            v[m] = load_f32(rs, vo[m], row0 * stride4);
         else
-            bits = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)vo[0], refl(row0 + m, n) * stride4,
-                                                        0);
-        v[m] = __builtin_bit_cast(float, bits);
+            v[m] = load_f32(rs, vo[0], refl(row0 + m, n) * stride4);
     }
 }
 
@@ -124,44 +122,48 @@ __device__ __forceinline__ void fma_chunk(float (&acc)[S], const float (&lo)[S],
     }
 }
 
-// nch chunks of S taps over rows base .. base + (nch+1)*S - 1; three row
-// buffers rotate so the loads of chunk ch+2 are in flight while chunk ch is
-// multiplied.  Reads rows up to base + (nch+2)*S - 1.
-template <int S, bool INTERIOR>
+// nch chunks of S taps.  Chunk ch multiplies row chunks X_ch and X_{ch+1}
+// (X_j = rows base + j*S .. base + j*S + S - 1).  The ring X[0..R-1] holds
+// X_ch .. X_{ch+R-2} when chunk ch starts and the load of X_{ch+R-1} is issued
+// before its multiply-adds, so R-1 chunks of loads are in flight.
+// Reads rows up to base + (nch + R - 1) * S - 1.
+template <int S, int R, bool INTERIOR>
 __device__ __forceinline__ void blur_chunks(__amdgpu_buffer_rsrc_t rs, int stride4, int n,
                                             unsigned c, int base, int nch, cptr_t w,
                                             float (&acc)[S])
 {
-    unsigned voff[S];
+    unsigned vo[S];
 #pragma unroll
     for (int m = 0; m < S; ++m)
-        voff[m] = 4u * c + (INTERIOR ? (unsigned)(m * stride4) : 0u);
-    float A[S], B[S], C[S];
-    load_rows<S, INTERIOR>(A, rs, stride4, voff, base, n);
-    load_rows<S, INTERIOR>(B, rs, stride4, voff, base + S, n);
+        vo[m] = 4u * c + (INTERIOR ? (unsigned)(m * stride4) : 0u);
+    float X[R][S];
+#pragma unroll
+    for (int j = 0; j < R - 1; ++j)
+        load_rows<S, INTERIOR>(X[j], rs, stride4, vo, base + j * S, n);
     int ch = 0;
-    for (; ch + 3 <= nch; ch += 3) {
-        load_rows<S, INTERIOR>(C, rs, stride4, voff, base + (ch + 2) * S, n);
-        fma_chunk<S>(acc, A, B, w + ch * S);
-        load_rows<S, INTERIOR>(A, rs, stride4, voff, base + (ch + 3) * S, n);
-        fma_chunk<S>(acc, B, C, w + (ch + 1) * S);
-        load_rows<S, INTERIOR>(B, rs, stride4, voff, base + (ch + 4) * S, n);
-        fma_chunk<S>(acc, C, A, w + (ch + 2) * S);
+    for (; ch + R <= nch; ch += R) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            load_rows<S, INTERIOR>(X[(q + R - 1) % R], rs, stride4, vo, base + (ch + q + R - 1) * S, n);
+            fma_chunk<S>(acc, X[q], X[(q + 1) % R], w + (ch + q) * S);
+        }
     }
-    const int rem = nch - ch;
-    if (rem == 2)
-        load_rows<S, INTERIOR>(C, rs, stride4, voff, base + (ch + 2) * S, n);
-    if (rem >= 1)
-        fma_chunk<S>(acc, A, B, w + ch * S);
-    if (rem == 2)
-        fma_chunk<S>(acc, B, C, w + (ch + 1) * S);
+    // fewer than R chunks left; X[0..R-2] hold X_ch .. X_{ch+R-2}
+#pragma unroll
+    for (int q = 0; q < R - 1; ++q) {
+        if (q < nch - ch) {
+            if (q == R - 2)
+                load_rows<S, INTERIOR>(X[R - 1], rs, stride4, vo, base + (ch + R - 1) * S, n);
+            fma_chunk<S>(acc, X[q], X[q + 1], w + (ch + q) * S);
+        }
+    }
 }
 
 // acc[t] = sum_{j=0}^{2r} w[j] * col[refl(y0 - r + t + j)], t = 0..S-1, where
-// col[m] is column c of row m of the plane behind `rs`.  Taps are accumulated in ascending order, so
-// every output sees the same summation order whatever the tile shape; w must
-// be zero-padded up to ceil((2r+1)/S)*S.
-template <int S>
+// col[m] is column c of row m of the plane behind `rs`.  Taps are accumulated
+// in ascending order, so every output sees the same summation order whatever
+// the tile shape; w must be zero-padded up to ceil((2r+1)/S)*S.
+template <int S, int R>
 __device__ __forceinline__ void blur_strip(__amdgpu_buffer_rsrc_t rs, int stride4, int n, int c,
                                            int y0, int r, const float* w, float (&acc)[S])
 {
@@ -171,15 +173,20 @@ __device__ __forceinline__ void blur_strip(__amdgpu_buffer_rsrc_t rs, int stride
     for (int t = 0; t < S; ++t)
         acc[t] = 0.0f;
     const cptr_t cw = (cptr_t)w;
-    if (base >= 0 && base + (nch + 2) * S <= n)
-        blur_chunks<S, true>(rs, stride4, n, (unsigned)c, base, nch, cw, acc);
+    if (base >= 0 && base + (nch + R - 1) * S <= n)
+        blur_chunks<S, R, true>(rs, stride4, n, (unsigned)c, base, nch, cw, acc);
     else
-        blur_chunks<S, false>(rs, stride4, n, (unsigned)c, base, nch, cw, acc);
+        blur_chunks<S, R, false>(rs, stride4, n, (unsigned)c, base, nch, cw, acc);
 }
 
-// Pull the next tile id for the whole workgroup.
+// Pull the next tile id of one list for the whole workgroup.  The leading
+// barrier keeps thread 0's atomic in the same convergent region as the reads
+// that follow: without it the compiler may merge a thread-0-only block at the
+// end of the previous tile with this one across the loop back-edge, letting
+// the other lanes re-read a stale tile id.
 __device__ __forceinline__ int next_tile(uint32_t* ctr, int* s_tile)
 {
+    __syncthreads();
     if (threadIdx.x == 0)
         *s_tile = (int)atomicAdd(ctr, 1u);
     __syncthreads();
@@ -188,27 +195,55 @@ __device__ __forceinline__ int next_tile(uint32_t* ctr, int* s_tile)
     return t;
 }
 
+// Drain the home list (workgroup id mod 8), then the other lists, calling
+// body(unit, tile_within_unit) for each tile.  Every thread of the workgroup
+// calls body with the same arguments.
+template <class Body>
+__device__ __forceinline__ void drain_queues(const Queue* queue, uint32_t* ctr, int* s_tile,
+                                             Body&& body)
+{
+    const DOG_CONSTANT_AS Queue* q = cst(queue);
+    const int home = (int)(blockIdx.x % DOG_NXCD);
+    for (int s = 0; s < DOG_NXCD; ++s) {
+        const int x = (home + s) % DOG_NXCD;
+        const int total = q->total[x];
+        if (total == 0)
+            continue;
+        const DOG_CONSTANT_AS WorkUnit* units = cst(q->units) + q->off[x];
+        const int nu = q->n[x];
+        for (;;) {
+            const int tile = next_tile(ctr + x, s_tile);
+            if (tile < 0 || tile >= total)  // a counter read as negative also ends the list
+                break;
+            const WorkUnit u = units[find_unit(units, nu, tile)];
+            body(u, tile - u.first_tile);
+        }
+    }
+}
+
+__device__ __forceinline__ void clear_counters(uint32_t* c)
+{
+#pragma unroll
+    for (int i = 0; i < DOG_NXCD; ++i)
+        c[i] = 0u;
+}
+
 // Pass 1: T_p = column blur of the input frame, stored transposed.
 // Tile = 64 columns x (S*NW*BI) rows of one (frame, plane) unit.
-template <int S, int NW, int BI>
+template <int S, int R, int NW, int BI>
 __global__ void __launch_bounds__(64 * NW) k_pass1(LaunchArgs a)
 {
     __shared__ int s_tile;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     constexpr int BAND = S * NW * BI;
-    for (;;) {
-        const int tile = next_tile(&a.counters->pass1, &s_tile);
-        if (tile >= a.total1)
-            break;
-        if (tile == 0 && threadIdx.x == 0) {
-            a.counters->nms = 0u;
-            a.cand->count = 0u;
-        }
-        const WorkUnit u = cst(a.units1)[find_unit(a.units1, a.n_units1, tile)];
-        const int lt = tile - u.first_tile;
-        const int cb = lt / u.n_band;
-        const int band = lt - cb * u.n_band;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        clear_counters(a.counters->c[2]);
+        a.cand->count = 0u;
+    }
+    drain_queues(a.queues + 0, a.counters->c[0], &s_tile, [&](const WorkUnit& u, int lt) {
+        const int cb = u.cb0 + lt / u.n_band;
+        const int band = lt % u.n_band;
         const FrameDesc f = cst(a.frames)[u.frame];
         const int p = u.plane;
         const int r = cst(a.ladders)[f.ladder].r[p];
@@ -223,7 +258,7 @@ __global__ void __launch_bounds__(64 * NW) k_pass1(LaunchArgs a)
                 if (y0 >= f.H)
                     break;
                 float acc[S];
-                blur_strip<S>(rs, stride4, f.H, col, y0, r, w, acc);
+                blur_strip<S, R>(rs, stride4, f.H, col, y0, r, w, acc);
                 float* __restrict__ dst = f.T + ((long long)p * f.W + col) * f.pitch + y0;
                 if (y0 + S <= f.H) {
 #pragma unroll
@@ -238,28 +273,23 @@ __global__ void __launch_bounds__(64 * NW) k_pass1(LaunchArgs a)
                 }
             }
         }
-    }
+    });
 }
 
 // Pass 2: L_p = blur of T_p down its columns (along x of the frame); output in
 // the same transposed layout.  Tile = 64 columns (y) x (S*NW*BI) rows (x).
-template <int S, int NW, int BI>
+template <int S, int R, int NW, int BI>
 __global__ void __launch_bounds__(64 * NW) k_pass2(LaunchArgs a)
 {
     __shared__ int s_tile;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     constexpr int BAND = S * NW * BI;
-    for (;;) {
-        const int tile = next_tile(&a.counters->pass2, &s_tile);
-        if (tile >= a.total2)
-            break;
-        if (tile == 0 && threadIdx.x == 0)
-            a.counters->pass1 = 0u;
-        const WorkUnit u = cst(a.units2)[find_unit(a.units2, a.n_units2, tile)];
-        const int lt = tile - u.first_tile;
-        const int cb = lt / u.n_band;
-        const int band = lt - cb * u.n_band;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        clear_counters(a.counters->c[0]);
+    drain_queues(a.queues + 1, a.counters->c[1], &s_tile, [&](const WorkUnit& u, int lt) {
+        const int cb = u.cb0 + lt / u.n_band;
+        const int band = lt % u.n_band;
         const FrameDesc f = cst(a.frames)[u.frame];
         const int p = u.plane;
         const int r = cst(a.ladders)[f.ladder].r[p];
@@ -275,36 +305,61 @@ __global__ void __launch_bounds__(64 * NW) k_pass2(LaunchArgs a)
                 if (x0 >= f.W)
                     break;
                 float acc[S];
-                blur_strip<S>(rs, stride4, f.W, col, x0, r, w, acc);
+                blur_strip<S, R>(rs, stride4, f.W, col, x0, r, w, acc);
 #pragma unroll
                 for (int t = 0; t < S; ++t)
                     if (x0 + t < f.W)
                         dstp[(long long)(x0 + t) * f.pitch + col] = acc[t];
             }
         }
+    });
+}
+
+// Lanes i-1 and i+1 of a wave (-inf where the neighbour lane does not exist).
+__device__ __forceinline__ float lane_prev(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, -INFINITY),
+                                                                 __builtin_bit_cast(int, v), 0x138,
+                                                                 0xf, 0xf, false));
+}
+
+__device__ __forceinline__ float lane_next(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, -INFINITY),
+                                                                 __builtin_bit_cast(int, v), 0x130,
+                                                                 0xf, 0xf, false));
+}
+
+// Rows x0-1 .. x0+BN of column y of transposed plane p (0 outside the frame).
+template <int BN>
+__device__ __forceinline__ void load_plane_rows(float (&v)[BN + 2], const FrameDesc& f, int p,
+                                                int x0, unsigned voff)
+{
+    const __amdgpu_buffer_rsrc_t rs = plane_rsrc(f.L + (long long)p * f.W * f.pitch,
+                                                 (unsigned)((long long)f.W * f.pitch * 4));
+    const int stride4 = (int)(f.pitch * 4);
+#pragma unroll
+    for (int j = 0; j < BN + 2; ++j) {
+        const int x = x0 - 1 + j;
+        v[j] = (x >= 0 && x < f.W) ? load_f32(rs, voff, x * stride4) : 0.0f;
     }
 }
 
-// DoG of one scale over a band of BN rows plus a one-row halo on each side:
-// loads L_{i+1} (rows x0-1 .. x0+BN), forms D_i = sigma_i (L_i - L_{i+1}) with
-// -inf outside the frame, and returns the 3x3 spatial maxima s3 and the
-// centre values dc of the BN band rows.  Lp holds L_i on entry, L_{i+1} on exit.
+// DoG of one scale over BN band rows plus a one-row halo on each side:
+// D = sigma (La - Lb), -inf outside the frame; returns the 3x3 spatial maxima
+// s3 and the centre values dc of the band rows.
 template <int BN>
-__device__ __forceinline__ void dog_plane(const float* __restrict__ Lnext, long long pitch, int W,
-                                          int x0, int y, bool ycol, float sigma,
-                                          float (&Lp)[BN + 2], float (&s3)[BN], float (&dc)[BN])
+__device__ __forceinline__ void dog_rows(const float (&La)[BN + 2], const float (&Lb)[BN + 2],
+                                         float sigma, int x0, int W, bool ycol, float (&s3)[BN],
+                                         float (&dc)[BN])
 {
     float hm[BN + 2];
 #pragma unroll
     for (int j = 0; j < BN + 2; ++j) {
         const int x = x0 - 1 + j;
         const bool ok = ycol && x >= 0 && x < W;
-        const float ln = ok ? Lnext[(long long)x * pitch + y] : 0.0f;
-        const float d = ok ? sigma * (Lp[j] - ln) : -INFINITY;
-        Lp[j] = ln;
-        const float up = __shfl_up(d, 1);
-        const float dn = __shfl_down(d, 1);
-        hm[j] = fmaxf(d, fmaxf(up, dn));
+        const float d = ok ? sigma * (La[j] - Lb[j]) : -INFINITY;
+        hm[j] = fmaxf(d, fmaxf(lane_prev(d), lane_next(d)));
         if (j >= 1 && j <= BN)
             dc[j - 1] = d;
     }
@@ -313,26 +368,32 @@ __device__ __forceinline__ void dog_plane(const float* __restrict__ Lnext, long 
         s3[j] = fmaxf(hm[j], fmaxf(hm[j + 1], hm[j + 2]));
 }
 
+#define DOG_LDS_RECS 512
+
 // Local maxima of the DoG cube with threshold, compacted into records.
 // Tile = 62 output columns (y; lanes 1..62, lanes 0 and 63 are the halo)
-// x (BN*NW) rows (x) of one frame; every wave walks all scales.
+// x (BN*NW) rows (x) of one frame; every wave walks all scales, with the
+// loads of plane i+3 in flight while plane i+1's DoG is formed.  Survivors
+// are appended to a workgroup buffer in LDS and flushed with one global
+// atomic per tile.
 template <int BN, int NW>
 __global__ void __launch_bounds__(64 * NW) k_nms(LaunchArgs a)
 {
     __shared__ int s_tile;
+    __shared__ uint32_t s_n;
+    __shared__ uint32_t s_base;
+    __shared__ CandRec s_rec[DOG_LDS_RECS];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     CandRec* __restrict__ recs = reinterpret_cast<CandRec*>(a.cand + 1);
-    for (;;) {
-        const int tile = next_tile(&a.counters->nms, &s_tile);
-        if (tile >= a.total3)
-            break;
-        if (tile == 0 && threadIdx.x == 0)
-            a.counters->pass2 = 0u;
-        const WorkUnit u = cst(a.units3)[find_unit(a.units3, a.n_units3, tile)];
-        const int lt = tile - u.first_tile;
-        const int cb = lt / u.n_band;
-        const int band = lt - cb * u.n_band;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        clear_counters(a.counters->c[1]);
+    if (threadIdx.x == 0)
+        s_n = 0u;
+    __syncthreads();
+    drain_queues(a.queues + 2, a.counters->c[2], &s_tile, [&](const WorkUnit& u, int lt) {
+        const int cb = u.cb0 + lt / u.n_band;
+        const int band = lt % u.n_band;
         const FrameDesc f = cst(a.frames)[u.frame];
         const DOG_CONSTANT_AS LadderDesc* ld = cst(a.ladders) + f.ladder;
         const int k = ld->n_g - 1;
@@ -340,24 +401,31 @@ __global__ void __launch_bounds__(64 * NW) k_nms(LaunchArgs a)
         const int y = cb * DOG_NMS_COLS - 1 + lane;
         const bool ycol = y >= 0 && y < f.H;
         const bool yout = ycol && lane >= 1 && lane <= DOG_NMS_COLS;
+        const unsigned voff = (unsigned)(ycol ? y : 0) * 4u;
         const int x0 = band * (BN * NW) + wv * BN;
         if (x0 < f.W) {  // wave-uniform
             const long long plane_sz = (long long)f.W * f.pitch;
-            float Lp[BN + 2];
-#pragma unroll
-            for (int j = 0; j < BN + 2; ++j) {
-                const int x = x0 - 1 + j;
-                Lp[j] = (ycol && x >= 0 && x < f.W) ? f.L[(long long)x * f.pitch + y] : 0.0f;
-            }
+            float La[BN + 2], Lb[BN + 2], Lc[BN + 2], Ld[BN + 2];
+            load_plane_rows<BN>(La, f, 0, x0, voff);
+            load_plane_rows<BN>(Lb, f, 1, x0, voff);
+            if (k >= 2)
+                load_plane_rows<BN>(Lc, f, 2, x0, voff);
             float s3m[BN], s3c[BN], s3n[BN], dc[BN], dn[BN];
 #pragma unroll
             for (int j = 0; j < BN; ++j)
                 s3m[j] = -INFINITY;
-            dog_plane<BN>(f.L + plane_sz, f.pitch, f.W, x0, y, ycol, ld->sigma[0], Lp, s3c, dc);
+            dog_rows<BN>(La, Lb, ld->sigma[0], x0, f.W, ycol, s3c, dc);
             for (int i = 0; i < k; ++i) {
+                // Lb = L_{i+1}, Lc = L_{i+2} (when i + 2 <= k)
                 if (i + 1 < k) {
-                    dog_plane<BN>(f.L + (long long)(i + 2) * plane_sz, f.pitch, f.W, x0, y, ycol,
-                                  ld->sigma[i + 1], Lp, s3n, dn);
+                    if (i + 3 <= k)
+                        load_plane_rows<BN>(Ld, f, i + 3, x0, voff);
+                    dog_rows<BN>(Lb, Lc, ld->sigma[i + 1], x0, f.W, ycol, s3n, dn);
+#pragma unroll
+                    for (int j = 0; j < BN + 2; ++j) {
+                        Lb[j] = Lc[j];
+                        Lc[j] = Ld[j];
+                    }
                 } else {
 #pragma unroll
                     for (int j = 0; j < BN; ++j) {
@@ -369,26 +437,31 @@ __global__ void __launch_bounds__(64 * NW) k_nms(LaunchArgs a)
                 for (int j = 0; j < BN; ++j) {
                     const int x = x0 + j;
                     const float m = fmaxf(s3m[j], fmaxf(s3c[j], s3n[j]));
-                    const bool flag = yout && x < f.W && dc[j] == m && dc[j] > thr;
-                    if (f.Ddbg != nullptr && yout && x < f.W)
+                    const bool inside = yout && x < f.W;
+                    const bool flag = inside && dc[j] == m && dc[j] > thr;
+                    if (f.Ddbg != nullptr && inside)
                         f.Ddbg[(long long)i * plane_sz + (long long)x * f.pitch + y] = dc[j];
                     const unsigned long long bal = __ballot(flag);
                     if (bal != 0ull) {
                         unsigned base = 0;
                         if (lane == 0)
-                            base = atomicAdd(&a.cand->count, (unsigned)__popcll(bal));
+                            base = atomicAdd(&s_n, (unsigned)__popcll(bal));
                         base = __shfl(base, 0);
                         if (flag) {
+                            CandRec rec;
+                            rec.frame = f.frame_id;
+                            rec.y = y;
+                            rec.x = x;
+                            rec.scale = i;
+                            rec.response = dc[j];
                             const unsigned idx =
                                 base + (unsigned)__popcll(bal & ((1ull << lane) - 1ull));
-                            if (idx < a.cap) {
-                                CandRec rec;
-                                rec.frame = f.frame_id;
-                                rec.y = y;
-                                rec.x = x;
-                                rec.scale = i;
-                                rec.response = dc[j];
-                                recs[idx] = rec;
+                            if (idx < DOG_LDS_RECS) {
+                                s_rec[idx] = rec;
+                            } else {
+                                const unsigned g = atomicAdd(&a.cand->count, 1u);
+                                if (g < a.cap)
+                                    recs[g] = rec;
                             }
                         }
                     }
@@ -401,7 +474,25 @@ __global__ void __launch_bounds__(64 * NW) k_nms(LaunchArgs a)
                 }
             }
         }
-    }
+        // flush this tile's records: one global atomic for the workgroup.
+        // s_n is reset between barriers (every thread has read it, none
+        // appends again before the next tile), and the body ends on a
+        // barrier so the copies finish before s_rec is reused.
+        __syncthreads();
+        const uint32_t n = s_n < DOG_LDS_RECS ? s_n : DOG_LDS_RECS;
+        if (threadIdx.x == 0)
+            s_base = n ? atomicAdd(&a.cand->count, n) : 0u;
+        __syncthreads();
+        const uint32_t gbase = s_base;
+        if (threadIdx.x == 0)
+            s_n = 0u;
+        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const uint32_t g = gbase + i;
+            if (g < a.cap)
+                recs[g] = s_rec[i];
+        }
+        __syncthreads();
+    });
 }
 
 // dst[(p*H + y)*W + x] = src[(p*W + x)*pitch + y]: back to row-major planes.
@@ -431,17 +522,18 @@ struct KernelSet {
     const void* pass1;
     const void* pass2;
     const void* nms;
-    int S, NW, BI, BN, NWN;
+    int S, R, NW, BI, BN, NWN;
 };
 
-template <int S, int NW, int BI, int BN, int NWN>
+template <int S, int R, int NW, int BI, int BN, int NWN>
 static KernelSet make_set()
 {
     KernelSet k;
-    k.pass1 = reinterpret_cast<const void*>(&k_pass1<S, NW, BI>);
-    k.pass2 = reinterpret_cast<const void*>(&k_pass2<S, NW, BI>);
+    k.pass1 = reinterpret_cast<const void*>(&k_pass1<S, R, NW, BI>);
+    k.pass2 = reinterpret_cast<const void*>(&k_pass2<S, R, NW, BI>);
     k.nms = reinterpret_cast<const void*>(&k_nms<BN, NWN>);
     k.S = S;
+    k.R = R;
     k.NW = NW;
     k.BI = BI;
     k.BN = BN;
@@ -449,17 +541,18 @@ static KernelSet make_set()
     return k;
 }
 
-// Variants available to the autotuner: (S, waves, strips per wave) for the
-// blur passes and (rows, waves) for the local-maximum kernel.
+// Variants available to the autotuner: (S outputs per lane, R ring buffers,
+// waves per workgroup, strips per wave) for the blur passes and (rows per
+// wave, waves) for the local-maximum kernel.
 static const KernelSet kSets[] = {
-    make_set<8, 4, 2, 16, 4>(),
-    make_set<8, 4, 4, 16, 4>(),
-    make_set<8, 4, 8, 16, 4>(),
-    make_set<8, 4, 1, 16, 4>(),
-    make_set<4, 4, 4, 16, 4>(),
-    make_set<12, 4, 2, 16, 4>(),
-    make_set<16, 4, 1, 16, 4>(),
-    make_set<8, 4, 16, 16, 4>(),
+    make_set<8, 6, 4, 1, 8, 4>(),
+    make_set<8, 4, 4, 1, 8, 4>(),
+    make_set<8, 8, 4, 1, 8, 4>(),
+    make_set<8, 6, 4, 2, 8, 4>(),
+    make_set<16, 4, 4, 1, 8, 4>(),
+    make_set<12, 4, 4, 1, 8, 4>(),
+    make_set<4, 10, 4, 1, 8, 4>(),
+    make_set<8, 6, 4, 1, 16, 4>(),
 };
 
 }  // namespace dog
@@ -478,20 +571,33 @@ void dogk_variant_geometry(int v, int* S, int* NW, int* BI, int* BN, int* NWN)
     *NWN = k.NWN;
 }
 
+int dogk_variant_ring(int v) { return dog::kSets[v].R; }
+
 // Launch pass 1, pass 2 and the local-maximum kernel on `stream` with the
-// given persistent grid sizes.  Returns the first launch error.
+// given persistent grid sizes (multiples of 8 keep the XCD lists balanced).
+// If ev is non-NULL, events ev[0..3] are recorded before, between and after
+// the kernels.  Returns the first launch error.
 hipError_t dogk_launch_sequence(int variant, const dog::LaunchArgs* args, int grid1, int grid2,
-                                int grid3, hipStream_t stream)
+                                int grid3, hipStream_t stream, hipEvent_t* ev)
 {
     const dog::KernelSet& k = dog::kSets[variant];
     void* params[] = {const_cast<dog::LaunchArgs*>(args)};
-    hipError_t e = hipLaunchKernel(k.pass1, dim3(grid1), dim3(64 * k.NW), params, 0, stream);
-    if (e != hipSuccess)
-        return e;
-    e = hipLaunchKernel(k.pass2, dim3(grid2), dim3(64 * k.NW), params, 0, stream);
-    if (e != hipSuccess)
-        return e;
-    return hipLaunchKernel(k.nms, dim3(grid3), dim3(64 * k.NWN), params, 0, stream);
+    hipError_t e = hipSuccess;
+    if (ev)
+        e = hipEventRecord(ev[0], stream);
+    if (e == hipSuccess)
+        e = hipLaunchKernel(k.pass1, dim3(grid1), dim3(64 * k.NW), params, 0, stream);
+    if (e == hipSuccess && ev)
+        e = hipEventRecord(ev[1], stream);
+    if (e == hipSuccess)
+        e = hipLaunchKernel(k.pass2, dim3(grid2), dim3(64 * k.NW), params, 0, stream);
+    if (e == hipSuccess && ev)
+        e = hipEventRecord(ev[2], stream);
+    if (e == hipSuccess)
+        e = hipLaunchKernel(k.nms, dim3(grid3), dim3(64 * k.NWN), params, 0, stream);
+    if (e == hipSuccess && ev)
+        e = hipEventRecord(ev[3], stream);
+    return e;
 }
 
 hipError_t dogk_launch_nms(int variant, const dog::LaunchArgs* args, int grid3, hipStream_t stream)

@@ -174,73 +174,106 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
     if (D0)
         *D0 = fd[0].Ddbg;
 
+    // ---- per-XCD work lists.  Each (frame, plane) unit's column blocks are
+    // cut into DOG_NXCD contiguous slices; slice s goes to XCD (s + frame) %
+    // DOG_NXCD so one XCD's L2 holds one band of columns of every plane (and
+    // small frames spread over the XCDs).  Within a list, units are ordered
+    // widest kernel first so the persistent grid drains evenly.
     const int band = V.band();
-    std::vector<WorkUnit> u1, u2, u3;
-    u1.reserve((size_t)n * n_g);
-    u2.reserve((size_t)n * n_g);
+    struct Raw {
+        int frame, plane, n_cb, n_band, radius;
+    };
+    std::vector<Raw> r1, r2, r3;
     for (int f = 0; f < n; ++f) {
         const int H = frames[f].H, W = frames[f].W;
         for (int p = 0; p < n_g; ++p) {
-            WorkUnit a{};
-            a.frame = f;
-            a.plane = p;
-            a.n_cb = (W + 63) / 64;
-            a.n_band = (H + band - 1) / band;
-            u1.push_back(a);
-            WorkUnit b{};
-            b.frame = f;
-            b.plane = p;
-            b.n_cb = (H + 63) / 64;
-            b.n_band = (W + band - 1) / band;
-            u2.push_back(b);
+            r1.push_back({f, p, (W + 63) / 64, (H + band - 1) / band, P.r[p]});
+            r2.push_back({f, p, (H + 63) / 64, (W + band - 1) / band, P.r[p]});
         }
-        WorkUnit m{};
-        m.frame = f;
-        m.plane = 0;
-        m.n_cb = (H + DOG_NMS_COLS - 1) / DOG_NMS_COLS;
-        m.n_band = (W + V.nms_band() - 1) / V.nms_band();
-        u3.push_back(m);
+        r3.push_back({f, 0, (H + DOG_NMS_COLS - 1) / DOG_NMS_COLS,
+                      (W + V.nms_band() - 1) / V.nms_band(), 0});
     }
-    // widest kernels first so the persistent grid drains evenly
-    auto by_cost = [&](const WorkUnit& a, const WorkUnit& b) {
-        if (P.r[a.plane] != P.r[b.plane])
-            return P.r[a.plane] > P.r[b.plane];
+    auto by_cost = [](const Raw& a, const Raw& b) {
+        if (a.radius != b.radius)
+            return a.radius > b.radius;
         return a.frame < b.frame;
     };
-    std::stable_sort(u1.begin(), u1.end(), by_cost);
-    std::stable_sort(u2.begin(), u2.end(), by_cost);
-    auto prefix = [](std::vector<WorkUnit>& u) {
-        long long t = 0;
-        for (WorkUnit& w : u) {
-            w.first_tile = (int)t;
-            t += (long long)w.n_cb * w.n_band;
-        }
-        return t;
+    std::stable_sort(r1.begin(), r1.end(), by_cost);
+    std::stable_sort(r2.begin(), r2.end(), by_cost);
+    struct Lists {
+        std::vector<WorkUnit> units;
+        Queue q;
     };
-    const long long t1 = prefix(u1), t2 = prefix(u2), t3 = prefix(u3);
-    if (t1 > INT32_MAX / 2 || t2 > INT32_MAX / 2 || t3 > INT32_MAX / 2) {
+    auto slice = [](const std::vector<Raw>& raw, Lists* L) -> bool {
+        std::vector<WorkUnit> per[DOG_NXCD];
+        long long tot[DOG_NXCD] = {0};
+        for (const Raw& r : raw) {
+            for (int s = 0; s < DOG_NXCD; ++s) {
+                const int c0 = (int)((long long)s * r.n_cb / DOG_NXCD);
+                const int c1 = (int)((long long)(s + 1) * r.n_cb / DOG_NXCD);
+                if (c1 <= c0)
+                    continue;
+                const int x = (s + r.frame) % DOG_NXCD;
+                WorkUnit w{};
+                w.frame = r.frame;
+                w.plane = r.plane;
+                w.cb0 = c0;
+                w.n_cb = c1 - c0;
+                w.n_band = r.n_band;
+                w.first_tile = (int)tot[x];
+                tot[x] += (long long)w.n_cb * w.n_band;
+                per[x].push_back(w);
+            }
+        }
+        L->units.clear();
+        std::memset(&L->q, 0, sizeof(L->q));
+        for (int x = 0; x < DOG_NXCD; ++x) {
+            if (tot[x] > INT32_MAX / 2)
+                return false;
+            L->q.off[x] = (int)L->units.size();
+            L->q.n[x] = (int)per[x].size();
+            L->q.total[x] = (int)tot[x];
+            L->units.insert(L->units.end(), per[x].begin(), per[x].end());
+        }
+        return true;
+    };
+    Lists l1, l2, l3;
+    if (!slice(r1, &l1) || !slice(r2, &l2) || !slice(r3, &l3)) {
         set_error("batch too large for one launch");
         return DOG_EINVAL;
+    }
+    long long t1 = 0, t2 = 0, t3 = 0;
+    for (int x = 0; x < DOG_NXCD; ++x) {
+        t1 += l1.q.total[x];
+        t2 += l2.q.total[x];
+        t3 += l3.q.total[x];
     }
 
     const size_t o_frames = 0;
     const size_t o_ladder = align_up(o_frames + sizeof(FrameDesc) * n, 256);
     const size_t o_weights = align_up(o_ladder + sizeof(LadderDesc), 256);
-    const size_t o_u1 = align_up(o_weights + sizeof(float) * P.weights.size(), 256);
-    const size_t o_u2 = align_up(o_u1 + sizeof(WorkUnit) * u1.size(), 256);
-    const size_t o_u3 = align_up(o_u2 + sizeof(WorkUnit) * u2.size(), 256);
-    const size_t tbytes = align_up(o_u3 + sizeof(WorkUnit) * u3.size(), 256);
+    const size_t o_queues = align_up(o_weights + sizeof(float) * P.weights.size(), 256);
+    const size_t o_u1 = align_up(o_queues + sizeof(Queue) * 3, 256);
+    const size_t o_u2 = align_up(o_u1 + sizeof(WorkUnit) * l1.units.size(), 256);
+    const size_t o_u3 = align_up(o_u2 + sizeof(WorkUnit) * l2.units.size(), 256);
+    const size_t tbytes = align_up(o_u3 + sizeof(WorkUnit) * l3.units.size(), 256);
     if ((rc = ctx_alloc(c, &c->tables, tbytes, "launch tables")) != DOG_OK)
         return rc;
     if ((rc = ctx_pin(&c->h_tables, tbytes)) != DOG_OK)
         return rc;
+    char* dt = static_cast<char*>(c->tables.p);
+    l1.q.units = reinterpret_cast<const WorkUnit*>(dt + o_u1);
+    l2.q.units = reinterpret_cast<const WorkUnit*>(dt + o_u2);
+    l3.q.units = reinterpret_cast<const WorkUnit*>(dt + o_u3);
+    const Queue qs[3] = {l1.q, l2.q, l3.q};
     char* h = static_cast<char*>(c->h_tables.p);
     std::memcpy(h + o_frames, fd.data(), sizeof(FrameDesc) * n);
     std::memcpy(h + o_ladder, &P.desc, sizeof(LadderDesc));
     std::memcpy(h + o_weights, P.weights.data(), sizeof(float) * P.weights.size());
-    std::memcpy(h + o_u1, u1.data(), sizeof(WorkUnit) * u1.size());
-    std::memcpy(h + o_u2, u2.data(), sizeof(WorkUnit) * u2.size());
-    std::memcpy(h + o_u3, u3.data(), sizeof(WorkUnit) * u3.size());
+    std::memcpy(h + o_queues, qs, sizeof(qs));
+    std::memcpy(h + o_u1, l1.units.data(), sizeof(WorkUnit) * l1.units.size());
+    std::memcpy(h + o_u2, l2.units.data(), sizeof(WorkUnit) * l2.units.size());
+    std::memcpy(h + o_u3, l3.units.data(), sizeof(WorkUnit) * l3.units.size());
     DOG_HIP(hipMemcpyAsync(c->tables.p, h, tbytes, hipMemcpyHostToDevice, s));
 
     // ---- candidate buffer
@@ -251,30 +284,32 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
         c->cap = 65536;
     }
 
-    char* dt = static_cast<char*>(c->tables.p);
     LaunchArgs a;
     std::memset(&a, 0, sizeof(a));
     a.frames = reinterpret_cast<const FrameDesc*>(dt + o_frames);
     a.ladders = reinterpret_cast<const LadderDesc*>(dt + o_ladder);
     a.weights = reinterpret_cast<const float*>(dt + o_weights);
-    a.units1 = reinterpret_cast<const WorkUnit*>(dt + o_u1);
-    a.units2 = reinterpret_cast<const WorkUnit*>(dt + o_u2);
-    a.units3 = reinterpret_cast<const WorkUnit*>(dt + o_u3);
+    a.queues = reinterpret_cast<const Queue*>(dt + o_queues);
     a.counters = static_cast<Counters*>(c->counters.p);
     a.cand = static_cast<CandHeader*>(c->cand.p);
-    a.n_units1 = (int)u1.size();
-    a.n_units2 = (int)u2.size();
-    a.n_units3 = (int)u3.size();
-    a.total1 = (int)t1;
-    a.total2 = (int)t2;
-    a.total3 = (int)t3;
     a.cap = c->cap;
 
+    // persistent grids: resident capacity, a multiple of DOG_NXCD, no more
+    // workgroups than tiles (rounded up to DOG_NXCD)
     auto grid = [&](int i, long long tiles) {
         long long g = c->grid_override > 0 ? c->grid_override : (long long)c->occ[i] * c->n_cu;
-        return (int)std::max(1LL, std::min(g, tiles));
+        const long long t8 = (tiles + DOG_NXCD - 1) / DOG_NXCD * DOG_NXCD;
+        g = std::min(g, t8);
+        g = g / DOG_NXCD * DOG_NXCD;
+        return (int)std::max<long long>(DOG_NXCD, g);
     };
-    DOG_HIP(dogk_launch_sequence(c->variant, &a, grid(0, t1), grid(1, t2), grid(2, t3), s));
+    if (c->profiling) {
+        for (int i = 0; i < 4; ++i)
+            if (!c->ev[i])
+                DOG_HIP(hipEventCreate(&c->ev[i]));
+    }
+    DOG_HIP(dogk_launch_sequence(c->variant, &a, grid(0, t1), grid(1, t2), grid(2, t3), s,
+                                 c->profiling ? c->ev : nullptr));
 
     // ---- readback: header + a guess of the records in one copy
     uint32_t guess = std::min<uint32_t>(c->cap, std::max<uint32_t>(4096, c->last_count + c->last_count / 4 + 256));
@@ -284,6 +319,14 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
                            hipMemcpyDeviceToHost, s));
     DOG_HIP(hipStreamSynchronize(s));
     uint32_t count = static_cast<CandHeader*>(c->h_cand.p)->count;
+    if (c->profiling) {
+        for (int i = 0; i < 3; ++i) {
+            float ms = 0.0f;
+            DOG_HIP(hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
+            c->kernel_ms[i] += ms;
+        }
+        c->kernel_launches += 1;
+    }
     if (count > c->cap) {
         // overflow: enlarge the record buffer and rerun only the local-maximum
         // kernel; the planes are still in the workspace
@@ -296,7 +339,7 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
             return rc;
         a.cand = static_cast<CandHeader*>(c->cand.p);
         a.cap = c->cap;
-        DOG_HIP(dogk_fill_u32(&a.counters->nms, 1, 0u, s));
+        DOG_HIP(dogk_fill_u32(a.counters->c[2], DOG_NXCD, 0u, s));
         DOG_HIP(dogk_fill_u32(&a.cand->count, 1, 0u, s));
         DOG_HIP(dogk_launch_nms(c->variant, &a, grid(2, t3), s));
         DOG_HIP(hipMemcpyAsync(c->h_cand.p, c->cand.p, sizeof(CandHeader) + kRecBytes * count,

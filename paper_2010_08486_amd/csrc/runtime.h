@@ -75,8 +75,9 @@ struct Variant {
 extern "C" {
 int dogk_num_variants();
 void dogk_variant_geometry(int v, int* S, int* NW, int* BI, int* BN, int* NWN);
+int dogk_variant_ring(int v);
 hipError_t dogk_launch_sequence(int variant, const dog::LaunchArgs* args, int grid1, int grid2,
-                                int grid3, hipStream_t stream);
+                                int grid3, hipStream_t stream, hipEvent_t* ev);
 hipError_t dogk_launch_nms(int variant, const dog::LaunchArgs* args, int grid3, hipStream_t stream);
 hipError_t dogk_untranspose(const float* src, float* dst, int n_planes, int H, int W,
                             long long pitch, hipStream_t stream);
@@ -105,6 +106,13 @@ struct dog_context {
     dog::PinBuf h_tables;          // staging of the launch tables
     dog::PinBuf h_cand;            // readback of header + records
     dog::PinBuf h_input;           // staging of host frames
+
+    // optional per-kernel timing with HIP events recorded around each kernel
+    // on the stream it is launched on
+    bool profiling = false;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    double kernel_ms[3] = {0.0, 0.0, 0.0};
+    int64_t kernel_launches = 0;
 
     bool have_plan = false;
     dog::Plan plan;
