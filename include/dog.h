@@ -196,8 +196,6 @@ int dog_set_variant(dog_context* ctx, int variant);
 int dog_set_profiling(dog_context* ctx, int32_t on);
 int dog_kernel_times(dog_context* ctx, double* ms_out, int64_t* launches_out);
 
-/* Persistent-grid size (workgroups per kernel); 0 = automatic. */
-int dog_set_grid(dog_context* ctx, int32_t workgroups);
 
 #ifdef __cplusplus
 }

@@ -110,7 +110,6 @@ def lib() -> ctypes.CDLL:
         "dog_num_variants": (ctypes.c_int, []),
         "dog_variant_info": (ctypes.c_int, [ctypes.c_int] + [ctypes.POINTER(i32)] * 4),
         "dog_set_variant": (ctypes.c_int, [vp, ctypes.c_int]),
-        "dog_set_grid": (ctypes.c_int, [vp, i32]),
         "dog_set_profiling": (ctypes.c_int, [vp, i32]),
         "dog_kernel_times": (ctypes.c_int, [vp, ctypes.POINTER(dbl), pi64]),
     }
@@ -219,9 +218,6 @@ class Context:
 
     def set_variant(self, v: int) -> None:
         _check(lib().dog_set_variant(self._h, v))
-
-    def set_grid(self, workgroups: int) -> None:
-        _check(lib().dog_set_grid(self._h, workgroups))
 
     def set_profiling(self, on: bool) -> None:
         _check(lib().dog_set_profiling(self._h, 1 if on else 0))

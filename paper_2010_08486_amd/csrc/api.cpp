@@ -16,6 +16,7 @@ using namespace dog;
 namespace {
 
 constexpr int kMaxSide = 32768;
+constexpr int kDefaultVariant = 5;  // S = 12, R = 4: fastest on 1024x1024 frames
 
 int check_image(const void* p, int64_t h, int64_t w, int64_t stride)
 {
@@ -77,7 +78,7 @@ void free_context(dog_context* c)
     (void)hipSetDevice(c->device);
     if (c->stream)
         (void)hipStreamSynchronize(c->stream);
-    for (DevBuf* b : {&c->planes, &c->input, &c->tables, &c->cand, &c->counters})
+    for (DevBuf* b : {&c->planes, &c->input, &c->tables, &c->cand})
         if (b->p)
             (void)hipFree(b->p);
     for (PinBuf* b : {&c->h_tables, &c->h_cand, &c->h_input})
@@ -135,19 +136,8 @@ int dog_context_create(int device, uint64_t hbm_budget_bytes, dog_context** ctx)
     DOG_HIP(hipMemGetInfo(&free_b, &total_b));
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)free_b);
     DOG_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
-    int rc = ctx_alloc(c.get(), &c->counters, sizeof(Counters), "counters");
-    if (rc != DOG_OK) {
-        free_context(c.release());
-        return rc;
-    }
-    if (hipMemsetAsync(c->counters.p, 0, c->counters.bytes, c->stream) != hipSuccess ||
-        hipStreamSynchronize(c->stream) != hipSuccess) {
-        free_context(c.release());
-        set_error("failed to clear counters");
-        return DOG_EDEVICE;
-    }
-    c->variant_auto = 0;
-    rc = ctx_set_variant(c.get(), 0);
+    c->variant_auto = kDefaultVariant;
+    int rc = ctx_set_variant(c.get(), kDefaultVariant);
     if (rc != DOG_OK) {
         free_context(c.release());
         return rc;
@@ -217,15 +207,6 @@ int dog_kernel_times(dog_context* ctx, double* ms_out, int64_t* launches_out)
     return DOG_OK;
 }
 
-int dog_set_grid(dog_context* ctx, int32_t workgroups)
-{
-    if (!ctx || workgroups < 0) {
-        set_error("invalid argument");
-        return DOG_EINVAL;
-    }
-    ctx->grid_override = workgroups;
-    return DOG_OK;
-}
 
 int dog_prune(const dog_params* params, dog_blob* blobs, int64_t n, int64_t* n_out)
 {

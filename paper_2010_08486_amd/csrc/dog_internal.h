@@ -47,30 +47,20 @@ struct LadderDesc {
     float sigma[DOG_MAX_GAUSS];   // sigma_p rounded to fp32 (DoG scale factor)
 };
 
-// A unit of work of one kernel: one (frame, plane) for the blur passes or one
-// frame for the local-maximum kernel, restricted to the column blocks
-// [cb0, cb0 + n_cb) and tiled into n_cb x n_band tiles.
-struct WorkUnit {
-    int frame;
-    int plane;
-    int cb0;           // first column block of this slice
-    int n_cb;          // column blocks in this slice
-    int n_band;        // row bands
-    int first_tile;    // prefix sum of tiles over the preceding units of the same list
-    int pad_[2];
-};
-
 #define DOG_NXCD 8     // accelerator complex dies (each with its own L2)
 
-// One kernel's work split into DOG_NXCD lists, one per XCD: list c holds the
-// column slices meant to stay in XCD c's L2 and is drained first by the
-// workgroups dispatched to XCD c (workgroup id mod 8); idle workgroups then
-// steal from the other lists.
-struct Queue {
-    const WorkUnit* units;     // all lists back to back
-    int off[DOG_NXCD];         // first unit of list c
-    int n[DOG_NXCD];           // units in list c
-    int total[DOG_NXCD];       // tiles in list c
+// One workgroup's tile: column block cb and row band of plane `plane` of
+// frame `frame` (plane unused by the local-maximum kernel).  Each kernel is
+// launched with one workgroup per tile and reads its tile from a host-built
+// table indexed by the workgroup id; the table lists the tiles widest kernel
+// first and interleaves XCD-local column slices so that workgroup b, which
+// the dispatcher places on XCD b mod 8, works on that XCD's slice.
+struct Tile {
+    uint16_t frame;
+    uint8_t plane;
+    uint8_t pad_;
+    uint16_t cb;
+    uint16_t band;
 };
 
 // Candidate record written by the local-maximum kernel.
@@ -88,25 +78,17 @@ struct CandHeader {
     uint32_t pad_[3];
 };
 
-// Tile counters of the three persistent kernels, one per XCD list.  Block 0
-// of each kernel clears the counters of the kernel two steps ahead in the
-// launch sequence (pass 1 -> local maxima, pass 2 -> pass 1, local maxima ->
-// pass 2), which are never in use at that time.
-struct Counters {
-    uint32_t c[3][DOG_NXCD];
-};
-
 // Arguments of one launch sequence (all pointers are device pointers).
 struct LaunchArgs {
     const FrameDesc* frames;
     const LadderDesc* ladders;
     const float* weights;
-    const Queue* queues;        // [3]: pass 1, pass 2, local maxima
-    Counters* counters;
+    const Tile* tiles1;         // pass 1, one per workgroup
+    const Tile* tiles2;         // pass 2
+    const Tile* tiles3;         // local maxima
     CandHeader* cand;           // header; records at (CandRec*)(cand + 1)
     uint32_t cap;               // record capacity
-    int pad_;
+    int n1, n2, n3;             // tiles (= workgroups) of each kernel
 };
-
 
 }  // namespace dog

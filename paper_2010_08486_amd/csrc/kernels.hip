@@ -21,10 +21,11 @@
 // only ever applies to the walking direction, where the row index is uniform,
 // so the interior path has no per-lane boundary logic at all.
 //
-// All three kernels are persistent: a fixed grid of workgroups pulls tiles
-// from per-XCD atomic counters (home list first, then the other XCDs' lists),
-// so one captured launch sequence serves batches of any composition and each
-// XCD's L2 mostly sees its own column slices.
+// Each kernel runs one workgroup per tile and reads its tile from a host-built
+// table: widest kernels first (the dispatcher hands out workgroups in order,
+// which balances the uneven tap counts), with XCD-local column slices
+// interleaved so workgroup b, placed on XCD b mod 8, stays in that XCD's L2.
+// No atomics are needed to distribute work.
 #include <hip/hip_runtime.h>
 
 #include "dog_internal.h"
@@ -61,20 +62,6 @@ __device__ __forceinline__ const DOG_CONSTANT_AS T* cst(const T* p)
 }
 
 typedef const DOG_CONSTANT_AS float* cptr_t;
-
-// Last unit whose first_tile <= tile (units sorted by first_tile).
-__device__ __forceinline__ int find_unit(const DOG_CONSTANT_AS WorkUnit* u, int n, int tile)
-{
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (u[mid].first_tile <= tile)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo;
-}
 
 // Buffer resource over one plane: raw (unswizzled) dword loads with a scalar
 // row offset and a per-lane column offset; the hardware range check returns 0
@@ -179,53 +166,10 @@ __device__ __forceinline__ void blur_strip(__amdgpu_buffer_rsrc_t rs, int stride
         blur_chunks<S, R, false>(rs, stride4, n, (unsigned)c, base, nch, cw, acc);
 }
 
-// Pull the next tile id of one list for the whole workgroup.  The leading
-// barrier keeps thread 0's atomic in the same convergent region as the reads
-// that follow: without it the compiler may merge a thread-0-only block at the
-// end of the previous tile with this one across the loop back-edge, letting
-// the other lanes re-read a stale tile id.
-__device__ __forceinline__ int next_tile(uint32_t* ctr, int* s_tile)
+// This workgroup's tile.
+__device__ __forceinline__ Tile my_tile(const Tile* table)
 {
-    __syncthreads();
-    if (threadIdx.x == 0)
-        *s_tile = (int)atomicAdd(ctr, 1u);
-    __syncthreads();
-    const int t = __builtin_amdgcn_readfirstlane(*s_tile);
-    __syncthreads();
-    return t;
-}
-
-// Drain the home list (workgroup id mod 8), then the other lists, calling
-// body(unit, tile_within_unit) for each tile.  Every thread of the workgroup
-// calls body with the same arguments.
-template <class Body>
-__device__ __forceinline__ void drain_queues(const Queue* queue, uint32_t* ctr, int* s_tile,
-                                             Body&& body)
-{
-    const DOG_CONSTANT_AS Queue* q = cst(queue);
-    const int home = (int)(blockIdx.x % DOG_NXCD);
-    for (int s = 0; s < DOG_NXCD; ++s) {
-        const int x = (home + s) % DOG_NXCD;
-        const int total = q->total[x];
-        if (total == 0)
-            continue;
-        const DOG_CONSTANT_AS WorkUnit* units = cst(q->units) + q->off[x];
-        const int nu = q->n[x];
-        for (;;) {
-            const int tile = next_tile(ctr + x, s_tile);
-            if (tile < 0 || tile >= total)  // a counter read as negative also ends the list
-                break;
-            const WorkUnit u = units[find_unit(units, nu, tile)];
-            body(u, tile - u.first_tile);
-        }
-    }
-}
-
-__device__ __forceinline__ void clear_counters(uint32_t* c)
-{
-#pragma unroll
-    for (int i = 0; i < DOG_NXCD; ++i)
-        c[i] = 0u;
+    return cst(table)[blockIdx.x];
 }
 
 // Pass 1: T_p = column blur of the input frame, stored transposed.
@@ -233,19 +177,17 @@ __device__ __forceinline__ void clear_counters(uint32_t* c)
 template <int S, int R, int NW, int BI>
 __global__ void __launch_bounds__(64 * NW) k_pass1(LaunchArgs a)
 {
-    __shared__ int s_tile;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     constexpr int BAND = S * NW * BI;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        clear_counters(a.counters->c[2]);
-        a.cand->count = 0u;
-    }
-    drain_queues(a.queues + 0, a.counters->c[0], &s_tile, [&](const WorkUnit& u, int lt) {
-        const int cb = u.cb0 + lt / u.n_band;
-        const int band = lt % u.n_band;
-        const FrameDesc f = cst(a.frames)[u.frame];
-        const int p = u.plane;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        a.cand->count = 0u;  // read by the local-maximum kernel of this sequence
+    {
+        const Tile tl = my_tile(a.tiles1);
+        const int cb = tl.cb;
+        const int band = tl.band;
+        const FrameDesc f = cst(a.frames)[tl.frame];
+        const int p = tl.plane;
         const int r = cst(a.ladders)[f.ladder].r[p];
         const float* w = a.weights + cst(a.ladders)[f.ladder].woff[p];
         const int col = cb * 64 + lane;
@@ -273,7 +215,7 @@ __global__ void __launch_bounds__(64 * NW) k_pass1(LaunchArgs a)
                 }
             }
         }
-    });
+    }
 }
 
 // Pass 2: L_p = blur of T_p down its columns (along x of the frame); output in
@@ -281,17 +223,15 @@ __global__ void __launch_bounds__(64 * NW) k_pass1(LaunchArgs a)
 template <int S, int R, int NW, int BI>
 __global__ void __launch_bounds__(64 * NW) k_pass2(LaunchArgs a)
 {
-    __shared__ int s_tile;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     constexpr int BAND = S * NW * BI;
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        clear_counters(a.counters->c[0]);
-    drain_queues(a.queues + 1, a.counters->c[1], &s_tile, [&](const WorkUnit& u, int lt) {
-        const int cb = u.cb0 + lt / u.n_band;
-        const int band = lt % u.n_band;
-        const FrameDesc f = cst(a.frames)[u.frame];
-        const int p = u.plane;
+    {
+        const Tile tl = my_tile(a.tiles2);
+        const int cb = tl.cb;
+        const int band = tl.band;
+        const FrameDesc f = cst(a.frames)[tl.frame];
+        const int p = tl.plane;
         const int r = cst(a.ladders)[f.ladder].r[p];
         const float* w = a.weights + cst(a.ladders)[f.ladder].woff[p];
         const __amdgpu_buffer_rsrc_t rs = plane_rsrc(f.T + (long long)p * f.W * f.pitch,
@@ -312,7 +252,7 @@ __global__ void __launch_bounds__(64 * NW) k_pass2(LaunchArgs a)
                         dstp[(long long)(x0 + t) * f.pitch + col] = acc[t];
             }
         }
-    });
+    }
 }
 
 // Lanes i-1 and i+1 of a wave (-inf where the neighbour lane does not exist).
@@ -379,22 +319,20 @@ __device__ __forceinline__ void dog_rows(const float (&La)[BN + 2], const float 
 template <int BN, int NW>
 __global__ void __launch_bounds__(64 * NW) k_nms(LaunchArgs a)
 {
-    __shared__ int s_tile;
     __shared__ uint32_t s_n;
     __shared__ uint32_t s_base;
     __shared__ CandRec s_rec[DOG_LDS_RECS];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     CandRec* __restrict__ recs = reinterpret_cast<CandRec*>(a.cand + 1);
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        clear_counters(a.counters->c[1]);
     if (threadIdx.x == 0)
         s_n = 0u;
     __syncthreads();
-    drain_queues(a.queues + 2, a.counters->c[2], &s_tile, [&](const WorkUnit& u, int lt) {
-        const int cb = u.cb0 + lt / u.n_band;
-        const int band = lt % u.n_band;
-        const FrameDesc f = cst(a.frames)[u.frame];
+    {
+        const Tile tl = my_tile(a.tiles3);
+        const int cb = tl.cb;
+        const int band = tl.band;
+        const FrameDesc f = cst(a.frames)[tl.frame];
         const DOG_CONSTANT_AS LadderDesc* ld = cst(a.ladders) + f.ladder;
         const int k = ld->n_g - 1;
         const float thr = ld->thr;
@@ -474,25 +412,19 @@ __global__ void __launch_bounds__(64 * NW) k_nms(LaunchArgs a)
                 }
             }
         }
-        // flush this tile's records: one global atomic for the workgroup.
-        // s_n is reset between barriers (every thread has read it, none
-        // appends again before the next tile), and the body ends on a
-        // barrier so the copies finish before s_rec is reused.
+        // flush this tile's records with one global atomic for the workgroup
         __syncthreads();
         const uint32_t n = s_n < DOG_LDS_RECS ? s_n : DOG_LDS_RECS;
         if (threadIdx.x == 0)
             s_base = n ? atomicAdd(&a.cand->count, n) : 0u;
         __syncthreads();
         const uint32_t gbase = s_base;
-        if (threadIdx.x == 0)
-            s_n = 0u;
         for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
             const uint32_t g = gbase + i;
             if (g < a.cap)
                 recs[g] = s_rec[i];
         }
-        __syncthreads();
-    });
+    }
 }
 
 // dst[(p*H + y)*W + x] = src[(p*W + x)*pitch + y]: back to row-major planes.

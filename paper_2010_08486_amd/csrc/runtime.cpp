@@ -174,11 +174,13 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
     if (D0)
         *D0 = fd[0].Ddbg;
 
-    // ---- per-XCD work lists.  Each (frame, plane) unit's column blocks are
-    // cut into DOG_NXCD contiguous slices; slice s goes to XCD (s + frame) %
-    // DOG_NXCD so one XCD's L2 holds one band of columns of every plane (and
-    // small frames spread over the XCDs).  Within a list, units are ordered
-    // widest kernel first so the persistent grid drains evenly.
+    // ---- tile tables.  Each (frame, plane) unit's column blocks are cut into
+    // DOG_NXCD contiguous slices and slice s goes to XCD (s + frame) %
+    // DOG_NXCD, so one XCD's L2 holds one band of columns of every plane
+    // (small frames spread over the XCDs).  Per XCD, tiles are ordered widest
+    // kernel first; the launch table interleaves the XCD lists so workgroup b
+    // (dispatched to XCD b % 8) gets a tile of list b % 8, and an exhausted
+    // list's slot is filled from the longest remaining list.
     const int band = V.band();
     struct Raw {
         int frame, plane, n_cb, n_band, radius;
@@ -200,80 +202,75 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
     };
     std::stable_sort(r1.begin(), r1.end(), by_cost);
     std::stable_sort(r2.begin(), r2.end(), by_cost);
-    struct Lists {
-        std::vector<WorkUnit> units;
-        Queue q;
-    };
-    auto slice = [](const std::vector<Raw>& raw, Lists* L) -> bool {
-        std::vector<WorkUnit> per[DOG_NXCD];
-        long long tot[DOG_NXCD] = {0};
+    auto build_table = [](const std::vector<Raw>& raw, std::vector<Tile>* out) {
+        std::vector<Tile> per[DOG_NXCD];
         for (const Raw& r : raw) {
             for (int s = 0; s < DOG_NXCD; ++s) {
                 const int c0 = (int)((long long)s * r.n_cb / DOG_NXCD);
                 const int c1 = (int)((long long)(s + 1) * r.n_cb / DOG_NXCD);
-                if (c1 <= c0)
-                    continue;
                 const int x = (s + r.frame) % DOG_NXCD;
-                WorkUnit w{};
-                w.frame = r.frame;
-                w.plane = r.plane;
-                w.cb0 = c0;
-                w.n_cb = c1 - c0;
-                w.n_band = r.n_band;
-                w.first_tile = (int)tot[x];
-                tot[x] += (long long)w.n_cb * w.n_band;
-                per[x].push_back(w);
+                for (int cb = c0; cb < c1; ++cb)
+                    for (int b = 0; b < r.n_band; ++b) {
+                        Tile t;
+                        t.frame = (uint16_t)r.frame;
+                        t.plane = (uint8_t)r.plane;
+                        t.pad_ = 0;
+                        t.cb = (uint16_t)cb;
+                        t.band = (uint16_t)b;
+                        per[x].push_back(t);
+                    }
             }
         }
-        L->units.clear();
-        std::memset(&L->q, 0, sizeof(L->q));
-        for (int x = 0; x < DOG_NXCD; ++x) {
-            if (tot[x] > INT32_MAX / 2)
-                return false;
-            L->q.off[x] = (int)L->units.size();
-            L->q.n[x] = (int)per[x].size();
-            L->q.total[x] = (int)tot[x];
-            L->units.insert(L->units.end(), per[x].begin(), per[x].end());
+        size_t total = 0, pos[DOG_NXCD] = {0};
+        for (int x = 0; x < DOG_NXCD; ++x)
+            total += per[x].size();
+        out->clear();
+        out->reserve(total);
+        while (out->size() < total) {
+            for (int x = 0; x < DOG_NXCD && out->size() < total; ++x) {
+                int src = x;
+                if (pos[x] >= per[x].size()) {
+                    size_t best = 0;
+                    for (int y = 0; y < DOG_NXCD; ++y)
+                        if (per[y].size() - pos[y] > best) {
+                            best = per[y].size() - pos[y];
+                            src = y;
+                        }
+                }
+                out->push_back(per[src][pos[src]++]);
+            }
         }
-        return true;
     };
-    Lists l1, l2, l3;
-    if (!slice(r1, &l1) || !slice(r2, &l2) || !slice(r3, &l3)) {
+    std::vector<Tile> tb1, tb2, tb3;
+    build_table(r1, &tb1);
+    build_table(r2, &tb2);
+    build_table(r3, &tb3);
+    const long long t1 = (long long)tb1.size(), t2 = (long long)tb2.size(), t3 = (long long)tb3.size();
+    if (t1 > INT32_MAX / 2 || t2 > INT32_MAX / 2 || t3 > INT32_MAX / 2 || n > 65535 ||
+        (long long)frames[0].W > 65535 * 64LL) {
         set_error("batch too large for one launch");
         return DOG_EINVAL;
-    }
-    long long t1 = 0, t2 = 0, t3 = 0;
-    for (int x = 0; x < DOG_NXCD; ++x) {
-        t1 += l1.q.total[x];
-        t2 += l2.q.total[x];
-        t3 += l3.q.total[x];
     }
 
     const size_t o_frames = 0;
     const size_t o_ladder = align_up(o_frames + sizeof(FrameDesc) * n, 256);
     const size_t o_weights = align_up(o_ladder + sizeof(LadderDesc), 256);
-    const size_t o_queues = align_up(o_weights + sizeof(float) * P.weights.size(), 256);
-    const size_t o_u1 = align_up(o_queues + sizeof(Queue) * 3, 256);
-    const size_t o_u2 = align_up(o_u1 + sizeof(WorkUnit) * l1.units.size(), 256);
-    const size_t o_u3 = align_up(o_u2 + sizeof(WorkUnit) * l2.units.size(), 256);
-    const size_t tbytes = align_up(o_u3 + sizeof(WorkUnit) * l3.units.size(), 256);
+    const size_t o_t1 = align_up(o_weights + sizeof(float) * P.weights.size(), 256);
+    const size_t o_t2 = align_up(o_t1 + sizeof(Tile) * tb1.size(), 256);
+    const size_t o_t3 = align_up(o_t2 + sizeof(Tile) * tb2.size(), 256);
+    const size_t tbytes = align_up(o_t3 + sizeof(Tile) * tb3.size(), 256);
     if ((rc = ctx_alloc(c, &c->tables, tbytes, "launch tables")) != DOG_OK)
         return rc;
     if ((rc = ctx_pin(&c->h_tables, tbytes)) != DOG_OK)
         return rc;
     char* dt = static_cast<char*>(c->tables.p);
-    l1.q.units = reinterpret_cast<const WorkUnit*>(dt + o_u1);
-    l2.q.units = reinterpret_cast<const WorkUnit*>(dt + o_u2);
-    l3.q.units = reinterpret_cast<const WorkUnit*>(dt + o_u3);
-    const Queue qs[3] = {l1.q, l2.q, l3.q};
     char* h = static_cast<char*>(c->h_tables.p);
     std::memcpy(h + o_frames, fd.data(), sizeof(FrameDesc) * n);
     std::memcpy(h + o_ladder, &P.desc, sizeof(LadderDesc));
     std::memcpy(h + o_weights, P.weights.data(), sizeof(float) * P.weights.size());
-    std::memcpy(h + o_queues, qs, sizeof(qs));
-    std::memcpy(h + o_u1, l1.units.data(), sizeof(WorkUnit) * l1.units.size());
-    std::memcpy(h + o_u2, l2.units.data(), sizeof(WorkUnit) * l2.units.size());
-    std::memcpy(h + o_u3, l3.units.data(), sizeof(WorkUnit) * l3.units.size());
+    std::memcpy(h + o_t1, tb1.data(), sizeof(Tile) * tb1.size());
+    std::memcpy(h + o_t2, tb2.data(), sizeof(Tile) * tb2.size());
+    std::memcpy(h + o_t3, tb3.data(), sizeof(Tile) * tb3.size());
     DOG_HIP(hipMemcpyAsync(c->tables.p, h, tbytes, hipMemcpyHostToDevice, s));
 
     // ---- candidate buffer
@@ -289,26 +286,21 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
     a.frames = reinterpret_cast<const FrameDesc*>(dt + o_frames);
     a.ladders = reinterpret_cast<const LadderDesc*>(dt + o_ladder);
     a.weights = reinterpret_cast<const float*>(dt + o_weights);
-    a.queues = reinterpret_cast<const Queue*>(dt + o_queues);
-    a.counters = static_cast<Counters*>(c->counters.p);
+    a.tiles1 = reinterpret_cast<const Tile*>(dt + o_t1);
+    a.tiles2 = reinterpret_cast<const Tile*>(dt + o_t2);
+    a.tiles3 = reinterpret_cast<const Tile*>(dt + o_t3);
     a.cand = static_cast<CandHeader*>(c->cand.p);
     a.cap = c->cap;
+    a.n1 = (int)t1;
+    a.n2 = (int)t2;
+    a.n3 = (int)t3;
 
-    // persistent grids: resident capacity, a multiple of DOG_NXCD, no more
-    // workgroups than tiles (rounded up to DOG_NXCD)
-    auto grid = [&](int i, long long tiles) {
-        long long g = c->grid_override > 0 ? c->grid_override : (long long)c->occ[i] * c->n_cu;
-        const long long t8 = (tiles + DOG_NXCD - 1) / DOG_NXCD * DOG_NXCD;
-        g = std::min(g, t8);
-        g = g / DOG_NXCD * DOG_NXCD;
-        return (int)std::max<long long>(DOG_NXCD, g);
-    };
     if (c->profiling) {
         for (int i = 0; i < 4; ++i)
             if (!c->ev[i])
                 DOG_HIP(hipEventCreate(&c->ev[i]));
     }
-    DOG_HIP(dogk_launch_sequence(c->variant, &a, grid(0, t1), grid(1, t2), grid(2, t3), s,
+    DOG_HIP(dogk_launch_sequence(c->variant, &a, (int)t1, (int)t2, (int)t3, s,
                                  c->profiling ? c->ev : nullptr));
 
     // ---- readback: header + a guess of the records in one copy
@@ -339,9 +331,8 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
             return rc;
         a.cand = static_cast<CandHeader*>(c->cand.p);
         a.cap = c->cap;
-        DOG_HIP(dogk_fill_u32(a.counters->c[2], DOG_NXCD, 0u, s));
         DOG_HIP(dogk_fill_u32(&a.cand->count, 1, 0u, s));
-        DOG_HIP(dogk_launch_nms(c->variant, &a, grid(2, t3), s));
+        DOG_HIP(dogk_launch_nms(c->variant, &a, (int)t3, s));
         DOG_HIP(hipMemcpyAsync(c->h_cand.p, c->cand.p, sizeof(CandHeader) + kRecBytes * count,
                                hipMemcpyDeviceToHost, s));
         DOG_HIP(hipStreamSynchronize(s));

@@ -93,14 +93,12 @@ struct dog_context {
     int n_cu = 0;
     int variant = 0;               // active kernel variant
     int variant_auto = 0;          // autotuned choice
-    int grid_override = 0;
     int occ[3] = {0, 0, 0};        // workgroups per CU of each kernel (active variant)
 
     dog::DevBuf planes;            // T, L (and debug D) planes of all frames
     dog::DevBuf input;             // device copies of host frames
     dog::DevBuf tables;            // frames, ladder, weights, units
     dog::DevBuf cand;              // CandHeader + records
-    dog::DevBuf counters;          // dog::Counters
     uint32_t cap = 0;              // record capacity of `cand`
 
     dog::PinBuf h_tables;          // staging of the launch tables

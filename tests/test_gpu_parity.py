@@ -150,19 +150,6 @@ def test_all_variants_bitwise_identical(dog, ctx, torch_mod):
         ctx.set_variant(-1)
 
 
-def test_grid_size_does_not_change_results(dog, ctx, torch_mod):
-    img = synth.camera_frame(seed=8, H=300, W=260, n_blobs=50)
-    t = _dev(torch_mod, img)
-    prm = dog.Params(**CAMERA)
-    ref = ctx.debug_candidates(t, prm)
-    try:
-        for g in (1, 3, 17):
-            ctx.set_grid(g)
-            assert ctx.debug_candidates(t, prm).tobytes() == ref.tobytes()
-    finally:
-        ctx.set_grid(0)
-
-
 def test_batch_equals_single_frames(dog, ctx, torch_mod):
     shapes = [(256, 256), (128, 512), (300, 200), (64, 64), (512, 256)]
     frames = [synth.camera_frame(seed=50 + i, H=h, W=w, n_blobs=h * w // 2000 + 1)
