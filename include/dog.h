@@ -187,12 +187,21 @@ int dog_num_variants(void);
 int dog_variant_info(int variant, int32_t* S, int32_t* waves, int32_t* strips, int32_t* nms_rows);
 int dog_set_variant(dog_context* ctx, int variant);
 
+/* Launch mode: on (default) = the launch sequence of a table layout (frame
+ * table upload, the three kernels, candidate readback) is captured once into
+ * a hipGraph and replayed while frame shapes, parameters and buffers stay the
+ * same; off = the same operations are issued one by one on every call.
+ * Results are identical in both modes. */
+int dog_set_graph_mode(dog_context* ctx, int32_t on);
+
 /* Per-kernel timing: when on, every launch sequence of the context records
  * HIP events around each of its three kernels (pass 1, pass 2, local
  * maxima) on the stream they run on; dog_kernel_times returns the summed
  * milliseconds of each kernel (ms_out[3]) and the number of sequences since
  * profiling was last switched on.  Timing adds three event records per
- * sequence and is off by default. */
+ * sequence and is off by default; while it is on the sequence is issued
+ * directly rather than replayed as a graph (events inside a graph cannot be
+ * timed), with the same kernels and arguments. */
 int dog_set_profiling(dog_context* ctx, int32_t on);
 int dog_kernel_times(dog_context* ctx, double* ms_out, int64_t* launches_out);
 

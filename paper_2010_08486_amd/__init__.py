@@ -111,6 +111,7 @@ def lib() -> ctypes.CDLL:
         "dog_variant_info": (ctypes.c_int, [ctypes.c_int] + [ctypes.POINTER(i32)] * 4),
         "dog_set_variant": (ctypes.c_int, [vp, ctypes.c_int]),
         "dog_set_profiling": (ctypes.c_int, [vp, i32]),
+        "dog_set_graph_mode": (ctypes.c_int, [vp, i32]),
         "dog_kernel_times": (ctypes.c_int, [vp, ctypes.POINTER(dbl), pi64]),
     }
     for name, (res, args) in sig.items():
@@ -218,6 +219,9 @@ class Context:
 
     def set_variant(self, v: int) -> None:
         _check(lib().dog_set_variant(self._h, v))
+
+    def set_graph_mode(self, on: bool) -> None:
+        _check(lib().dog_set_graph_mode(self._h, 1 if on else 0))
 
     def set_profiling(self, on: bool) -> None:
         _check(lib().dog_set_profiling(self._h, 1 if on else 0))

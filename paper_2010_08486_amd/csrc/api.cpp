@@ -16,7 +16,7 @@ using namespace dog;
 namespace {
 
 constexpr int kMaxSide = 32768;
-constexpr int kDefaultVariant = 5;  // S = 12, R = 4: fastest on 1024x1024 frames
+constexpr int kDefaultVariant = 0;  // S = 12, R = 4: fastest on 1024x1024 frames
 
 int check_image(const void* p, int64_t h, int64_t w, int64_t stride)
 {
@@ -84,9 +84,12 @@ void free_context(dog_context* c)
     for (PinBuf* b : {&c->h_tables, &c->h_cand, &c->h_input})
         if (b->p)
             (void)hipHostFree(b->p);
+    drop_graph(c);
     for (hipEvent_t& e : c->ev)
         if (e)
             (void)hipEventDestroy(e);
+    if (c->ev_in)
+        (void)hipEventDestroy(c->ev_in);
     if (c->stream)
         (void)hipStreamDestroy(c->stream);
     delete c;
@@ -187,10 +190,24 @@ int dog_set_profiling(dog_context* ctx, int32_t on)
         set_error("ctx is NULL");
         return DOG_EINVAL;
     }
+    if (ctx->profiling != (on != 0))
+        drop_graph(ctx);
     ctx->profiling = on != 0;
     for (double& m : ctx->kernel_ms)
         m = 0.0;
     ctx->kernel_launches = 0;
+    return DOG_OK;
+}
+
+int dog_set_graph_mode(dog_context* ctx, int32_t on)
+{
+    if (!ctx) {
+        set_error("ctx is NULL");
+        return DOG_EINVAL;
+    }
+    if (ctx->use_graphs != (on != 0))
+        drop_graph(ctx);
+    ctx->use_graphs = on != 0;
     return DOG_OK;
 }
 

@@ -310,13 +310,75 @@ __device__ __forceinline__ void dog_rows(const float (&La)[BN + 2], const float 
 
 #define DOG_LDS_RECS 512
 
+// Workgroup-local candidate buffer: survivors are appended in LDS and
+// flushed with one global atomic per tile; on LDS overflow a record goes
+// straight to the global list.
+struct CandSink {
+    uint32_t* s_n;
+    CandRec* s_rec;
+    CandHeader* cand;
+    CandRec* recs;
+    uint32_t cap;
+};
+
+// Test one band row of scale i for every lane and append the survivors:
+// a voxel is kept iff it equals the maximum of its 3x3x3 neighbourhood and
+// exceeds the threshold.  Also writes the debug DoG plane when requested.
+__device__ __forceinline__ void emit_row(const CandSink& snk, const FrameDesc& f, int lane, int y,
+                                         int x, int i, bool inside, float d, float m, float thr,
+                                         long long plane_sz)
+{
+    const bool flag = inside && d == m && d > thr;
+    if (f.Ddbg != nullptr && inside)
+        f.Ddbg[(long long)i * plane_sz + (long long)x * f.pitch + y] = d;
+    const unsigned long long bal = __ballot(flag);
+    if (bal != 0ull) {
+        unsigned base = 0;
+        if (lane == 0)
+            base = atomicAdd(snk.s_n, (unsigned)__popcll(bal));
+        base = __shfl(base, 0);
+        if (flag) {
+            CandRec rec;
+            rec.frame = f.frame_id;
+            rec.y = y;
+            rec.x = x;
+            rec.scale = i;
+            rec.response = d;
+            const unsigned idx = base + (unsigned)__popcll(bal & ((1ull << lane) - 1ull));
+            if (idx < DOG_LDS_RECS) {
+                snk.s_rec[idx] = rec;
+            } else {
+                const unsigned g = atomicAdd(&snk.cand->count, 1u);
+                if (g < snk.cap)
+                    snk.recs[g] = rec;
+            }
+        }
+    }
+}
+
+// Flush the workgroup's LDS records with one global atomic.
+__device__ __forceinline__ void flush_sink(const CandSink& snk, uint32_t* s_base)
+{
+    __syncthreads();
+    const uint32_t n = *snk.s_n < DOG_LDS_RECS ? *snk.s_n : DOG_LDS_RECS;
+    if (threadIdx.x == 0)
+        *s_base = n ? atomicAdd(&snk.cand->count, n) : 0u;
+    __syncthreads();
+    const uint32_t gbase = *s_base;
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const uint32_t g = gbase + i;
+        if (g < snk.cap)
+            snk.recs[g] = snk.s_rec[i];
+    }
+}
+
 // Local maxima of the DoG cube with threshold, compacted into records.
 // Tile = 62 output columns (y; lanes 1..62, lanes 0 and 63 are the halo)
-// x (BN*NW) rows (x) of one frame; every wave walks all scales, with the
-// loads of plane i+3 in flight while plane i+1's DoG is formed.  Survivors
-// are appended to a workgroup buffer in LDS and flushed with one global
-// atomic per tile.
-template <int BN, int NW>
+// x (BN*NW) rows (x) of one frame; every wave walks all scales.
+// KMAX > 0: ladders of at most KMAX Gaussian planes; all planes' rows are
+// loaded up front, so a wave waits for memory once.  KMAX == 0: any ladder;
+// plane i+3 is loaded while plane i+1's DoG is formed.
+template <int BN, int NW, int KMAX>
 __global__ void __launch_bounds__(64 * NW) k_nms(LaunchArgs a)
 {
     __shared__ uint32_t s_n;
@@ -324,34 +386,66 @@ __global__ void __launch_bounds__(64 * NW) k_nms(LaunchArgs a)
     __shared__ CandRec s_rec[DOG_LDS_RECS];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    CandRec* __restrict__ recs = reinterpret_cast<CandRec*>(a.cand + 1);
     if (threadIdx.x == 0)
         s_n = 0u;
     __syncthreads();
-    {
-        const Tile tl = my_tile(a.tiles3);
-        const int cb = tl.cb;
-        const int band = tl.band;
-        const FrameDesc f = cst(a.frames)[tl.frame];
-        const DOG_CONSTANT_AS LadderDesc* ld = cst(a.ladders) + f.ladder;
-        const int k = ld->n_g - 1;
-        const float thr = ld->thr;
-        const int y = cb * DOG_NMS_COLS - 1 + lane;
-        const bool ycol = y >= 0 && y < f.H;
-        const bool yout = ycol && lane >= 1 && lane <= DOG_NMS_COLS;
-        const unsigned voff = (unsigned)(ycol ? y : 0) * 4u;
-        const int x0 = band * (BN * NW) + wv * BN;
-        if (x0 < f.W) {  // wave-uniform
-            const long long plane_sz = (long long)f.W * f.pitch;
+    const CandSink snk{&s_n, s_rec, a.cand, reinterpret_cast<CandRec*>(a.cand + 1), a.cap};
+    const Tile tl = my_tile(a.tiles3);
+    const FrameDesc f = cst(a.frames)[tl.frame];
+    const DOG_CONSTANT_AS LadderDesc* ld = cst(a.ladders) + f.ladder;
+    const int k = ld->n_g - 1;
+    const float thr = ld->thr;
+    const int y = tl.cb * DOG_NMS_COLS - 1 + lane;
+    const bool ycol = y >= 0 && y < f.H;
+    const bool yout = ycol && lane >= 1 && lane <= DOG_NMS_COLS;
+    const unsigned voff = (unsigned)(ycol ? y : 0) * 4u;
+    const int x0 = tl.band * (BN * NW) + wv * BN;
+    const long long plane_sz = (long long)f.W * f.pitch;
+    if (x0 < f.W) {  // wave-uniform
+        float s3m[BN], s3c[BN], s3n[BN], dc[BN], dn[BN];
+#pragma unroll
+        for (int j = 0; j < BN; ++j)
+            s3m[j] = -INFINITY;
+        if constexpr (KMAX > 0) {
+            float Lr[KMAX][BN + 2];
+#pragma unroll
+            for (int p = 0; p < KMAX; ++p)
+                if (p <= k)
+                    load_plane_rows<BN>(Lr[p], f, p, x0, voff);
+            dog_rows<BN>(Lr[0], Lr[1], ld->sigma[0], x0, f.W, ycol, s3c, dc);
+#pragma unroll
+            for (int i = 0; i + 1 < KMAX; ++i) {
+                if (i < k) {
+                    if (i + 1 < k) {
+                        dog_rows<BN>(Lr[i + 1], Lr[(i + 2) < KMAX ? i + 2 : i + 1],
+                                     ld->sigma[i + 1], x0, f.W, ycol, s3n, dn);
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < BN; ++j) {
+                            s3n[j] = -INFINITY;
+                            dn[j] = -INFINITY;
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < BN; ++j) {
+                        const int x = x0 + j;
+                        emit_row(snk, f, lane, y, x, i, yout && x < f.W, dc[j],
+                                 fmaxf(s3m[j], fmaxf(s3c[j], s3n[j])), thr, plane_sz);
+                    }
+#pragma unroll
+                    for (int j = 0; j < BN; ++j) {
+                        s3m[j] = s3c[j];
+                        s3c[j] = s3n[j];
+                        dc[j] = dn[j];
+                    }
+                }
+            }
+        } else {
             float La[BN + 2], Lb[BN + 2], Lc[BN + 2], Ld[BN + 2];
             load_plane_rows<BN>(La, f, 0, x0, voff);
             load_plane_rows<BN>(Lb, f, 1, x0, voff);
             if (k >= 2)
                 load_plane_rows<BN>(Lc, f, 2, x0, voff);
-            float s3m[BN], s3c[BN], s3n[BN], dc[BN], dn[BN];
-#pragma unroll
-            for (int j = 0; j < BN; ++j)
-                s3m[j] = -INFINITY;
             dog_rows<BN>(La, Lb, ld->sigma[0], x0, f.W, ycol, s3c, dc);
             for (int i = 0; i < k; ++i) {
                 // Lb = L_{i+1}, Lc = L_{i+2} (when i + 2 <= k)
@@ -374,35 +468,8 @@ __global__ void __launch_bounds__(64 * NW) k_nms(LaunchArgs a)
 #pragma unroll
                 for (int j = 0; j < BN; ++j) {
                     const int x = x0 + j;
-                    const float m = fmaxf(s3m[j], fmaxf(s3c[j], s3n[j]));
-                    const bool inside = yout && x < f.W;
-                    const bool flag = inside && dc[j] == m && dc[j] > thr;
-                    if (f.Ddbg != nullptr && inside)
-                        f.Ddbg[(long long)i * plane_sz + (long long)x * f.pitch + y] = dc[j];
-                    const unsigned long long bal = __ballot(flag);
-                    if (bal != 0ull) {
-                        unsigned base = 0;
-                        if (lane == 0)
-                            base = atomicAdd(&s_n, (unsigned)__popcll(bal));
-                        base = __shfl(base, 0);
-                        if (flag) {
-                            CandRec rec;
-                            rec.frame = f.frame_id;
-                            rec.y = y;
-                            rec.x = x;
-                            rec.scale = i;
-                            rec.response = dc[j];
-                            const unsigned idx =
-                                base + (unsigned)__popcll(bal & ((1ull << lane) - 1ull));
-                            if (idx < DOG_LDS_RECS) {
-                                s_rec[idx] = rec;
-                            } else {
-                                const unsigned g = atomicAdd(&a.cand->count, 1u);
-                                if (g < a.cap)
-                                    recs[g] = rec;
-                            }
-                        }
-                    }
+                    emit_row(snk, f, lane, y, x, i, yout && x < f.W, dc[j],
+                             fmaxf(s3m[j], fmaxf(s3c[j], s3n[j])), thr, plane_sz);
                 }
 #pragma unroll
                 for (int j = 0; j < BN; ++j) {
@@ -412,19 +479,8 @@ __global__ void __launch_bounds__(64 * NW) k_nms(LaunchArgs a)
                 }
             }
         }
-        // flush this tile's records with one global atomic for the workgroup
-        __syncthreads();
-        const uint32_t n = s_n < DOG_LDS_RECS ? s_n : DOG_LDS_RECS;
-        if (threadIdx.x == 0)
-            s_base = n ? atomicAdd(&a.cand->count, n) : 0u;
-        __syncthreads();
-        const uint32_t gbase = s_base;
-        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-            const uint32_t g = gbase + i;
-            if (g < a.cap)
-                recs[g] = s_rec[i];
-        }
     }
+    flush_sink(snk, &s_base);
 }
 
 // dst[(p*H + y)*W + x] = src[(p*W + x)*pitch + y]: back to row-major planes.
@@ -450,10 +506,15 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, int n, uint32_t v)
 }
 
 // ---------------------------------------------------------------- launchers
+// Local-maximum kernels that hold every plane in registers handle ladders of
+// up to DOG_NMS_KMAX Gaussian planes; longer ladders use the rolling kernel.
+#define DOG_NMS_KMAX 10
+
 struct KernelSet {
     const void* pass1;
     const void* pass2;
-    const void* nms;
+    const void* nms;       // any ladder
+    const void* nms_k;     // ladders of at most DOG_NMS_KMAX Gaussian planes
     int S, R, NW, BI, BN, NWN;
 };
 
@@ -463,7 +524,8 @@ static KernelSet make_set()
     KernelSet k;
     k.pass1 = reinterpret_cast<const void*>(&k_pass1<S, R, NW, BI>);
     k.pass2 = reinterpret_cast<const void*>(&k_pass2<S, R, NW, BI>);
-    k.nms = reinterpret_cast<const void*>(&k_nms<BN, NWN>);
+    k.nms = reinterpret_cast<const void*>(&k_nms<BN, NWN, 0>);
+    k.nms_k = reinterpret_cast<const void*>(&k_nms<BN, NWN, DOG_NMS_KMAX>);
     k.S = S;
     k.R = R;
     k.NW = NW;
@@ -477,14 +539,14 @@ static KernelSet make_set()
 // waves per workgroup, strips per wave) for the blur passes and (rows per
 // wave, waves) for the local-maximum kernel.
 static const KernelSet kSets[] = {
-    make_set<8, 6, 4, 1, 8, 4>(),
-    make_set<8, 4, 4, 1, 8, 4>(),
-    make_set<8, 8, 4, 1, 8, 4>(),
-    make_set<8, 6, 4, 2, 8, 4>(),
-    make_set<16, 4, 4, 1, 8, 4>(),
+    make_set<12, 4, 4, 1, 4, 4>(),
     make_set<12, 4, 4, 1, 8, 4>(),
-    make_set<4, 10, 4, 1, 8, 4>(),
-    make_set<8, 6, 4, 1, 16, 4>(),
+    make_set<12, 6, 4, 1, 4, 4>(),
+    make_set<16, 4, 4, 1, 4, 4>(),
+    make_set<16, 3, 4, 1, 4, 4>(),
+    make_set<8, 8, 4, 1, 4, 4>(),
+    make_set<12, 4, 2, 1, 4, 4>(),
+    make_set<20, 3, 4, 1, 4, 4>(),
 };
 
 }  // namespace dog
@@ -510,9 +572,10 @@ int dogk_variant_ring(int v) { return dog::kSets[v].R; }
 // If ev is non-NULL, events ev[0..3] are recorded before, between and after
 // the kernels.  Returns the first launch error.
 hipError_t dogk_launch_sequence(int variant, const dog::LaunchArgs* args, int grid1, int grid2,
-                                int grid3, hipStream_t stream, hipEvent_t* ev)
+                                int grid3, int max_gauss, hipStream_t stream, hipEvent_t* ev)
 {
     const dog::KernelSet& k = dog::kSets[variant];
+    const void* nms = max_gauss <= DOG_NMS_KMAX ? k.nms_k : k.nms;
     void* params[] = {const_cast<dog::LaunchArgs*>(args)};
     hipError_t e = hipSuccess;
     if (ev)
@@ -526,17 +589,19 @@ hipError_t dogk_launch_sequence(int variant, const dog::LaunchArgs* args, int gr
     if (e == hipSuccess && ev)
         e = hipEventRecord(ev[2], stream);
     if (e == hipSuccess)
-        e = hipLaunchKernel(k.nms, dim3(grid3), dim3(64 * k.NWN), params, 0, stream);
+        e = hipLaunchKernel(nms, dim3(grid3), dim3(64 * k.NWN), params, 0, stream);
     if (e == hipSuccess && ev)
         e = hipEventRecord(ev[3], stream);
     return e;
 }
 
-hipError_t dogk_launch_nms(int variant, const dog::LaunchArgs* args, int grid3, hipStream_t stream)
+hipError_t dogk_launch_nms(int variant, const dog::LaunchArgs* args, int grid3, int max_gauss,
+                           hipStream_t stream)
 {
     const dog::KernelSet& k = dog::kSets[variant];
     void* params[] = {const_cast<dog::LaunchArgs*>(args)};
-    return hipLaunchKernel(k.nms, dim3(grid3), dim3(64 * k.NWN), params, 0, stream);
+    return hipLaunchKernel(max_gauss <= DOG_NMS_KMAX ? k.nms_k : k.nms, dim3(grid3),
+                           dim3(64 * k.NWN), params, 0, stream);
 }
 
 // Resident workgroups per CU of each kernel of a variant.
@@ -549,7 +614,7 @@ hipError_t dogk_occupancy(int variant, int* wg1, int* wg2, int* wg3)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(wg2, k.pass2, 64 * k.NW, 0);
     if (e != hipSuccess)
         return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(wg3, k.nms, 64 * k.NWN, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(wg3, k.nms_k, 64 * k.NWN, 0);
 }
 
 hipError_t dogk_untranspose(const float* src, float* dst, int n_planes, int H, int W,

@@ -92,6 +92,7 @@ int ctx_plan(dog_context* c, const dog_params* prm, const Plan** out)
         }
         c->plan = std::move(P);
         c->have_plan = true;
+        c->plan_gen += 1;
     }
     *out = &c->plan;
     return DOG_OK;
@@ -107,6 +108,8 @@ int ctx_set_variant(dog_context* c, int v)
     }
     int o[3];
     DOG_HIP(dogk_occupancy(v, &o[0], &o[1], &o[2]));
+    if (v != c->variant)
+        drop_graph(c);
     c->variant = v;
     for (int i = 0; i < 3; ++i)
         c->occ[i] = std::max(1, o[i]);
@@ -123,6 +126,63 @@ static Variant variant_geometry(int v)
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 static constexpr size_t kRecBytes = sizeof(CandRec);
+
+// The launch sequence of the current tables on stream st: upload of the
+// frame table from pinned staging, the three kernels (with timing events when
+// profiling), and the readback of the candidate header and the first
+// `guess` records into pinned memory.  Captured once into a graph, or issued
+// directly when graphs are off.
+static hipError_t enqueue_sequence(dog_context* c, hipStream_t st)
+{
+    const LaunchArgs& a = c->args;
+    hipError_t e = hipMemcpyAsync(const_cast<FrameDesc*>(a.frames), c->h_tables.p, c->frames_bytes,
+                                  hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = dogk_launch_sequence(c->variant, &a, a.n1, a.n2, a.n3, c->n_gauss, st,
+                                 c->profiling ? c->ev : nullptr);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->h_cand.p, c->cand.p, sizeof(CandHeader) + kRecBytes * c->guess,
+                           hipMemcpyDeviceToHost, st);
+    return e;
+}
+
+void drop_graph(dog_context* c)
+{
+    if (c->graph_exec)
+        (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph)
+        (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+    c->graph_key.clear();
+    c->tables_ready = false;
+}
+
+// Everything that fixes the launch tables, the buffers they point into and
+// the captured sequence, apart from the frames' pixel pointers.
+static std::vector<long long> launch_key(const dog_context* c, const std::vector<FrameIn>& frames,
+                                         bool dbg_D)
+{
+    std::vector<long long> k;
+    k.reserve(16 + 3 * frames.size());
+    k.push_back((long long)frames.size());
+    k.push_back(c->variant);
+    k.push_back((long long)c->plan_gen);
+    k.push_back(dbg_D ? 1 : 0);
+    k.push_back(c->profiling ? 1 : 0);
+    k.push_back((long long)(uintptr_t)c->planes.p);
+    k.push_back((long long)(uintptr_t)c->tables.p);
+    k.push_back((long long)(uintptr_t)c->cand.p);
+    k.push_back((long long)(uintptr_t)c->h_tables.p);
+    k.push_back((long long)(uintptr_t)c->h_cand.p);
+    k.push_back((long long)c->cap);
+    for (const FrameIn& f : frames) {
+        k.push_back(f.H);
+        k.push_back(f.W);
+        k.push_back(f.stride);
+    }
+    return k;
+}
 
 int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames, hipStream_t s,
                std::vector<std::vector<dog_blob>>* out, bool dbg_D, long long* pitch0,
@@ -148,9 +208,17 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
     int rc = ctx_alloc(c, &c->planes, total * sizeof(float), "scale-space planes");
     if (rc != DOG_OK)
         return rc;
+    if (c->cap == 0) {
+        if ((rc = ctx_alloc(c, &c->cand, sizeof(CandHeader) + kRecBytes * 65536, "candidates")) !=
+            DOG_OK)
+            return rc;
+        c->cap = 65536;
+    }
+    if ((rc = ctx_pin(&c->h_cand, sizeof(CandHeader) + kRecBytes * (size_t)c->cap)) != DOG_OK)
+        return rc;
     float* planes = static_cast<float*>(c->planes.p);
 
-    // ---- launch tables
+    // ---- frame table (the only part that changes between replays)
     std::vector<FrameDesc> fd(n);
     for (int f = 0; f < n; ++f) {
         const size_t plane = (size_t)frames[f].W * (size_t)pitch[f];
@@ -173,143 +241,176 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
         *L0 = fd[0].L;
     if (D0)
         *D0 = fd[0].Ddbg;
+    const size_t frames_bytes = sizeof(FrameDesc) * n;
 
-    // ---- tile tables.  Each (frame, plane) unit's column blocks are cut into
-    // DOG_NXCD contiguous slices and slice s goes to XCD (s + frame) %
-    // DOG_NXCD, so one XCD's L2 holds one band of columns of every plane
-    // (small frames spread over the XCDs).  Per XCD, tiles are ordered widest
-    // kernel first; the launch table interleaves the XCD lists so workgroup b
-    // (dispatched to XCD b % 8) gets a tile of list b % 8, and an exhausted
-    // list's slot is filled from the longest remaining list.
-    const int band = V.band();
-    struct Raw {
-        int frame, plane, n_cb, n_band, radius;
-    };
-    std::vector<Raw> r1, r2, r3;
-    for (int f = 0; f < n; ++f) {
-        const int H = frames[f].H, W = frames[f].W;
-        for (int p = 0; p < n_g; ++p) {
-            r1.push_back({f, p, (W + 63) / 64, (H + band - 1) / band, P.r[p]});
-            r2.push_back({f, p, (H + 63) / 64, (W + band - 1) / band, P.r[p]});
-        }
-        r3.push_back({f, 0, (H + DOG_NMS_COLS - 1) / DOG_NMS_COLS,
-                      (W + V.nms_band() - 1) / V.nms_band(), 0});
-    }
-    auto by_cost = [](const Raw& a, const Raw& b) {
-        if (a.radius != b.radius)
-            return a.radius > b.radius;
-        return a.frame < b.frame;
-    };
-    std::stable_sort(r1.begin(), r1.end(), by_cost);
-    std::stable_sort(r2.begin(), r2.end(), by_cost);
-    auto build_table = [](const std::vector<Raw>& raw, std::vector<Tile>* out) {
-        std::vector<Tile> per[DOG_NXCD];
-        for (const Raw& r : raw) {
-            for (int s = 0; s < DOG_NXCD; ++s) {
-                const int c0 = (int)((long long)s * r.n_cb / DOG_NXCD);
-                const int c1 = (int)((long long)(s + 1) * r.n_cb / DOG_NXCD);
-                const int x = (s + r.frame) % DOG_NXCD;
-                for (int cb = c0; cb < c1; ++cb)
-                    for (int b = 0; b < r.n_band; ++b) {
-                        Tile t;
-                        t.frame = (uint16_t)r.frame;
-                        t.plane = (uint8_t)r.plane;
-                        t.pad_ = 0;
-                        t.cb = (uint16_t)cb;
-                        t.band = (uint16_t)b;
-                        per[x].push_back(t);
-                    }
+    // events recorded inside a graph cannot be timed, so per-kernel timing
+    // issues the same sequence directly
+    const bool use_graph = c->use_graphs && !c->profiling;
+    std::vector<long long> key = launch_key(c, frames, dbg_D);
+    if (!c->tables_ready || key != c->graph_key) {
+        drop_graph(c);
+        // ---- tile tables.  Each (frame, plane) unit's column blocks are cut
+        // into DOG_NXCD contiguous slices and slice s goes to XCD (s + frame) %
+        // DOG_NXCD, so one XCD's L2 holds one band of columns of every plane
+        // (small frames spread over the XCDs).  Per XCD, tiles are ordered
+        // widest kernel first; the launch table interleaves the XCD lists so
+        // workgroup b (dispatched to XCD b % 8) gets a tile of list b % 8, and
+        // an exhausted list's slot is filled from the longest remaining list.
+        const int band = V.band();
+        struct Raw {
+            int frame, plane, n_cb, n_band, radius;
+        };
+        std::vector<Raw> r1, r2, r3;
+        for (int f = 0; f < n; ++f) {
+            const int H = frames[f].H, W = frames[f].W;
+            for (int p = 0; p < n_g; ++p) {
+                r1.push_back({f, p, (W + 63) / 64, (H + band - 1) / band, P.r[p]});
+                r2.push_back({f, p, (H + 63) / 64, (W + band - 1) / band, P.r[p]});
             }
+            r3.push_back({f, 0, (H + DOG_NMS_COLS - 1) / DOG_NMS_COLS,
+                          (W + V.nms_band() - 1) / V.nms_band(), 0});
         }
-        size_t total = 0, pos[DOG_NXCD] = {0};
-        for (int x = 0; x < DOG_NXCD; ++x)
-            total += per[x].size();
-        out->clear();
-        out->reserve(total);
-        while (out->size() < total) {
-            for (int x = 0; x < DOG_NXCD && out->size() < total; ++x) {
-                int src = x;
-                if (pos[x] >= per[x].size()) {
-                    size_t best = 0;
-                    for (int y = 0; y < DOG_NXCD; ++y)
-                        if (per[y].size() - pos[y] > best) {
-                            best = per[y].size() - pos[y];
-                            src = y;
+        auto by_cost = [](const Raw& a, const Raw& b) {
+            if (a.radius != b.radius)
+                return a.radius > b.radius;
+            return a.frame < b.frame;
+        };
+        std::stable_sort(r1.begin(), r1.end(), by_cost);
+        std::stable_sort(r2.begin(), r2.end(), by_cost);
+        auto build_table = [](const std::vector<Raw>& raw, std::vector<Tile>* outt) {
+            std::vector<Tile> per[DOG_NXCD];
+            for (const Raw& r : raw) {
+                for (int sl = 0; sl < DOG_NXCD; ++sl) {
+                    const int c0 = (int)((long long)sl * r.n_cb / DOG_NXCD);
+                    const int c1 = (int)((long long)(sl + 1) * r.n_cb / DOG_NXCD);
+                    const int x = (sl + r.frame) % DOG_NXCD;
+                    for (int cb = c0; cb < c1; ++cb)
+                        for (int bnd = 0; bnd < r.n_band; ++bnd) {
+                            Tile t;
+                            t.frame = (uint16_t)r.frame;
+                            t.plane = (uint8_t)r.plane;
+                            t.pad_ = 0;
+                            t.cb = (uint16_t)cb;
+                            t.band = (uint16_t)bnd;
+                            per[x].push_back(t);
                         }
                 }
-                out->push_back(per[src][pos[src]++]);
             }
+            size_t tot = 0, pos[DOG_NXCD] = {0};
+            for (int x = 0; x < DOG_NXCD; ++x)
+                tot += per[x].size();
+            outt->clear();
+            outt->reserve(tot);
+            while (outt->size() < tot) {
+                for (int x = 0; x < DOG_NXCD && outt->size() < tot; ++x) {
+                    int src = x;
+                    if (pos[x] >= per[x].size()) {
+                        size_t best = 0;
+                        for (int y = 0; y < DOG_NXCD; ++y)
+                            if (per[y].size() - pos[y] > best) {
+                                best = per[y].size() - pos[y];
+                                src = y;
+                            }
+                    }
+                    outt->push_back(per[src][pos[src]++]);
+                }
+            }
+        };
+        std::vector<Tile> tb1, tb2, tb3;
+        build_table(r1, &tb1);
+        build_table(r2, &tb2);
+        build_table(r3, &tb3);
+        const long long t1 = (long long)tb1.size(), t2 = (long long)tb2.size(),
+                        t3 = (long long)tb3.size();
+        if (t1 > INT32_MAX / 2 || t2 > INT32_MAX / 2 || t3 > INT32_MAX / 2 || n > 65535) {
+            set_error("batch too large for one launch");
+            return DOG_EINVAL;
         }
-    };
-    std::vector<Tile> tb1, tb2, tb3;
-    build_table(r1, &tb1);
-    build_table(r2, &tb2);
-    build_table(r3, &tb3);
-    const long long t1 = (long long)tb1.size(), t2 = (long long)tb2.size(), t3 = (long long)tb3.size();
-    if (t1 > INT32_MAX / 2 || t2 > INT32_MAX / 2 || t3 > INT32_MAX / 2 || n > 65535 ||
-        (long long)frames[0].W > 65535 * 64LL) {
-        set_error("batch too large for one launch");
-        return DOG_EINVAL;
-    }
 
-    const size_t o_frames = 0;
-    const size_t o_ladder = align_up(o_frames + sizeof(FrameDesc) * n, 256);
-    const size_t o_weights = align_up(o_ladder + sizeof(LadderDesc), 256);
-    const size_t o_t1 = align_up(o_weights + sizeof(float) * P.weights.size(), 256);
-    const size_t o_t2 = align_up(o_t1 + sizeof(Tile) * tb1.size(), 256);
-    const size_t o_t3 = align_up(o_t2 + sizeof(Tile) * tb2.size(), 256);
-    const size_t tbytes = align_up(o_t3 + sizeof(Tile) * tb3.size(), 256);
-    if ((rc = ctx_alloc(c, &c->tables, tbytes, "launch tables")) != DOG_OK)
-        return rc;
-    if ((rc = ctx_pin(&c->h_tables, tbytes)) != DOG_OK)
-        return rc;
-    char* dt = static_cast<char*>(c->tables.p);
-    char* h = static_cast<char*>(c->h_tables.p);
-    std::memcpy(h + o_frames, fd.data(), sizeof(FrameDesc) * n);
-    std::memcpy(h + o_ladder, &P.desc, sizeof(LadderDesc));
-    std::memcpy(h + o_weights, P.weights.data(), sizeof(float) * P.weights.size());
-    std::memcpy(h + o_t1, tb1.data(), sizeof(Tile) * tb1.size());
-    std::memcpy(h + o_t2, tb2.data(), sizeof(Tile) * tb2.size());
-    std::memcpy(h + o_t3, tb3.data(), sizeof(Tile) * tb3.size());
-    DOG_HIP(hipMemcpyAsync(c->tables.p, h, tbytes, hipMemcpyHostToDevice, s));
-
-    // ---- candidate buffer
-    if (c->cap == 0) {
-        if ((rc = ctx_alloc(c, &c->cand, sizeof(CandHeader) + kRecBytes * 65536, "candidates")) !=
-            DOG_OK)
+        const size_t o_frames = 0;
+        const size_t o_ladder = align_up(o_frames + frames_bytes, 256);
+        const size_t o_weights = align_up(o_ladder + sizeof(LadderDesc), 256);
+        const size_t o_t1 = align_up(o_weights + sizeof(float) * P.weights.size(), 256);
+        const size_t o_t2 = align_up(o_t1 + sizeof(Tile) * tb1.size(), 256);
+        const size_t o_t3 = align_up(o_t2 + sizeof(Tile) * tb2.size(), 256);
+        const size_t tbytes = align_up(o_t3 + sizeof(Tile) * tb3.size(), 256);
+        if ((rc = ctx_alloc(c, &c->tables, tbytes, "launch tables")) != DOG_OK)
             return rc;
-        c->cap = 65536;
+        if ((rc = ctx_pin(&c->h_tables, tbytes)) != DOG_OK)
+            return rc;
+        key = launch_key(c, frames, dbg_D);  // buffers may have moved
+        char* dt = static_cast<char*>(c->tables.p);
+        char* h = static_cast<char*>(c->h_tables.p);
+        std::memcpy(h + o_frames, fd.data(), frames_bytes);
+        std::memcpy(h + o_ladder, &P.desc, sizeof(LadderDesc));
+        std::memcpy(h + o_weights, P.weights.data(), sizeof(float) * P.weights.size());
+        std::memcpy(h + o_t1, tb1.data(), sizeof(Tile) * tb1.size());
+        std::memcpy(h + o_t2, tb2.data(), sizeof(Tile) * tb2.size());
+        std::memcpy(h + o_t3, tb3.data(), sizeof(Tile) * tb3.size());
+        DOG_HIP(hipMemcpyAsync(c->tables.p, h, tbytes, hipMemcpyHostToDevice, c->stream));
+        DOG_HIP(hipStreamSynchronize(c->stream));
+
+        LaunchArgs& a = c->args;
+        std::memset(&a, 0, sizeof(a));
+        a.frames = reinterpret_cast<const FrameDesc*>(dt + o_frames);
+        a.ladders = reinterpret_cast<const LadderDesc*>(dt + o_ladder);
+        a.weights = reinterpret_cast<const float*>(dt + o_weights);
+        a.tiles1 = reinterpret_cast<const Tile*>(dt + o_t1);
+        a.tiles2 = reinterpret_cast<const Tile*>(dt + o_t2);
+        a.tiles3 = reinterpret_cast<const Tile*>(dt + o_t3);
+        a.cand = static_cast<CandHeader*>(c->cand.p);
+        a.cap = c->cap;
+        a.n1 = (int)t1;
+        a.n2 = (int)t2;
+        a.n3 = (int)t3;
+        c->n_gauss = n_g;
+        // readback size fixed in the captured sequence: header + a guess of
+        // the record count (more is copied afterwards if needed)
+        c->guess = std::min<uint32_t>(
+            c->cap, std::max<uint32_t>(2048, c->last_count + c->last_count / 2 + 256));
+
+        if (c->profiling) {
+            for (int i = 0; i < 4; ++i)
+                if (!c->ev[i])
+                    DOG_HIP(hipEventCreate(&c->ev[i]));
+        }
+        c->frames_bytes = frames_bytes;
+        if (use_graph) {
+            // capture: frame table upload, the three kernels, the readback
+            DOG_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            const hipError_t e = enqueue_sequence(c, c->stream);
+            hipGraph_t g = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+            if (e != hipSuccess) {
+                if (g)
+                    (void)hipGraphDestroy(g);
+                return hip_fail(e, "capture of the launch sequence");
+            }
+            DOG_HIP(e2);
+            c->graph = g;
+            DOG_HIP(hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+        }
+        c->graph_key = key;
+        c->tables_ready = true;
+    } else {
+        std::memcpy(c->h_tables.p, fd.data(), frames_bytes);
     }
 
-    LaunchArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.frames = reinterpret_cast<const FrameDesc*>(dt + o_frames);
-    a.ladders = reinterpret_cast<const LadderDesc*>(dt + o_ladder);
-    a.weights = reinterpret_cast<const float*>(dt + o_weights);
-    a.tiles1 = reinterpret_cast<const Tile*>(dt + o_t1);
-    a.tiles2 = reinterpret_cast<const Tile*>(dt + o_t2);
-    a.tiles3 = reinterpret_cast<const Tile*>(dt + o_t3);
-    a.cand = static_cast<CandHeader*>(c->cand.p);
-    a.cap = c->cap;
-    a.n1 = (int)t1;
-    a.n2 = (int)t2;
-    a.n3 = (int)t3;
-
-    if (c->profiling) {
-        for (int i = 0; i < 4; ++i)
-            if (!c->ev[i])
-                DOG_HIP(hipEventCreate(&c->ev[i]));
+    // ---- run: the caller's stream s orders the input; the sequence runs on
+    // the context stream after it
+    if (s != c->stream) {
+        if (!c->ev_in)
+            DOG_HIP(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+        DOG_HIP(hipEventRecord(c->ev_in, s));
+        DOG_HIP(hipStreamWaitEvent(c->stream, c->ev_in, 0));
     }
-    DOG_HIP(dogk_launch_sequence(c->variant, &a, (int)t1, (int)t2, (int)t3, s,
-                                 c->profiling ? c->ev : nullptr));
-
-    // ---- readback: header + a guess of the records in one copy
-    uint32_t guess = std::min<uint32_t>(c->cap, std::max<uint32_t>(4096, c->last_count + c->last_count / 4 + 256));
-    if ((rc = ctx_pin(&c->h_cand, sizeof(CandHeader) + kRecBytes * (size_t)c->cap)) != DOG_OK)
-        return rc;
-    DOG_HIP(hipMemcpyAsync(c->h_cand.p, c->cand.p, sizeof(CandHeader) + kRecBytes * guess,
-                           hipMemcpyDeviceToHost, s));
-    DOG_HIP(hipStreamSynchronize(s));
+    if (use_graph)
+        DOG_HIP(hipGraphLaunch(c->graph_exec, c->stream));
+    else
+        DOG_HIP(enqueue_sequence(c, c->stream));
+    DOG_HIP(hipStreamSynchronize(c->stream));
+    LaunchArgs a = c->args;
+    const uint32_t guess = c->guess;
     uint32_t count = static_cast<CandHeader*>(c->h_cand.p)->count;
     if (c->profiling) {
         for (int i = 0; i < 3; ++i) {
@@ -329,13 +430,14 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
         c->cap = newcap;
         if ((rc = ctx_pin(&c->h_cand, sizeof(CandHeader) + kRecBytes * (size_t)newcap)) != DOG_OK)
             return rc;
+        drop_graph(c);  // points at the old buffers
         a.cand = static_cast<CandHeader*>(c->cand.p);
         a.cap = c->cap;
-        DOG_HIP(dogk_fill_u32(&a.cand->count, 1, 0u, s));
-        DOG_HIP(dogk_launch_nms(c->variant, &a, (int)t3, s));
+        DOG_HIP(dogk_fill_u32(&a.cand->count, 1, 0u, c->stream));
+        DOG_HIP(dogk_launch_nms(c->variant, &a, a.n3, n_g, c->stream));
         DOG_HIP(hipMemcpyAsync(c->h_cand.p, c->cand.p, sizeof(CandHeader) + kRecBytes * count,
-                               hipMemcpyDeviceToHost, s));
-        DOG_HIP(hipStreamSynchronize(s));
+                               hipMemcpyDeviceToHost, c->stream));
+        DOG_HIP(hipStreamSynchronize(c->stream));
         const uint32_t again = static_cast<CandHeader*>(c->h_cand.p)->count;
         if (again != count) {
             set_error("candidate count changed between identical launches");
@@ -344,8 +446,9 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
     } else if (count > guess) {
         char* hb = static_cast<char*>(c->h_cand.p) + sizeof(CandHeader) + kRecBytes * guess;
         const char* db = static_cast<const char*>(c->cand.p) + sizeof(CandHeader) + kRecBytes * guess;
-        DOG_HIP(hipMemcpyAsync(hb, db, kRecBytes * (count - guess), hipMemcpyDeviceToHost, s));
-        DOG_HIP(hipStreamSynchronize(s));
+        DOG_HIP(hipMemcpyAsync(hb, db, kRecBytes * (count - guess), hipMemcpyDeviceToHost,
+                               c->stream));
+        DOG_HIP(hipStreamSynchronize(c->stream));
     }
     c->last_count = count;
 

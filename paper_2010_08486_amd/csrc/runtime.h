@@ -77,8 +77,9 @@ int dogk_num_variants();
 void dogk_variant_geometry(int v, int* S, int* NW, int* BI, int* BN, int* NWN);
 int dogk_variant_ring(int v);
 hipError_t dogk_launch_sequence(int variant, const dog::LaunchArgs* args, int grid1, int grid2,
-                                int grid3, hipStream_t stream, hipEvent_t* ev);
-hipError_t dogk_launch_nms(int variant, const dog::LaunchArgs* args, int grid3, hipStream_t stream);
+                                int grid3, int max_gauss, hipStream_t stream, hipEvent_t* ev);
+hipError_t dogk_launch_nms(int variant, const dog::LaunchArgs* args, int grid3, int max_gauss,
+                           hipStream_t stream);
 hipError_t dogk_untranspose(const float* src, float* dst, int n_planes, int H, int W,
                             long long pitch, hipStream_t stream);
 hipError_t dogk_fill_u32(uint32_t* p, int n, uint32_t v, hipStream_t stream);
@@ -112,7 +113,21 @@ struct dog_context {
     double kernel_ms[3] = {0.0, 0.0, 0.0};
     int64_t kernel_launches = 0;
 
+    // the captured launch sequence of the last table layout (frame table
+    // upload, three kernels, readback) and what it was built for
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<long long> graph_key;
+    dog::LaunchArgs args;
+    int n_gauss = 0;
+    size_t frames_bytes = 0;       // frame table bytes uploaded per launch
+    uint32_t guess = 0;            // records read back by the captured sequence
+    bool tables_ready = false;     // device tables match graph_key
+    bool use_graphs = true;        // replay a captured graph (else launch directly)
+    hipEvent_t ev_in = nullptr;    // orders the caller's stream before the sequence
+
     bool have_plan = false;
+    uint64_t plan_gen = 0;
     dog::Plan plan;
     uint32_t last_count = 0;       // candidates found by the previous launch (readback guess)
 };
@@ -123,6 +138,7 @@ int ctx_alloc(dog_context* c, DevBuf* b, size_t bytes, const char* what);
 int ctx_pin(PinBuf* b, size_t bytes);
 int ctx_plan(dog_context* c, const dog_params* prm, const Plan** out);
 int ctx_set_variant(dog_context* c, int v);
+void drop_graph(dog_context* c);
 
 // Run the three kernels over `frames` (device pixels) with plan P and read
 // back the candidate records, grouped per frame and sorted by (y, x, scale).

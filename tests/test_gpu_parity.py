@@ -177,3 +177,42 @@ def test_invalid_device_arguments(dog, ctx, torch_mod):
     assert e.value.code == dog.DOG_EINVAL
     with pytest.raises(dog.DogError):
         dog.detect(np.zeros((0, 5), np.float32), 1, 8)
+
+
+def test_graph_replays_match_eager_launches(dog, torch_mod):
+    # the captured sequence is replayed with new frame pointers; every replay,
+    # with eager work and synchronisations in between, must equal the eager path
+    torch = torch_mod
+    frames = [synth.camera_frame(seed=70 + i, H=300, W=260, n_blobs=40) for i in range(3)]
+    prm = dog.Params(**CAMERA)
+    with dog.Context(0) as eager:
+        eager.set_graph_mode(False)
+        ref = [eager.detect_device(_dev(torch, f), prm) for f in frames]
+        ref_batch, _ = eager.detect_batch(frames, prm)
+    dev = [_dev(torch, f) for f in frames]
+    with dog.Context(0) as g:
+        for rep in range(4):
+            for i, t in enumerate(dev):
+                got = g.detect_device(t, prm)
+                assert got.tobytes() == ref[i].tobytes(), (rep, i)
+                float((t * 2.0).sum().item())      # eager torch work on the same stream
+                torch.cuda.synchronize()
+            got_b, _ = g.detect_batch(dev, prm)
+            for i in range(3):
+                assert got_b[i].tobytes() == ref_batch[i].tobytes() == ref[i].tobytes()
+
+
+def test_kernel_timing_in_both_launch_modes(dog, torch_mod):
+    img = synth.camera_frame(seed=9, H=512, W=512, n_blobs=100)
+    t = _dev(torch_mod, img)
+    prm = dog.Params(**CAMERA)
+    with dog.Context(0) as c:
+        for graphs in (True, False):
+            c.set_graph_mode(graphs)
+            c.set_profiling(True)
+            for _ in range(3):
+                c.detect_device(t, prm)
+            ms, n = c.kernel_times()
+            c.set_profiling(False)
+            assert n == 3
+            assert all(m > 0 for m in ms), ms
