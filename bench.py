@@ -38,7 +38,7 @@ PEAK_FP32_TFLOPS = N_CU * CLOCK_HZ * FP32_FMA_PER_CU_CLK * 2 / 1e12   # 78.6: un
 PEAK_FP32_PACKED_TFLOPS = 157.3   # needs v_pk_fma_f32, which this build does not emit
 PEAK_HBM_GBS = 8000.0
 
-PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "pass2_frame1k_counters.txt")
+PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "dog_kernels_frame1k_counters.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2010_08486_amd", "csrc", "kernels.hip")
 
 
@@ -95,6 +95,9 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--variant", type=int, default=-1)
+    ap.add_argument("--pmc-workload", type=int, default=0,
+                    help="only run N detector steps on the 1024x1024 frame, then a plain 256 MiB "
+                         "device copy (the calibration for rocprofv3 byte counters), and exit")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -120,6 +123,19 @@ def main() -> int:
     ctx = dog.Context(0)
     if args.variant >= 0:
         ctx.set_variant(args.variant)
+
+    if args.pmc_workload > 0:
+        for _ in range(args.pmc_workload):
+            ctx.detect_device(t_img, prm)
+        a = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        ctx.close()
+        print("pmc workload done", flush=True)
+        return 0
 
     for _ in range(args.warmup):
         ctx.detect_device(t_img, prm)

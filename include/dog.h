@@ -206,6 +206,51 @@ int dog_set_profiling(dog_context* ctx, int32_t on);
 int dog_kernel_times(dog_context* ctx, double* ms_out, int64_t* launches_out);
 
 
+/* ------------------------------------------------------------ serving */
+
+/* Serving loop: host frames are submitted at any time; a dispatcher forms a
+ * batch from whatever waits (at most max_batch_frames, and only while the
+ * device footprint of all batches in flight stays within the admission
+ * budget) and hands it to an idle slot.  Each slot owns a context and a
+ * stream, so batches overlap on the device; a request that arrives while
+ * others run joins the next batch as soon as a slot and memory are free.
+ * Results are the same as dog_detect on the frame alone. */
+typedef struct {
+    int32_t max_batch_frames;   /* frames per launch sequence (<= 0: 16)              */
+    int32_t slots;              /* launch sequences in flight (<= 0: 2)               */
+    int32_t queue_capacity;     /* waiting requests before DOG_EBUSY (<= 0: 4096)    */
+    int32_t dry_run;            /* test hook: no GPU work; a batch takes
+                                   dry_run_us_per_mpx per Mpixel and finds no blobs  */
+    uint64_t hbm_budget_bytes;  /* admission budget (0: the slot context's budget)   */
+    double max_wait_ms;         /* batching window (0: launch whatever waits)        */
+    double dry_run_us_per_mpx;
+} dog_server_opts;
+
+typedef struct {
+    int64_t submitted, completed, failed, rejected, queued, running, batches;
+    double mean_batch_frames;
+    double p50_ms, p99_ms, mean_ms, max_ms;   /* submit -> blob list ready          */
+    double frames_per_s;                      /* completed / (last done - first submit) */
+    uint64_t reserved_bytes, peak_reserved_bytes;
+} dog_stats;
+
+/* Create a server on GPU `device` for fixed detector parameters.  Frame
+ * footprint for admission: 2 (k+1) W ceil64(H) + H W floats + 4 KiB. */
+int dog_server_create(int device, const dog_params* params, const dog_server_opts* opts,
+                      dog_server** out);
+/* Queue a host frame (copied; the caller may reuse its buffer at once).
+ * DOG_EBUSY: queue full; DOG_ENOMEM: the frame alone exceeds the budget. */
+int dog_server_submit(dog_server* sv, const dog_frame* frame, uint64_t* ticket);
+/* Result of a ticket: DOG_OK (moved into *out, with t_arrive_ns/t_done_ns),
+ * DOG_EAGAIN (not done yet), DOG_ENOTFOUND (unknown or already taken). */
+int dog_server_poll(dog_server* sv, uint64_t ticket, dog_result* out);
+int dog_server_wait(dog_server* sv, uint64_t ticket, dog_result* out);
+/* Block until every submitted request has completed. */
+int dog_server_drain(dog_server* sv);
+int dog_server_stats(dog_server* sv, dog_stats* out);
+/* Finish running batches, drop queued requests and untaken results. */
+void dog_server_destroy(dog_server* sv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -58,6 +58,21 @@ class dog_result(ctypes.Structure):
                 ("t_done_ns", ctypes.c_int64)]
 
 
+class dog_server_opts(ctypes.Structure):
+    _fields_ = [("max_batch_frames", ctypes.c_int32), ("slots", ctypes.c_int32),
+                ("queue_capacity", ctypes.c_int32), ("dry_run", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_uint64), ("max_wait_ms", ctypes.c_double),
+                ("dry_run_us_per_mpx", ctypes.c_double)]
+
+
+class dog_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "failed", "rejected",
+                                               "queued", "running", "batches")] + \
+               [(n, ctypes.c_double) for n in ("mean_batch_frames", "p50_ms", "p99_ms", "mean_ms",
+                                                "max_ms", "frames_per_s")] + \
+               [("reserved_bytes", ctypes.c_uint64), ("peak_reserved_bytes", ctypes.c_uint64)]
+
+
 @dataclass
 class Params:
     """Detector hyper-parameters; defaults follow Sec. 4.1 (threshold 0.1,
@@ -107,6 +122,14 @@ def lib() -> ctypes.CDLL:
         "dog_plan_info": (i32, [ctypes.POINTER(dog_params), ctypes.POINTER(i32),
                                 ctypes.POINTER(dbl), ctypes.POINTER(i32), i32]),
         "dog_prune": (i32, [ctypes.POINTER(dog_params), vp, i64, pi64]),
+        "dog_server_create": (i32, [ctypes.c_int, ctypes.POINTER(dog_params),
+                                    ctypes.POINTER(dog_server_opts), ctypes.POINTER(vp)]),
+        "dog_server_submit": (i32, [vp, ctypes.POINTER(dog_frame), ctypes.POINTER(u64)]),
+        "dog_server_poll": (i32, [vp, u64, ctypes.POINTER(dog_result)]),
+        "dog_server_wait": (i32, [vp, u64, ctypes.POINTER(dog_result)]),
+        "dog_server_drain": (i32, [vp]),
+        "dog_server_stats": (i32, [vp, ctypes.POINTER(dog_stats)]),
+        "dog_server_destroy": (None, [vp]),
         "dog_num_variants": (ctypes.c_int, []),
         "dog_variant_info": (ctypes.c_int, [ctypes.c_int] + [ctypes.POINTER(i32)] * 4),
         "dog_set_variant": (ctypes.c_int, [vp, ctypes.c_int]),
@@ -333,3 +356,78 @@ def footprint(params: Params, shapes) -> int:
     prm = params.c()
     _check(lib().dog_footprint(ctypes.byref(prm), len(shapes), hs, ws, ctypes.byref(out)))
     return int(out.value)
+
+
+class Server:
+    """dog_server: continuous batching of host frames (see include/dog.h)."""
+
+    def __init__(self, params: Params, device: int = 0, max_batch_frames: int = 16,
+                 slots: int = 2, queue_capacity: int = 4096, hbm_budget_bytes: int = 0,
+                 max_wait_ms: float = 0.0, dry_run: bool = False,
+                 dry_run_us_per_mpx: float = 0.0):
+        self._h = ctypes.c_void_p()
+        opts = dog_server_opts(max_batch_frames, slots, queue_capacity, 1 if dry_run else 0,
+                               hbm_budget_bytes, max_wait_ms, dry_run_us_per_mpx)
+        prm = params.c()
+        _check(lib().dog_server_create(device, ctypes.byref(prm), ctypes.byref(opts),
+                                       ctypes.byref(self._h)))
+
+    def close(self) -> None:
+        if self._h:
+            lib().dog_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def submit(self, frame: np.ndarray) -> int:
+        a = np.asarray(frame)
+        if a.dtype != np.float32 or a.ndim != 2:
+            raise TypeError("frames must be 2-D float32 arrays")
+        if a.strides[1] != 4 or a.strides[0] % 4:
+            a = np.ascontiguousarray(a)
+        fr = dog_frame(a.ctypes.data, a.shape[0], a.shape[1], a.strides[0] // 4, 0, 0)
+        t = ctypes.c_uint64(0)
+        _check(lib().dog_server_submit(self._h, ctypes.byref(fr), ctypes.byref(t)))
+        return int(t.value)
+
+    @staticmethod
+    def _unpack(r: dog_result):
+        b = np.empty(r.count, BLOB_DTYPE)
+        if r.count:
+            ctypes.memmove(b.ctypes.data, r.blobs, r.count * BLOB_DTYPE.itemsize)
+        lib().dog_blobs_free(ctypes.cast(r.blobs, ctypes.c_void_p))
+        info = {"status": int(r.status), "raw_count": int(r.raw_count),
+                "t_arrive_ns": int(r.t_arrive_ns), "t_done_ns": int(r.t_done_ns)}
+        return b, info
+
+    def poll(self, ticket: int):
+        """(blobs, info) if done, None if still pending; raises on unknown tickets."""
+        r = dog_result()
+        rc = lib().dog_server_poll(self._h, ticket, ctypes.byref(r))
+        if rc == DOG_EAGAIN:
+            return None
+        _check(rc)
+        return self._unpack(r)
+
+    def wait(self, ticket: int):
+        r = dog_result()
+        _check(lib().dog_server_wait(self._h, ticket, ctypes.byref(r)))
+        return self._unpack(r)
+
+    def drain(self) -> None:
+        _check(lib().dog_server_drain(self._h))
+
+    def stats(self) -> dict:
+        st = dog_stats()
+        _check(lib().dog_server_stats(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in dog_stats._fields_}

@@ -1,0 +1,182 @@
+// Whole detector on a list of frames of any sizes: validation, grouping into
+// launch sequences that fit the context's HBM budget, staging of host frames,
+// the launch, and per-frame pruning.  Used by dog_detect_batch and the server.
+#include <cstdlib>
+#include <cstring>
+
+#include "runtime.h"
+
+namespace dog {
+
+constexpr int kMaxSide = 32768;
+
+int check_image(const void* p, int64_t h, int64_t w, int64_t stride)
+{
+    if (!p) {
+        set_error("image pointer is NULL");
+        return DOG_EINVAL;
+    }
+    if (h < 1 || w < 1 || h > kMaxSide || w > kMaxSide) {
+        set_error("image height and width must be in [1, 32768]");
+        return DOG_EINVAL;
+    }
+    if (stride < w) {
+        set_error("row_stride must be >= width");
+        return DOG_EINVAL;
+    }
+    // every plane is addressed with 32-bit byte offsets: input rows and
+    // transposed planes (width rows of height rounded up to 64) stay < 2 GiB
+    if ((double)h * (double)stride >= (double)(1LL << 29) ||
+        (double)w * (double)(h + 63) >= (double)(1LL << 29)) {
+        set_error("height * row_stride and width * (height + 63) must be < 2^29");
+        return DOG_EINVAL;
+    }
+    return DOG_OK;
+}
+
+
+// Copy a sorted, pruned blob vector into a malloc'd array.
+int export_blobs(const std::vector<dog_blob>& v, dog_blob** out, int64_t* n)
+{
+    *out = nullptr;
+    *n = 0;
+    if (v.empty())
+        return DOG_OK;
+    dog_blob* p = static_cast<dog_blob*>(std::malloc(sizeof(dog_blob) * v.size()));
+    if (!p) {
+        set_error("out of host memory");
+        return DOG_ENOMEM;
+    }
+    std::memcpy(p, v.data(), sizeof(dog_blob) * v.size());
+    *out = p;
+    *n = (int64_t)v.size();
+    return DOG_OK;
+}
+
+
+int detect_frames(dog_context* ctx, const dog_params* params, int32_t n_frames,
+                  const dog_frame* frames, hipStream_t s, dog_result* results)
+{
+    for (int32_t f = 0; f < n_frames; ++f)
+        std::memset(&results[f], 0, sizeof(dog_result));
+    int rc = DOG_OK;
+    {
+        hipError_t e = hipSetDevice(ctx->device);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipSetDevice");
+    }
+    const Plan* P = nullptr;
+    if ((rc = ctx_plan(ctx, params, &P)) != DOG_OK) {
+        for (int32_t f = 0; f < n_frames; ++f)
+            results[f].status = rc;
+        return rc;
+    }
+    int first_err = DOG_OK;
+    std::string first_msg;
+
+    // valid frames, and the bytes each needs: planes + staged host pixels
+    std::vector<int> idx;
+    std::vector<uint64_t> need;
+    for (int32_t f = 0; f < n_frames; ++f) {
+        const dog_frame& fr = frames[f];
+        const int e = check_image(fr.data, fr.height, fr.width, fr.row_stride);
+        if (e != DOG_OK) {
+            results[f].status = e;
+            if (first_err == DOG_OK) {
+                first_err = e;
+                first_msg = last_error();
+            }
+            continue;
+        }
+        const uint64_t pitch = ((uint64_t)fr.height + 63) / 64 * 64;
+        uint64_t b = 2ull * P->n_g * (uint64_t)fr.width * pitch * sizeof(float) + 256;
+        if (!fr.on_device)
+            b += (uint64_t)fr.height * (uint64_t)fr.width * sizeof(float) + 256;
+        idx.push_back(f);
+        need.push_back(b);
+    }
+    // consecutive chunks that fit in what the budget leaves for planes and inputs
+    const uint64_t fixed = ctx->used - ctx->planes.bytes - ctx->input.bytes;
+    const uint64_t room = ctx->budget > fixed + (64u << 20) ? ctx->budget - fixed - (64u << 20) : 0;
+    size_t i = 0;
+    while (i < idx.size()) {
+        size_t j = i;
+        uint64_t sum = 0;
+        while (j < idx.size() && (j == i || sum + need[j] <= room)) {
+            sum += need[j];
+            ++j;
+        }
+        if (sum > room) {
+            for (size_t q = i; q < j; ++q)
+                results[idx[q]].status = DOG_ENOMEM;
+            if (first_err == DOG_OK) {
+                first_err = DOG_ENOMEM;
+                first_msg = "frame footprint exceeds the HBM budget";
+            }
+            i = j;
+            continue;
+        }
+        // stage host frames
+        uint64_t in_bytes = 0;
+        for (size_t q = i; q < j; ++q)
+            if (!frames[idx[q]].on_device)
+                in_bytes += ((uint64_t)frames[idx[q]].height * frames[idx[q]].width * sizeof(float) + 255) / 256 * 256;
+        if (in_bytes) {
+            if ((rc = ctx_pin(&ctx->h_input, in_bytes)) != DOG_OK ||
+                (rc = ctx_alloc(ctx, &ctx->input, in_bytes, "input frames")) != DOG_OK)
+                goto chunk_fail;
+        }
+        {
+            std::vector<FrameIn> fin;
+            uint64_t o = 0;
+            for (size_t q = i; q < j; ++q) {
+                const dog_frame& fr = frames[idx[q]];
+                if (fr.on_device) {
+                    fin.push_back({fr.data, (int)fr.height, (int)fr.width, (long long)fr.row_stride});
+                } else {
+                    char* hp = static_cast<char*>(ctx->h_input.p) + o;
+                    for (int64_t y = 0; y < fr.height; ++y)
+                        std::memcpy(hp + (size_t)y * fr.width * sizeof(float), fr.data + y * fr.row_stride,
+                                    (size_t)fr.width * sizeof(float));
+                    fin.push_back({reinterpret_cast<const float*>(static_cast<char*>(ctx->input.p) + o),
+                                   (int)fr.height, (int)fr.width, (long long)fr.width});
+                    o += ((uint64_t)fr.height * fr.width * sizeof(float) + 255) / 256 * 256;
+                }
+            }
+            if (o) {
+                hipError_t e = hipMemcpyAsync(ctx->input.p, ctx->h_input.p, o, hipMemcpyHostToDevice, s);
+                if (e != hipSuccess) {
+                    rc = hip_fail(e, "hipMemcpyAsync(input)");
+                    goto chunk_fail;
+                }
+            }
+            std::vector<std::vector<dog_blob>> res;
+            rc = run_frames(ctx, *P, fin, s, &res, false, nullptr, nullptr, nullptr);
+            if (rc != DOG_OK)
+                goto chunk_fail;
+            for (size_t q = i; q < j; ++q) {
+                dog_result& R = results[idx[q]];
+                std::vector<dog_blob>& v = res[q - i];
+                R.raw_count = (int64_t)v.size();
+                prune_blobs(v, P->sigma, P->prm.overlap);
+                R.status = export_blobs(v, &R.blobs, &R.count);
+            }
+        }
+        i = j;
+        continue;
+    chunk_fail:
+        for (size_t q = i; q < j; ++q)
+            results[idx[q]].status = rc;
+        if (first_err == DOG_OK) {
+            first_err = rc;
+            first_msg = last_error();
+        }
+        i = j;
+    }
+    if (first_err != DOG_OK)
+        set_error(first_msg);
+    return first_err;
+}
+
+
+}  // namespace dog

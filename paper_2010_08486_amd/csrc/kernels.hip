@@ -255,22 +255,23 @@ __global__ void __launch_bounds__(64 * NW) k_pass2(LaunchArgs a)
     }
 }
 
-// Lanes i-1 and i+1 of a wave (-inf where the neighbour lane does not exist).
+// Lanes i-1 and i+1 of a wave.  Lanes 0 and 63 receive 0 from outside the
+// wave; they are halo lanes whose results are never used.
 __device__ __forceinline__ float lane_prev(float v)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, -INFINITY),
-                                                                 __builtin_bit_cast(int, v), 0x138,
-                                                                 0xf, 0xf, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138,
+                                                              0xf, 0xf, true));
 }
 
 __device__ __forceinline__ float lane_next(float v)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, -INFINITY),
-                                                                 __builtin_bit_cast(int, v), 0x130,
-                                                                 0xf, 0xf, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130,
+                                                              0xf, 0xf, true));
 }
 
-// Rows x0-1 .. x0+BN of column y of transposed plane p (0 outside the frame).
+// Rows x0-1 .. x0+BN of column y of transposed plane p, loaded without
+// branches: rows outside the frame are clamped (their values are replaced by
+// -inf in dog_rows) and the row offset is forced into a scalar register.
 template <int BN>
 __device__ __forceinline__ void load_plane_rows(float (&v)[BN + 2], const FrameDesc& f, int p,
                                                 int x0, unsigned voff)
@@ -280,8 +281,9 @@ __device__ __forceinline__ void load_plane_rows(float (&v)[BN + 2], const FrameD
     const int stride4 = (int)(f.pitch * 4);
 #pragma unroll
     for (int j = 0; j < BN + 2; ++j) {
-        const int x = x0 - 1 + j;
-        v[j] = (x >= 0 && x < f.W) ? load_f32(rs, voff, x * stride4) : 0.0f;
+        int x = x0 - 1 + j;
+        x = x < 0 ? 0 : (x >= f.W ? f.W - 1 : x);
+        v[j] = load_f32(rs, voff, __builtin_amdgcn_readfirstlane(x * stride4));
     }
 }
 
@@ -321,16 +323,11 @@ struct CandSink {
     uint32_t cap;
 };
 
-// Test one band row of scale i for every lane and append the survivors:
-// a voxel is kept iff it equals the maximum of its 3x3x3 neighbourhood and
-// exceeds the threshold.  Also writes the debug DoG plane when requested.
+// Append the voxels of one band row whose flag is set (wave ballot, prefix
+// popcount, one LDS atomic per wave).
 __device__ __forceinline__ void emit_row(const CandSink& snk, const FrameDesc& f, int lane, int y,
-                                         int x, int i, bool inside, float d, float m, float thr,
-                                         long long plane_sz)
+                                         int x, int i, bool flag, float d)
 {
-    const bool flag = inside && d == m && d > thr;
-    if (f.Ddbg != nullptr && inside)
-        f.Ddbg[(long long)i * plane_sz + (long long)x * f.pitch + y] = d;
     const unsigned long long bal = __ballot(flag);
     if (bal != 0ull) {
         unsigned base = 0;
@@ -356,6 +353,35 @@ __device__ __forceinline__ void emit_row(const CandSink& snk, const FrameDesc& f
     }
 }
 
+// Test the BN band rows of scale i: a voxel is kept iff it equals the maximum
+// of its 3x3x3 neighbourhood and exceeds the threshold.  One ballot decides
+// whether any row has a survivor; rows are then appended one by one.  The
+// debug build also stores the DoG plane.
+template <int BN, bool DBG>
+__device__ __forceinline__ void emit_plane(const CandSink& snk, const FrameDesc& f, int lane, int y,
+                                           int x0, int i, bool yout, const float (&dc)[BN],
+                                           const float (&s3m)[BN], const float (&s3c)[BN],
+                                           const float (&s3n)[BN], float thr, long long plane_sz)
+{
+    bool flag[BN];
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < BN; ++j) {
+        const int x = x0 + j;
+        const bool inside = yout && x < f.W;
+        const float m = fmaxf(s3m[j], fmaxf(s3c[j], s3n[j]));
+        flag[j] = inside && dc[j] == m && dc[j] > thr;
+        any = any || flag[j];
+        if (DBG && inside)
+            f.Ddbg[(long long)i * plane_sz + (long long)x * f.pitch + y] = dc[j];
+    }
+    if (__ballot(any) != 0ull) {
+#pragma unroll
+        for (int j = 0; j < BN; ++j)
+            emit_row(snk, f, lane, y, x0 + j, i, flag[j], dc[j]);
+    }
+}
+
 // Flush the workgroup's LDS records with one global atomic.
 __device__ __forceinline__ void flush_sink(const CandSink& snk, uint32_t* s_base)
 {
@@ -377,8 +403,9 @@ __device__ __forceinline__ void flush_sink(const CandSink& snk, uint32_t* s_base
 // x (BN*NW) rows (x) of one frame; every wave walks all scales.
 // KMAX > 0: ladders of at most KMAX Gaussian planes; all planes' rows are
 // loaded up front, so a wave waits for memory once.  KMAX == 0: any ladder;
-// plane i+3 is loaded while plane i+1's DoG is formed.
-template <int BN, int NW, int KMAX>
+// plane i+3 is loaded while plane i+1's DoG is formed.  DBG also writes the
+// DoG planes (parity tests only).
+template <int BN, int NW, int KMAX, bool DBG>
 __global__ void __launch_bounds__(64 * NW) k_nms(LaunchArgs a)
 {
     __shared__ uint32_t s_n;
@@ -410,8 +437,7 @@ __global__ void __launch_bounds__(64 * NW) k_nms(LaunchArgs a)
             float Lr[KMAX][BN + 2];
 #pragma unroll
             for (int p = 0; p < KMAX; ++p)
-                if (p <= k)
-                    load_plane_rows<BN>(Lr[p], f, p, x0, voff);
+                load_plane_rows<BN>(Lr[p], f, p <= k ? p : k, x0, voff);
             dog_rows<BN>(Lr[0], Lr[1], ld->sigma[0], x0, f.W, ycol, s3c, dc);
 #pragma unroll
             for (int i = 0; i + 1 < KMAX; ++i) {
@@ -426,12 +452,8 @@ __global__ void __launch_bounds__(64 * NW) k_nms(LaunchArgs a)
                             dn[j] = -INFINITY;
                         }
                     }
-#pragma unroll
-                    for (int j = 0; j < BN; ++j) {
-                        const int x = x0 + j;
-                        emit_row(snk, f, lane, y, x, i, yout && x < f.W, dc[j],
-                                 fmaxf(s3m[j], fmaxf(s3c[j], s3n[j])), thr, plane_sz);
-                    }
+                    emit_plane<BN, DBG>(snk, f, lane, y, x0, i, yout, dc, s3m, s3c, s3n, thr,
+                                        plane_sz);
 #pragma unroll
                     for (int j = 0; j < BN; ++j) {
                         s3m[j] = s3c[j];
@@ -444,14 +466,12 @@ __global__ void __launch_bounds__(64 * NW) k_nms(LaunchArgs a)
             float La[BN + 2], Lb[BN + 2], Lc[BN + 2], Ld[BN + 2];
             load_plane_rows<BN>(La, f, 0, x0, voff);
             load_plane_rows<BN>(Lb, f, 1, x0, voff);
-            if (k >= 2)
-                load_plane_rows<BN>(Lc, f, 2, x0, voff);
+            load_plane_rows<BN>(Lc, f, k >= 2 ? 2 : 1, x0, voff);
             dog_rows<BN>(La, Lb, ld->sigma[0], x0, f.W, ycol, s3c, dc);
             for (int i = 0; i < k; ++i) {
                 // Lb = L_{i+1}, Lc = L_{i+2} (when i + 2 <= k)
                 if (i + 1 < k) {
-                    if (i + 3 <= k)
-                        load_plane_rows<BN>(Ld, f, i + 3, x0, voff);
+                    load_plane_rows<BN>(Ld, f, i + 3 <= k ? i + 3 : k, x0, voff);
                     dog_rows<BN>(Lb, Lc, ld->sigma[i + 1], x0, f.W, ycol, s3n, dn);
 #pragma unroll
                     for (int j = 0; j < BN + 2; ++j) {
@@ -465,12 +485,8 @@ __global__ void __launch_bounds__(64 * NW) k_nms(LaunchArgs a)
                         dn[j] = -INFINITY;
                     }
                 }
-#pragma unroll
-                for (int j = 0; j < BN; ++j) {
-                    const int x = x0 + j;
-                    emit_row(snk, f, lane, y, x, i, yout && x < f.W, dc[j],
-                             fmaxf(s3m[j], fmaxf(s3c[j], s3n[j])), thr, plane_sz);
-                }
+                emit_plane<BN, DBG>(snk, f, lane, y, x0, i, yout, dc, s3m, s3c, s3n, thr,
+                                    plane_sz);
 #pragma unroll
                 for (int j = 0; j < BN; ++j) {
                     s3m[j] = s3c[j];
@@ -513,8 +529,7 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, int n, uint32_t v)
 struct KernelSet {
     const void* pass1;
     const void* pass2;
-    const void* nms;       // any ladder
-    const void* nms_k;     // ladders of at most DOG_NMS_KMAX Gaussian planes
+    const void* nms[2][2];  // [ladder of at most DOG_NMS_KMAX planes][debug planes]
     int S, R, NW, BI, BN, NWN;
 };
 
@@ -524,8 +539,10 @@ static KernelSet make_set()
     KernelSet k;
     k.pass1 = reinterpret_cast<const void*>(&k_pass1<S, R, NW, BI>);
     k.pass2 = reinterpret_cast<const void*>(&k_pass2<S, R, NW, BI>);
-    k.nms = reinterpret_cast<const void*>(&k_nms<BN, NWN, 0>);
-    k.nms_k = reinterpret_cast<const void*>(&k_nms<BN, NWN, DOG_NMS_KMAX>);
+    k.nms[0][0] = reinterpret_cast<const void*>(&k_nms<BN, NWN, 0, false>);
+    k.nms[0][1] = reinterpret_cast<const void*>(&k_nms<BN, NWN, 0, true>);
+    k.nms[1][0] = reinterpret_cast<const void*>(&k_nms<BN, NWN, DOG_NMS_KMAX, false>);
+    k.nms[1][1] = reinterpret_cast<const void*>(&k_nms<BN, NWN, DOG_NMS_KMAX, true>);
     k.S = S;
     k.R = R;
     k.NW = NW;
@@ -572,10 +589,11 @@ int dogk_variant_ring(int v) { return dog::kSets[v].R; }
 // If ev is non-NULL, events ev[0..3] are recorded before, between and after
 // the kernels.  Returns the first launch error.
 hipError_t dogk_launch_sequence(int variant, const dog::LaunchArgs* args, int grid1, int grid2,
-                                int grid3, int max_gauss, hipStream_t stream, hipEvent_t* ev)
+                                int grid3, int max_gauss, int debug, hipStream_t stream,
+                                hipEvent_t* ev)
 {
     const dog::KernelSet& k = dog::kSets[variant];
-    const void* nms = max_gauss <= DOG_NMS_KMAX ? k.nms_k : k.nms;
+    const void* nms = k.nms[max_gauss <= DOG_NMS_KMAX ? 1 : 0][debug ? 1 : 0];
     void* params[] = {const_cast<dog::LaunchArgs*>(args)};
     hipError_t e = hipSuccess;
     if (ev)
@@ -596,11 +614,11 @@ hipError_t dogk_launch_sequence(int variant, const dog::LaunchArgs* args, int gr
 }
 
 hipError_t dogk_launch_nms(int variant, const dog::LaunchArgs* args, int grid3, int max_gauss,
-                           hipStream_t stream)
+                           int debug, hipStream_t stream)
 {
     const dog::KernelSet& k = dog::kSets[variant];
     void* params[] = {const_cast<dog::LaunchArgs*>(args)};
-    return hipLaunchKernel(max_gauss <= DOG_NMS_KMAX ? k.nms_k : k.nms, dim3(grid3),
+    return hipLaunchKernel(k.nms[max_gauss <= DOG_NMS_KMAX ? 1 : 0][debug ? 1 : 0], dim3(grid3),
                            dim3(64 * k.NWN), params, 0, stream);
 }
 
@@ -614,7 +632,7 @@ hipError_t dogk_occupancy(int variant, int* wg1, int* wg2, int* wg3)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(wg2, k.pass2, 64 * k.NW, 0);
     if (e != hipSuccess)
         return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(wg3, k.nms_k, 64 * k.NWN, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(wg3, k.nms[1][0], 64 * k.NWN, 0);
 }
 
 hipError_t dogk_untranspose(const float* src, float* dst, int n_planes, int H, int W,

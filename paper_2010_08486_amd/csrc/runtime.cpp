@@ -138,8 +138,8 @@ static hipError_t enqueue_sequence(dog_context* c, hipStream_t st)
     hipError_t e = hipMemcpyAsync(const_cast<FrameDesc*>(a.frames), c->h_tables.p, c->frames_bytes,
                                   hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
-        e = dogk_launch_sequence(c->variant, &a, a.n1, a.n2, a.n3, c->n_gauss, st,
-                                 c->profiling ? c->ev : nullptr);
+        e = dogk_launch_sequence(c->variant, &a, a.n1, a.n2, a.n3, c->n_gauss,
+                                 c->debug_planes ? 1 : 0, st, c->profiling ? c->ev : nullptr);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->h_cand.p, c->cand.p, sizeof(CandHeader) + kRecBytes * c->guess,
                            hipMemcpyDeviceToHost, st);
@@ -244,10 +244,16 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
     const size_t frames_bytes = sizeof(FrameDesc) * n;
 
     // events recorded inside a graph cannot be timed, so per-kernel timing
-    // issues the same sequence directly
-    const bool use_graph = c->use_graphs && !c->profiling;
+    // issues the same sequence directly.  A layout is captured into a graph
+    // the second time in a row it is seen (a stream of ever-changing batch
+    // compositions is launched directly instead of re-capturing each time).
     std::vector<long long> key = launch_key(c, frames, dbg_D);
-    if (!c->tables_ready || key != c->graph_key) {
+    const bool have_graph = c->graph_exec != nullptr && key == c->graph_key;
+    const bool use_graph =
+        c->use_graphs && !c->profiling && (have_graph || key == c->seen_key);
+    c->seen_key = key;
+    const bool tables_ok = c->tables_ready && key == c->graph_key;
+    if (!tables_ok || (use_graph && !have_graph)) {
         drop_graph(c);
         // ---- tile tables.  Each (frame, plane) unit's column blocks are cut
         // into DOG_NXCD contiguous slices and slice s goes to XCD (s + frame) %
@@ -339,6 +345,7 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
         if ((rc = ctx_pin(&c->h_tables, tbytes)) != DOG_OK)
             return rc;
         key = launch_key(c, frames, dbg_D);  // buffers may have moved
+        c->seen_key = key;
         char* dt = static_cast<char*>(c->tables.p);
         char* h = static_cast<char*>(c->h_tables.p);
         std::memcpy(h + o_frames, fd.data(), frames_bytes);
@@ -364,6 +371,7 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
         a.n2 = (int)t2;
         a.n3 = (int)t3;
         c->n_gauss = n_g;
+        c->debug_planes = dbg_D;
         // readback size fixed in the captured sequence: header + a guess of
         // the record count (more is copied afterwards if needed)
         c->guess = std::min<uint32_t>(
@@ -404,7 +412,7 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
         DOG_HIP(hipEventRecord(c->ev_in, s));
         DOG_HIP(hipStreamWaitEvent(c->stream, c->ev_in, 0));
     }
-    if (use_graph)
+    if (use_graph && c->graph_exec)
         DOG_HIP(hipGraphLaunch(c->graph_exec, c->stream));
     else
         DOG_HIP(enqueue_sequence(c, c->stream));
@@ -434,7 +442,7 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
         a.cand = static_cast<CandHeader*>(c->cand.p);
         a.cap = c->cap;
         DOG_HIP(dogk_fill_u32(&a.cand->count, 1, 0u, c->stream));
-        DOG_HIP(dogk_launch_nms(c->variant, &a, a.n3, n_g, c->stream));
+        DOG_HIP(dogk_launch_nms(c->variant, &a, a.n3, n_g, c->debug_planes ? 1 : 0, c->stream));
         DOG_HIP(hipMemcpyAsync(c->h_cand.p, c->cand.p, sizeof(CandHeader) + kRecBytes * count,
                                hipMemcpyDeviceToHost, c->stream));
         DOG_HIP(hipStreamSynchronize(c->stream));

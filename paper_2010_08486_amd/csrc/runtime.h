@@ -69,6 +69,15 @@ struct Variant {
     int nms_band() const { return BN * NWN; }
 };
 
+const char* last_error();
+int check_image(const void* p, int64_t h, int64_t w, int64_t stride);
+int export_blobs(const std::vector<dog_blob>& v, dog_blob** out, int64_t* n);
+
+// Detector on n frames (host or device pixels) with results per frame; see
+// dog_detect_batch.
+int detect_frames(dog_context* ctx, const dog_params* params, int32_t n_frames,
+                  const dog_frame* frames, hipStream_t s, dog_result* results);
+
 }  // namespace dog
 
 // Kernel launchers (kernels.hip).
@@ -77,9 +86,10 @@ int dogk_num_variants();
 void dogk_variant_geometry(int v, int* S, int* NW, int* BI, int* BN, int* NWN);
 int dogk_variant_ring(int v);
 hipError_t dogk_launch_sequence(int variant, const dog::LaunchArgs* args, int grid1, int grid2,
-                                int grid3, int max_gauss, hipStream_t stream, hipEvent_t* ev);
+                                int grid3, int max_gauss, int debug, hipStream_t stream,
+                                hipEvent_t* ev);
 hipError_t dogk_launch_nms(int variant, const dog::LaunchArgs* args, int grid3, int max_gauss,
-                           hipStream_t stream);
+                           int debug, hipStream_t stream);
 hipError_t dogk_untranspose(const float* src, float* dst, int n_planes, int H, int W,
                             long long pitch, hipStream_t stream);
 hipError_t dogk_fill_u32(uint32_t* p, int n, uint32_t v, hipStream_t stream);
@@ -118,8 +128,10 @@ struct dog_context {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     std::vector<long long> graph_key;
+    std::vector<long long> seen_key;   // layout of the previous call
     dog::LaunchArgs args;
     int n_gauss = 0;
+    bool debug_planes = false;     // the current tables write the DoG planes
     size_t frames_bytes = 0;       // frame table bytes uploaded per launch
     uint32_t guess = 0;            // records read back by the captured sequence
     bool tables_ready = false;     // device tables match graph_key
@@ -147,5 +159,14 @@ void drop_graph(dog_context* c);
 int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames,
                hipStream_t s, std::vector<std::vector<dog_blob>>* out, bool dbg_D,
                long long* pitch0, float** L0, float** D0);
+
+const char* last_error();
+int check_image(const void* p, int64_t h, int64_t w, int64_t stride);
+int export_blobs(const std::vector<dog_blob>& v, dog_blob** out, int64_t* n);
+
+// Detector on n frames (host or device pixels) with results per frame; see
+// dog_detect_batch.
+int detect_frames(dog_context* ctx, const dog_params* params, int32_t n_frames,
+                  const dog_frame* frames, hipStream_t s, dog_result* results);
 
 }  // namespace dog

@@ -1,0 +1,448 @@
+// Serving loop: requests (host frames) arrive at any time; a dispatcher thread
+// forms batches from whatever is waiting, bounded by a frame count and by the
+// device footprint still free in the admission budget, and hands each batch
+// to an idle slot.  Every slot owns a context (workspace, stream, cached
+// launch graph) and a worker thread, so batches launched while others are
+// running overlap on the device.  Results are kept per ticket with arrival
+// and completion times for latency statistics.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <thread>
+#include <unordered_map>
+#include <unordered_set>
+
+#include "runtime.h"
+
+namespace {
+
+int64_t now_ns()
+{
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+struct Request {
+    uint64_t ticket;
+    std::vector<float> pixels;  // dense copy, row stride = width
+    int64_t H, W;
+    int64_t t_arrive;
+    uint64_t footprint;
+};
+
+struct Slot {
+    dog_context* ctx = nullptr;
+    std::thread th;
+    std::vector<Request> batch;
+    bool has_work = false;
+};
+
+}  // namespace
+
+struct dog_server {
+    dog_params prm{};
+    dog_server_opts opts{};
+    int n_g = 0;
+    uint64_t budget = 0;
+
+    std::mutex mu;
+    std::condition_variable cv_dispatch;  // queue grew or a slot became idle
+    std::condition_variable cv_done;      // a batch completed
+    std::deque<Request> queue;
+    std::vector<std::unique_ptr<Slot>> slots;
+    std::condition_variable cv_slot;      // a slot got work (or stop)
+    std::unordered_map<uint64_t, dog_result> done;
+    std::unordered_set<uint64_t> pending;  // queued or running
+    uint64_t next_ticket = 1;
+    uint64_t reserved = 0;                 // footprint of batches in flight
+    uint64_t peak_reserved = 0;
+    bool stop = false;
+    std::thread dispatcher;
+
+    // statistics
+    std::vector<double> lat_ms;
+    int64_t submitted = 0, completed = 0, failed = 0, rejected = 0, batches = 0, batch_frames = 0;
+    int64_t running = 0;
+    int64_t t_first = 0, t_last = 0;
+};
+
+namespace {
+
+uint64_t frame_footprint(int n_g, int64_t H, int64_t W)
+{
+    const uint64_t pitch = ((uint64_t)H + 63) / 64 * 64;
+    return 2ull * (uint64_t)n_g * (uint64_t)W * pitch * sizeof(float) +
+           (uint64_t)H * (uint64_t)W * sizeof(float) + 4096;
+}
+
+void run_slot(dog_server* sv, Slot* sl)
+{
+    for (;;) {
+        std::vector<Request> batch;
+        {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            sv->cv_slot.wait(lk, [&] { return sl->has_work || sv->stop; });
+            if (!sl->has_work)
+                return;
+            batch.swap(sl->batch);
+        }
+        const int n = (int)batch.size();
+        std::vector<dog_result> res(n);
+        int rc = DOG_OK;
+        if (sv->opts.dry_run) {
+            double mpx = 0;
+            for (const Request& r : batch)
+                mpx += (double)r.H * (double)r.W * 1e-6;
+            const int64_t us = (int64_t)(sv->opts.dry_run_us_per_mpx * mpx);
+            std::this_thread::sleep_for(std::chrono::microseconds(us));
+            for (dog_result& r : res)
+                std::memset(&r, 0, sizeof(r));
+        } else {
+            std::vector<dog_frame> fr(n);
+            for (int i = 0; i < n; ++i) {
+                fr[i].data = batch[i].pixels.data();
+                fr[i].height = batch[i].H;
+                fr[i].width = batch[i].W;
+                fr[i].row_stride = batch[i].W;
+                fr[i].on_device = 0;
+                fr[i].reserved = 0;
+            }
+            rc = dog::detect_frames(sl->ctx, &sv->prm, n, fr.data(), sl->ctx->stream, res.data());
+        }
+        const int64_t t_done = now_ns();
+        uint64_t freed = 0;
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            for (int i = 0; i < n; ++i) {
+                dog_result r = res[i];
+                if (rc != DOG_OK && r.status == DOG_OK)
+                    r.status = rc;
+                r.t_arrive_ns = batch[i].t_arrive;
+                r.t_done_ns = t_done;
+                if (r.status == DOG_OK) {
+                    sv->completed += 1;
+                    sv->lat_ms.push_back((double)(t_done - batch[i].t_arrive) * 1e-6);
+                } else {
+                    sv->failed += 1;
+                }
+                sv->pending.erase(batch[i].ticket);
+                sv->done[batch[i].ticket] = r;
+                freed += batch[i].footprint;
+            }
+            sv->reserved -= freed;
+            sv->running -= n;
+            sv->t_last = std::max(sv->t_last, t_done);
+            sl->has_work = false;
+        }
+        sv->cv_done.notify_all();
+        sv->cv_dispatch.notify_all();
+    }
+}
+
+// Dispatcher: whenever requests wait and a slot is idle, launch a batch of
+// the oldest requests that fit in the free admission budget.
+void run_dispatcher(dog_server* sv)
+{
+    std::unique_lock<std::mutex> lk(sv->mu);
+    for (;;) {
+        Slot* idle = nullptr;
+        sv->cv_dispatch.wait(lk, [&] {
+            if (sv->stop)
+                return true;
+            if (sv->queue.empty())
+                return false;
+            for (auto& s : sv->slots)
+                if (!s->has_work)
+                    return true;
+            return false;
+        });
+        if (sv->stop)
+            return;
+        for (auto& s : sv->slots)
+            if (!s->has_work) {
+                idle = s.get();
+                break;
+            }
+        // batching window: give a short batch a chance to grow
+        if (sv->opts.max_wait_ms > 0.0 && (int)sv->queue.size() < sv->opts.max_batch_frames) {
+            const int64_t deadline =
+                sv->queue.front().t_arrive + (int64_t)(sv->opts.max_wait_ms * 1e6);
+            const int64_t now = now_ns();
+            if (now < deadline) {
+                sv->cv_dispatch.wait_for(lk, std::chrono::nanoseconds(deadline - now));
+                continue;
+            }
+        }
+        std::vector<Request> batch;
+        uint64_t fp = 0;
+        while (!sv->queue.empty() && (int)batch.size() < sv->opts.max_batch_frames) {
+            const Request& r = sv->queue.front();
+            if (sv->reserved + fp + r.footprint > sv->budget)
+                break;  // admission: wait until running batches free memory
+            fp += r.footprint;
+            batch.push_back(std::move(sv->queue.front()));
+            sv->queue.pop_front();
+        }
+        if (batch.empty()) {
+            // the oldest request does not fit while other batches run
+            sv->cv_done.wait(lk);
+            continue;
+        }
+        sv->reserved += fp;
+        sv->peak_reserved = std::max(sv->peak_reserved, sv->reserved);
+        sv->running += (int64_t)batch.size();
+        sv->batches += 1;
+        sv->batch_frames += (int64_t)batch.size();
+        idle->batch = std::move(batch);
+        idle->has_work = true;
+        sv->cv_slot.notify_all();
+    }
+}
+
+void destroy_server(dog_server* sv)
+{
+    if (!sv)
+        return;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+    }
+    sv->cv_dispatch.notify_all();
+    sv->cv_done.notify_all();
+    if (sv->dispatcher.joinable())
+        sv->dispatcher.join();
+    // slots finish the batch they hold, then exit
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+    }
+    sv->cv_slot.notify_all();
+    for (auto& s : sv->slots) {
+        if (s->th.joinable())
+            s->th.join();
+        if (s->ctx)
+            dog_context_destroy(s->ctx);
+    }
+    for (auto& kv : sv->done)
+        std::free(kv.second.blobs);
+    for (Request& r : sv->queue)
+        (void)r;
+    delete sv;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dog_server_create(int device, const dog_params* params, const dog_server_opts* opts,
+                      dog_server** out)
+{
+    if (!params || !out) {
+        dog::set_error("invalid argument");
+        return DOG_EINVAL;
+    }
+    *out = nullptr;
+    dog::Plan P;
+    std::string err;
+    int rc = dog::build_plan(*params, &P, &err);
+    if (rc != DOG_OK) {
+        dog::set_error(err);
+        return rc;
+    }
+    std::unique_ptr<dog_server> sv(new dog_server());
+    sv->prm = *params;
+    if (opts)
+        sv->opts = *opts;
+    if (sv->opts.max_batch_frames <= 0)
+        sv->opts.max_batch_frames = 16;
+    if (sv->opts.slots <= 0)
+        sv->opts.slots = 2;
+    if (sv->opts.queue_capacity <= 0)
+        sv->opts.queue_capacity = 4096;
+    if (sv->opts.max_wait_ms < 0.0 || sv->opts.dry_run_us_per_mpx < 0.0) {
+        dog::set_error("negative batching window or dry-run time");
+        return DOG_EINVAL;
+    }
+    sv->n_g = P.n_g;
+    sv->budget = sv->opts.hbm_budget_bytes;
+    if (!sv->opts.dry_run) {
+        for (int i = 0; i < sv->opts.slots; ++i) {
+            auto sl = std::make_unique<Slot>();
+            rc = dog_context_create(device, sv->budget, &sl->ctx);
+            if (rc != DOG_OK) {
+                for (auto& s : sv->slots)
+                    dog_context_destroy(s->ctx);
+                return rc;
+            }
+            sv->slots.push_back(std::move(sl));
+        }
+        if (sv->budget == 0)
+            sv->budget = sv->slots[0]->ctx->budget;
+    } else {
+        for (int i = 0; i < sv->opts.slots; ++i)
+            sv->slots.push_back(std::make_unique<Slot>());
+        if (sv->budget == 0)
+            sv->budget = 1ull << 40;
+    }
+    dog_server* raw = sv.release();
+    for (auto& s : raw->slots) {
+        Slot* sp = s.get();
+        sp->th = std::thread(run_slot, raw, sp);
+    }
+    raw->dispatcher = std::thread(run_dispatcher, raw);
+    *out = raw;
+    return DOG_OK;
+}
+
+int dog_server_submit(dog_server* sv, const dog_frame* frame, uint64_t* ticket)
+{
+    if (!sv || !frame || !ticket) {
+        dog::set_error("invalid argument");
+        return DOG_EINVAL;
+    }
+    *ticket = 0;
+    int rc = dog::check_image(frame->data, frame->height, frame->width, frame->row_stride);
+    if (rc != DOG_OK)
+        return rc;
+    if (frame->on_device) {
+        dog::set_error("the server takes host frames");
+        return DOG_EINVAL;
+    }
+    Request r;
+    r.H = frame->height;
+    r.W = frame->width;
+    r.footprint = frame_footprint(sv->n_g, r.H, r.W);
+    if (r.footprint > sv->budget) {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->rejected += 1;
+        dog::set_error("frame footprint exceeds the server's HBM budget");
+        return DOG_ENOMEM;
+    }
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if ((int64_t)sv->queue.size() >= sv->opts.queue_capacity) {
+            sv->rejected += 1;
+            dog::set_error("server queue full");
+            return DOG_EBUSY;
+        }
+    }
+    r.t_arrive = now_ns();
+    r.pixels.resize((size_t)r.H * (size_t)r.W);
+    for (int64_t y = 0; y < r.H; ++y)
+        std::memcpy(r.pixels.data() + y * r.W, frame->data + y * frame->row_stride,
+                    (size_t)r.W * sizeof(float));
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        r.ticket = sv->next_ticket++;
+        *ticket = r.ticket;
+        sv->pending.insert(r.ticket);
+        sv->submitted += 1;
+        if (sv->t_first == 0)
+            sv->t_first = r.t_arrive;
+        sv->queue.push_back(std::move(r));
+    }
+    sv->cv_dispatch.notify_all();
+    return DOG_OK;
+}
+
+static int take_result(dog_server* sv, uint64_t ticket, dog_result* out)
+{
+    auto it = sv->done.find(ticket);
+    if (it == sv->done.end())
+        return sv->pending.count(ticket) ? DOG_EAGAIN : DOG_ENOTFOUND;
+    *out = it->second;
+    sv->done.erase(it);
+    return DOG_OK;
+}
+
+int dog_server_poll(dog_server* sv, uint64_t ticket, dog_result* out)
+{
+    if (!sv || !out) {
+        dog::set_error("invalid argument");
+        return DOG_EINVAL;
+    }
+    std::memset(out, 0, sizeof(*out));
+    std::lock_guard<std::mutex> lk(sv->mu);
+    const int rc = take_result(sv, ticket, out);
+    if (rc == DOG_ENOTFOUND)
+        dog::set_error("unknown ticket");
+    return rc;
+}
+
+int dog_server_wait(dog_server* sv, uint64_t ticket, dog_result* out)
+{
+    if (!sv || !out) {
+        dog::set_error("invalid argument");
+        return DOG_EINVAL;
+    }
+    std::memset(out, 0, sizeof(*out));
+    std::unique_lock<std::mutex> lk(sv->mu);
+    for (;;) {
+        const int rc = take_result(sv, ticket, out);
+        if (rc != DOG_EAGAIN) {
+            if (rc == DOG_ENOTFOUND)
+                dog::set_error("unknown ticket");
+            return rc;
+        }
+        sv->cv_done.wait(lk);
+    }
+}
+
+int dog_server_drain(dog_server* sv)
+{
+    if (!sv) {
+        dog::set_error("invalid argument");
+        return DOG_EINVAL;
+    }
+    std::unique_lock<std::mutex> lk(sv->mu);
+    sv->cv_done.wait(lk, [&] { return sv->pending.empty(); });
+    return DOG_OK;
+}
+
+int dog_server_stats(dog_server* sv, dog_stats* out)
+{
+    if (!sv || !out) {
+        dog::set_error("invalid argument");
+        return DOG_EINVAL;
+    }
+    std::memset(out, 0, sizeof(*out));
+    std::lock_guard<std::mutex> lk(sv->mu);
+    out->submitted = sv->submitted;
+    out->completed = sv->completed;
+    out->failed = sv->failed;
+    out->rejected = sv->rejected;
+    out->queued = (int64_t)sv->queue.size();
+    out->running = sv->running;
+    out->batches = sv->batches;
+    out->mean_batch_frames = sv->batches ? (double)sv->batch_frames / (double)sv->batches : 0.0;
+    out->reserved_bytes = sv->reserved;
+    out->peak_reserved_bytes = sv->peak_reserved;
+    if (!sv->lat_ms.empty()) {
+        std::vector<double> v = sv->lat_ms;
+        std::sort(v.begin(), v.end());
+        auto q = [&](double p) {
+            // linear interpolation between closest ranks
+            const double pos = p * (double)(v.size() - 1);
+            const size_t i = (size_t)pos;
+            const double f = pos - (double)i;
+            return i + 1 < v.size() ? v[i] * (1.0 - f) + v[i + 1] * f : v[i];
+        };
+        out->p50_ms = q(0.50);
+        out->p99_ms = q(0.99);
+        double s = 0;
+        for (double x : v)
+            s += x;
+        out->mean_ms = s / (double)v.size();
+        out->max_ms = v.back();
+    }
+    if (sv->t_last > sv->t_first && sv->completed > 0)
+        out->frames_per_s = (double)sv->completed / ((double)(sv->t_last - sv->t_first) * 1e-9);
+    return DOG_OK;
+}
+
+void dog_server_destroy(dog_server* sv) { destroy_server(sv); }
+
+}  // extern "C"
