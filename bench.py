@@ -12,11 +12,18 @@ Also printed in the same JSON line:
     kernel on the library stream during a second run of the same steps
     (issued directly: events inside a replayed graph cannot be timed);
   * per-frame latency p50/p99 of the timed steps;
-  * the same 64-frame uniform batch through the batched entry point vs one
-    frame at a time (throughput ratio and latency);
+  * the autotuner's per-variant timings for the frame and its choice;
+  * a uniform batch of 64 1024x1024 frames through the batched entry point
+    vs one frame at a time (throughput ratio and latency);
+  * an uneven batch of 128 frames (sides 256..2048, square and 2:1 crops):
+    batched vs per-frame on device frames, and the server at saturation vs
+    the plain host entry point frame by frame;
+  * the server fed by a Poisson stream of mixed frames (200 frames/s):
+    p50/p99 latency and sustained frames/s;
   * the FP64 CPU oracle timed on this host on a bounded sample.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-batch] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-batch] [--no-mixed]
+                    [--no-serve] [--serve-seconds S] [--no-cpu] [--variant V]
 """
 from __future__ import annotations
 
@@ -68,6 +75,34 @@ def measured_traffic(kernel: str):
     return float(vals[key]) if key in vals else None
 
 
+def _gen(args):
+    import synth
+    kind, a = args
+    if kind == "batch64":
+        return synth.batch64(n_frames=1, first_seed=1000 + a)[0]
+    H, W = a[1], a[2]
+    return synth.mixed_frame(a[0], H, W)
+
+
+def generate_inputs(want_batch: bool, want_mixed: bool, workers: int):
+    """Synthetic frames of the batch workloads, generated in worker processes
+    before this process touches the GPU."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import synth
+    jobs = []
+    if want_batch:
+        jobs += [("batch64", f) for f in range(64)]
+    if want_mixed:
+        jobs += [("mixed", (f, H, W)) for f, (H, W) in enumerate(synth.mixed_shapes())]
+    if not jobs:
+        return [], []
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+        frames = list(ex.map(_gen, jobs, chunksize=2))
+    nb = 64 if want_batch else 0
+    return frames[:nb], frames[nb:]
+
+
 def cpu_baseline(img, prm, k, budget_s=12.0):
     import oracle
     oracle.build()
@@ -86,6 +121,109 @@ def cpu_baseline(img, prm, k, budget_s=12.0):
                       "1024x1024 frame, %.1f s total" % (reps, t_total)}
 
 
+def bench_mixed(dog, torch, ctx, prm, k, frames, steps):
+    """Uneven batch of 128 frames: one batched launch sequence vs a launch per
+    frame (device frames), and the server at saturation vs the plain host
+    entry point frame by frame (host frames)."""
+    dev = torch.device("cuda:0")
+    dfr = [torch.from_numpy(f).to(dev) for f in frames]
+    tot = sum(f.shape[0] * f.shape[1] for f in frames) * k / 1e6
+    shapes = sorted({f.shape for f in frames}, key=lambda s: s[0] * s[1])
+    choice = {}
+    for shp in shapes:   # the autotuner picks a variant per frame size
+        f = next(t for t in dfr if tuple(t.shape) == shp)
+        choice["%dx%d" % shp] = ctx.autotune(f, prm, reps=3)[0]
+    torch.cuda.synchronize()
+    ctx.detect_batch(dfr, prm)
+    ctx.detect_batch(dfr, prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res, _ = ctx.detect_batch(dfr, prm)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / steps
+    for f in dfr[:8]:
+        ctx.detect_device(f, prm)
+    torch.cuda.synchronize()
+    per = []
+    t0 = time.perf_counter()
+    for f in dfr:
+        s0 = time.perf_counter()
+        ctx.detect_device(f, prm)
+        per.append(time.perf_counter() - s0)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    del dfr
+    # host frames: plain per-frame entry point vs the server fed all at once
+    for f in frames[:4]:
+        dog.detect(f, prm.sigma_min, prm.sigma_max, prm.sigma_ratio, prm.threshold, prm.overlap)
+    t0 = time.perf_counter()
+    for f in frames:
+        dog.detect(f, prm.sigma_min, prm.sigma_max, prm.sigma_ratio, prm.threshold, prm.overlap)
+    th = time.perf_counter() - t0
+    sv = dog.Server(prm, slots=2, max_batch_frames=32)
+    try:
+        for f in frames[:8]:
+            sv.wait(sv.submit(f))
+        t0 = time.perf_counter()
+        tickets = [sv.submit(f) for f in frames]
+        for tk in tickets:
+            sv.wait(tk)
+        ts = time.perf_counter() - t0
+        st = sv.stats()
+    finally:
+        sv.close()
+    return {"frames": len(frames), "mpixel_scales": round(tot, 1),
+            "autotuned_variant_per_shape": choice,
+            "batched_mpx_scales_per_s": round(tot / tb, 1),
+            "per_frame_device_mpx_scales_per_s": round(tot / tp, 1),
+            "batched_over_per_frame_device": round(tp / tb, 3),
+            "batched_ms_per_batch": round(tb * 1e3, 3),
+            "per_frame_device_p50_ms": round(pct(per, 50) * 1e3, 4),
+            "per_frame_device_p99_ms": round(pct(per, 99) * 1e3, 4),
+            "host_per_frame_mpx_scales_per_s": round(tot / th, 1),
+            "served_saturated_mpx_scales_per_s": round(tot / ts, 1),
+            "served_over_host_per_frame": round(th / ts, 3),
+            "served_mean_batch_frames": round(st["mean_batch_frames"], 2)}
+
+
+def bench_serving(dog, prm, k, pool, rate, seconds):
+    """The server fed by a Poisson stream: frames drawn in turn from the pool
+    of uneven frames, submitted at their arrival times."""
+    import synth
+    arrivals = synth.poisson_arrivals(rate=rate, duration=seconds)
+    sv = dog.Server(prm, slots=2, max_batch_frames=16)
+    try:
+        for f in pool[:8]:
+            sv.wait(sv.submit(f))
+        base = sv.stats()
+        tickets = []
+        t0 = time.perf_counter()
+        for i, ta in enumerate(arrivals):
+            while True:
+                now = time.perf_counter() - t0
+                if now >= ta:
+                    break
+                time.sleep(min(ta - now, 0.002))
+            tickets.append(sv.submit(pool[i % len(pool)]))
+        lat = []
+        for tk in tickets:
+            _, info = sv.wait(tk)
+            lat.append((info["t_done_ns"] - info["t_arrive_ns"]) / 1e6)
+        wall = time.perf_counter() - t0
+        st = sv.stats()
+    finally:
+        sv.close()
+    mpx = sum(pool[i % len(pool)].size for i in range(len(arrivals))) * k / 1e6
+    return {"rate_fps": rate, "seconds": seconds, "frames": len(arrivals),
+            "p50_ms": round(pct(lat, 50), 3), "p99_ms": round(pct(lat, 99), 3),
+            "max_ms": round(max(lat), 3),
+            "sustained_fps": round(len(arrivals) / wall, 1),
+            "mpx_scales_per_s": round(mpx / wall, 1),
+            "batches": st["batches"] - base["batches"],
+            "peak_reserved_gib": round(st["peak_reserved_bytes"] / 2**30, 3)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +231,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--pmc-workload", type=int, default=0,
@@ -107,11 +249,16 @@ def main() -> int:
         return 2
 
     import numpy as np
-    import torch
 
     import paper_2010_08486_amd as dog
     import synth
 
+    pmc = args.pmc_workload > 0
+    want_mixed = not pmc and not (args.no_mixed and args.no_serve)
+    batch_frames, mixed_frames = generate_inputs(not pmc and not args.no_batch, want_mixed,
+                                                 workers=min(16, os.cpu_count() or 1))
+
+    import torch
     dev = torch.device("cuda:0")
     prm = dog.Params(1.0, 30.0, 1.6, 0.05, 0.5)
     info = dog.plan_info(prm)
@@ -121,8 +268,13 @@ def main() -> int:
     H, W = img.shape
     t_img = torch.from_numpy(img).to(dev)
     ctx = dog.Context(0)
+    tune = None
     if args.variant >= 0:
         ctx.set_variant(args.variant)
+    elif not pmc:
+        v, us = ctx.autotune(t_img, prm, reps=5)
+        tune = {"variant": v, "geometry": dog.variant_info(v),
+                "kernel_us_per_variant": [round(u, 2) for u in us]}
 
     if args.pmc_workload > 0:
         for _ in range(args.pmc_workload):
@@ -199,11 +351,12 @@ def main() -> int:
            "kernel_ms_per_frame": round(kernel_sum_ms, 4),
            "eager_ms_per_step": round(dt_eager / args.steps * 1e3, 4),
            "kernel_only_mpx_scales_per_s": round(mpx / (kernel_sum_ms * 1e-3), 1),
-           "blobs": int(len(blobs))}
+           "blobs": int(len(blobs)),
+           "autotune": tune}
 
     # ---- uniform batch of 64 frames: batched entry point vs frame by frame
     if not args.no_batch:
-        frames = synth.batch64()
+        frames = batch_frames
         dfr = [torch.from_numpy(f).to(dev) for f in frames]
         torch.cuda.synchronize()
         ctx.detect_batch(dfr, prm)
@@ -232,6 +385,12 @@ def main() -> int:
                           "per_frame_p99_ms": round(pct(per, 99) * 1e3, 4),
                           "batched_frame_latency_ms": round(tb * 1e3, 3)}
         del dfr
+
+    if not args.no_mixed:
+        out["mixed128"] = bench_mixed(dog, torch, ctx, prm, k, mixed_frames, args.batch_steps)
+    if not args.no_serve:
+        out["serving"] = bench_serving(dog, prm, k, mixed_frames, args.serve_rate,
+                                       args.serve_seconds)
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(img, prm, k)

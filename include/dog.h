@@ -179,13 +179,41 @@ int dog_debug_candidates(dog_context* ctx, const float* d_image, int64_t height,
                          int64_t row_stride, const dog_params* params, dog_blob** blobs_out,
                          int64_t* count_out);
 
-/* Kernel variant (tile geometry) selection.  variant < 0 restores the
- * autotuned choice.  dog_num_variants() variants exist; dog_variant_info
- * describes one: S outputs per lane, waves per workgroup, strips per wave,
- * local-maximum rows per wave. */
+/* Kernel variant (tile geometry) selection.  Every variant computes bitwise
+ * identical results (same taps, same summation order); they differ only in
+ * speed.  dog_num_variants() variants exist; dog_variant_info describes one:
+ * S outputs per lane, waves per workgroup, strips per wave, local-maximum
+ * rows per wave.  dog_set_variant(ctx, v >= 0) pins variant v for every
+ * launch of the context; v < 0 returns to automatic selection (the tuned
+ * choice of the launch's dominant frame shape when one exists, see below,
+ * else the built-in default). */
 int dog_num_variants(void);
 int dog_variant_info(int variant, int32_t* S, int32_t* waves, int32_t* strips, int32_t* nms_rows);
 int dog_set_variant(dog_context* ctx, int variant);
+
+/* Autotuner.  dog_autotune times every variant on the device image d_image
+ * (height x width floats, row_stride >= width elements apart, on the
+ * context's device) with the per-kernel event timing below: one untimed
+ * launch then `reps` timed ones (reps = 0 means 5), and records the variant
+ * with the least summed kernel time as the choice for (height, width, the
+ * blur radii of params).  us_out (may be NULL) receives the mean microseconds
+ * of every variant (dog_num_variants() doubles); *variant_out (may be NULL)
+ * the winner.  A launch whose dominant shape (most pixels) was not tuned uses
+ * the choice of the tuned shape with the same radii nearest in pixel count.
+ * The variant pinned with dog_set_variant is restored afterwards.
+ * dog_autotune_save writes the choices as JSON to `path`; dog_autotune_load
+ * adds those of a file written for the same architecture and kernel build
+ * (a file of another build loads nothing and is not an error).
+ * dog_autotune_choice reports the variant automatic selection would take for
+ * one frame of the given shape.  Errors: DOG_EINVAL (NULL pointer, bad shape
+ * or parameters, unreadable or unwritable file), device errors. */
+int dog_autotune(dog_context* ctx, const dog_params* params, const float* d_image, int64_t height,
+                 int64_t width, int64_t row_stride, int32_t reps, int32_t* variant_out,
+                 double* us_out);
+int dog_autotune_save(dog_context* ctx, const char* path);
+int dog_autotune_load(dog_context* ctx, const char* path);
+int dog_autotune_choice(dog_context* ctx, const dog_params* params, int64_t height, int64_t width,
+                        int32_t* variant_out);
 
 /* Launch mode: on (default) = the launch sequence of a table layout (frame
  * table upload, the three kernels, candidate readback) is captured once into
@@ -224,6 +252,8 @@ typedef struct {
     uint64_t hbm_budget_bytes;  /* admission budget (0: the slot context's budget)   */
     double max_wait_ms;         /* batching window (0: launch whatever waits)        */
     double dry_run_us_per_mpx;
+    const char* tune_cache;     /* autotuner choices (dog_autotune_save) loaded into
+                                   every slot context, or NULL                        */
 } dog_server_opts;
 
 typedef struct {

@@ -62,7 +62,7 @@ class dog_server_opts(ctypes.Structure):
     _fields_ = [("max_batch_frames", ctypes.c_int32), ("slots", ctypes.c_int32),
                 ("queue_capacity", ctypes.c_int32), ("dry_run", ctypes.c_int32),
                 ("hbm_budget_bytes", ctypes.c_uint64), ("max_wait_ms", ctypes.c_double),
-                ("dry_run_us_per_mpx", ctypes.c_double)]
+                ("dry_run_us_per_mpx", ctypes.c_double), ("tune_cache", ctypes.c_char_p)]
 
 
 class dog_stats(ctypes.Structure):
@@ -136,6 +136,11 @@ def lib() -> ctypes.CDLL:
         "dog_set_profiling": (ctypes.c_int, [vp, i32]),
         "dog_set_graph_mode": (ctypes.c_int, [vp, i32]),
         "dog_kernel_times": (ctypes.c_int, [vp, ctypes.POINTER(dbl), pi64]),
+        "dog_autotune": (i32, [vp, ctypes.POINTER(dog_params), vp, i64, i64, i64, i32,
+                               ctypes.POINTER(i32), ctypes.POINTER(dbl)]),
+        "dog_autotune_save": (i32, [vp, ctypes.c_char_p]),
+        "dog_autotune_load": (i32, [vp, ctypes.c_char_p]),
+        "dog_autotune_choice": (i32, [vp, ctypes.POINTER(dog_params), i64, i64, ctypes.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -242,6 +247,31 @@ class Context:
 
     def set_variant(self, v: int) -> None:
         _check(lib().dog_set_variant(self._h, v))
+
+    def autotune(self, image, params: Params, reps: int = 5):
+        """dog_autotune on a 2-D float32 CUDA tensor.  Returns (winning
+        variant, list of mean microseconds per variant)."""
+        import torch
+        ptr, H, W, st = _tensor_image(image)
+        torch.cuda.synchronize(image.device)
+        nv = num_variants()
+        us = (ctypes.c_double * nv)()
+        v = ctypes.c_int32(-1)
+        prm = params.c()
+        _check(lib().dog_autotune(self._h, ctypes.byref(prm), ptr, H, W, st, reps, ctypes.byref(v), us))
+        return v.value, list(us)
+
+    def autotune_save(self, path: str) -> None:
+        _check(lib().dog_autotune_save(self._h, os.fsencode(path)))
+
+    def autotune_load(self, path: str) -> None:
+        _check(lib().dog_autotune_load(self._h, os.fsencode(path)))
+
+    def autotune_choice(self, params: Params, height: int, width: int) -> int:
+        v = ctypes.c_int32(-1)
+        prm = params.c()
+        _check(lib().dog_autotune_choice(self._h, ctypes.byref(prm), height, width, ctypes.byref(v)))
+        return v.value
 
     def set_graph_mode(self, on: bool) -> None:
         _check(lib().dog_set_graph_mode(self._h, 1 if on else 0))
@@ -364,10 +394,11 @@ class Server:
     def __init__(self, params: Params, device: int = 0, max_batch_frames: int = 16,
                  slots: int = 2, queue_capacity: int = 4096, hbm_budget_bytes: int = 0,
                  max_wait_ms: float = 0.0, dry_run: bool = False,
-                 dry_run_us_per_mpx: float = 0.0):
+                 dry_run_us_per_mpx: float = 0.0, tune_cache: str | None = None):
         self._h = ctypes.c_void_p()
         opts = dog_server_opts(max_batch_frames, slots, queue_capacity, 1 if dry_run else 0,
-                               hbm_budget_bytes, max_wait_ms, dry_run_us_per_mpx)
+                               hbm_budget_bytes, max_wait_ms, dry_run_us_per_mpx,
+                               os.fsencode(tune_cache) if tune_cache else None)
         prm = params.c()
         _check(lib().dog_server_create(device, ctypes.byref(prm), ctypes.byref(opts),
                                        ctypes.byref(self._h)))

@@ -8,6 +8,7 @@ generation disabled (-Xclang -target-feature -Xclang -packed-fp32-ops).
 from __future__ import annotations
 
 import concurrent.futures as cf
+import hashlib
 import os
 import subprocess
 import sys
@@ -29,9 +30,21 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Wall", "-Wno-unused-command-line-argument"]
 
 
+def kernel_hash() -> str:
+    """First 16 hex digits of the SHA-256 of the kernel source and its shared
+    header; names the kernel build in autotuner caches."""
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "dog_internal.h"):
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     cmd = [HIPCC] + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
+    if src == "autotune.cpp":
+        cmd.append('-DDOG_KERNEL_HASH="%s"' % kernel_hash())
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -134,7 +134,10 @@ int dog_set_variant(dog_context* ctx, int variant)
     int rc = use_device(ctx);
     if (rc != DOG_OK)
         return rc;
-    return ctx_set_variant(ctx, variant);
+    if ((rc = ctx_set_variant(ctx, variant)) != DOG_OK)
+        return rc;
+    ctx->variant_forced = variant >= 0;
+    return DOG_OK;
 }
 
 int dog_set_profiling(dog_context* ctx, int32_t on)

@@ -29,11 +29,15 @@ struct FrameDesc {
     float* T;                // n_g transposed planes of pass 1
     float* L;                // n_g transposed planes of pass 2
     float* Ddbg;             // optional: k transposed DoG planes written by the NMS kernel
+    const int* rows1;        // pass 1: byte offset of input row refl(t, H), t = -pad .. H+pad-1
+    const int* rows2;        // pass 2: byte offset of T row refl(t, W), t = -pad .. W+pad-1
     long long src_stride;    // elements between input rows
     long long pitch;         // elements between rows of a transposed plane
     int H, W;
     int ladder;              // index into the ladder table
     int frame_id;            // value written into candidate records
+    int pad;                 // rows of reflection on each side of the row tables
+    int pad_;
 };
 
 // A sigma ladder after planning (Sec. 4 Eq. 1 in geometric form).

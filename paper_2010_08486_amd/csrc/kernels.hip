@@ -41,18 +41,6 @@
 
 namespace dog {
 
-// Half-sample symmetric reflection into [0, n), period 2n.
-__device__ __forceinline__ int refl(int t, int n)
-{
-    if ((unsigned)t < (unsigned)n)
-        return t;
-    const int p = 2 * n;
-    int u = t % p;
-    if (u < 0)
-        u += p;
-    return u < n ? u : p - 1 - u;
-}
-
 // Scalar view of the launch tables: they are read-only during a launch and
 // indexed uniformly, so their fields land in scalar registers.
 template <class T>
@@ -77,21 +65,17 @@ __device__ __forceinline__ float load_f32(__amdgpu_buffer_rsrc_t rs, unsigned vo
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff, soff, 0));
 }
 
-// v[m] = column c of row (row0 + m), m = 0..S-1.  Interior rows: vo[m] =
-// 4c + m*stride4 (per-lane, loop-invariant) plus one scalar offset per chunk.
-// Border rows: each row is reflected into [0, n) and addressed through the
-// scalar offset, with vo[0] = 4c.  stride4 = row pitch in bytes.
-template <int S, bool INTERIOR>
-__device__ __forceinline__ void load_rows(float (&v)[S], __amdgpu_buffer_rsrc_t rs, int stride4,
-                                          const unsigned (&vo)[S], int row0, int n)
+// v[m] = column voff/4 of row refl(row0 + m), m = 0..S-1.  The byte offset of
+// every (reflected) row comes from a per-frame table read with scalar loads,
+// so interior and border strips run the same code and each lane keeps a
+// single column offset.
+template <int S>
+__device__ __forceinline__ void load_rows(float (&v)[S], __amdgpu_buffer_rsrc_t rs, unsigned voff,
+                                          const DOG_CONSTANT_AS int* rows, int row0)
 {
 #pragma unroll
-    for (int m = 0; m < S; ++m) {
-        if (INTERIOR)
-            v[m] = load_f32(rs, vo[m], row0 * stride4);
-        else
-            v[m] = load_f32(rs, vo[0], refl(row0 + m, n) * stride4);
-    }
+    for (int m = 0; m < S; ++m)
+        v[m] = load_f32(rs, voff, rows[row0 + m]);
 }
 
 // One chunk of S taps: acc[t] += sum_u wc[u] * window[u + t], where the
@@ -113,25 +97,21 @@ __device__ __forceinline__ void fma_chunk(float (&acc)[S], const float (&lo)[S],
 // (X_j = rows base + j*S .. base + j*S + S - 1).  The ring X[0..R-1] holds
 // X_ch .. X_{ch+R-2} when chunk ch starts and the load of X_{ch+R-1} is issued
 // before its multiply-adds, so R-1 chunks of loads are in flight.
-// Reads rows up to base + (nch + R - 1) * S - 1.
-template <int S, int R, bool INTERIOR>
-__device__ __forceinline__ void blur_chunks(__amdgpu_buffer_rsrc_t rs, int stride4, int n,
-                                            unsigned c, int base, int nch, cptr_t w,
-                                            float (&acc)[S])
+// Reads table rows up to base + (nch + R - 1) * S - 1.
+template <int S, int R>
+__device__ __forceinline__ void blur_chunks(__amdgpu_buffer_rsrc_t rs, unsigned voff,
+                                            const DOG_CONSTANT_AS int* rows, int base, int nch,
+                                            cptr_t w, float (&acc)[S])
 {
-    unsigned vo[S];
-#pragma unroll
-    for (int m = 0; m < S; ++m)
-        vo[m] = 4u * c + (INTERIOR ? (unsigned)(m * stride4) : 0u);
     float X[R][S];
 #pragma unroll
     for (int j = 0; j < R - 1; ++j)
-        load_rows<S, INTERIOR>(X[j], rs, stride4, vo, base + j * S, n);
+        load_rows<S>(X[j], rs, voff, rows, base + j * S);
     int ch = 0;
     for (; ch + R <= nch; ch += R) {
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-            load_rows<S, INTERIOR>(X[(q + R - 1) % R], rs, stride4, vo, base + (ch + q + R - 1) * S, n);
+            load_rows<S>(X[(q + R - 1) % R], rs, voff, rows, base + (ch + q + R - 1) * S);
             fma_chunk<S>(acc, X[q], X[(q + 1) % R], w + (ch + q) * S);
         }
     }
@@ -140,30 +120,25 @@ __device__ __forceinline__ void blur_chunks(__amdgpu_buffer_rsrc_t rs, int strid
     for (int q = 0; q < R - 1; ++q) {
         if (q < nch - ch) {
             if (q == R - 2)
-                load_rows<S, INTERIOR>(X[R - 1], rs, stride4, vo, base + (ch + R - 1) * S, n);
+                load_rows<S>(X[R - 1], rs, voff, rows, base + (ch + R - 1) * S);
             fma_chunk<S>(acc, X[q], X[q + 1], w + (ch + q) * S);
         }
     }
 }
 
 // acc[t] = sum_{j=0}^{2r} w[j] * col[refl(y0 - r + t + j)], t = 0..S-1, where
-// col[m] is column c of row m of the plane behind `rs`.  Taps are accumulated
-// in ascending order, so every output sees the same summation order whatever
-// the tile shape; w must be zero-padded up to ceil((2r+1)/S)*S.
+// col[m] is column c of row m of the plane behind `rs` and rows[t] is the byte
+// offset of row refl(t).  Taps are accumulated in ascending order, so every
+// output sees the same summation order whatever the tile shape; w must be
+// zero-padded up to ceil((2r+1)/S)*S.
 template <int S, int R>
-__device__ __forceinline__ void blur_strip(__amdgpu_buffer_rsrc_t rs, int stride4, int n, int c,
+__device__ __forceinline__ void blur_strip(__amdgpu_buffer_rsrc_t rs, const int* rows, int c,
                                            int y0, int r, const float* w, float (&acc)[S])
 {
-    const int base = y0 - r;
-    const int nch = (2 * r + S) / S;
 #pragma unroll
     for (int t = 0; t < S; ++t)
         acc[t] = 0.0f;
-    const cptr_t cw = (cptr_t)w;
-    if (base >= 0 && base + (nch + R - 1) * S <= n)
-        blur_chunks<S, R, true>(rs, stride4, n, (unsigned)c, base, nch, cw, acc);
-    else
-        blur_chunks<S, R, false>(rs, stride4, n, (unsigned)c, base, nch, cw, acc);
+    blur_chunks<S, R>(rs, (unsigned)c * 4u, cst(rows), y0 - r, (2 * r + S) / S, (cptr_t)w, acc);
 }
 
 // This workgroup's tile.
@@ -193,14 +168,14 @@ __global__ void __launch_bounds__(64 * NW) k_pass1(LaunchArgs a)
         const int col = cb * 64 + lane;
         const __amdgpu_buffer_rsrc_t rs =
             plane_rsrc(f.src, (unsigned)(((long long)(f.H - 1) * f.src_stride + f.W) * 4));
-        const int stride4 = (int)(f.src_stride * 4);
+        const int* rows = f.rows1 + f.pad;
         if (col < f.W) {
             for (int q = 0; q < BI; ++q) {
                 const int y0 = band * BAND + (q * NW + wv) * S;
                 if (y0 >= f.H)
                     break;
                 float acc[S];
-                blur_strip<S, R>(rs, stride4, f.H, col, y0, r, w, acc);
+                blur_strip<S, R>(rs, rows, col, y0, r, w, acc);
                 float* __restrict__ dst = f.T + ((long long)p * f.W + col) * f.pitch + y0;
                 if (y0 + S <= f.H) {
 #pragma unroll
@@ -236,7 +211,7 @@ __global__ void __launch_bounds__(64 * NW) k_pass2(LaunchArgs a)
         const float* w = a.weights + cst(a.ladders)[f.ladder].woff[p];
         const __amdgpu_buffer_rsrc_t rs = plane_rsrc(f.T + (long long)p * f.W * f.pitch,
                                                      (unsigned)((long long)f.W * f.pitch * 4));
-        const int stride4 = (int)(f.pitch * 4);
+        const int* rows = f.rows2 + f.pad;
         float* __restrict__ dstp = f.L + (long long)p * f.W * f.pitch;
         const int col = cb * 64 + lane;
         if (col < f.H) {
@@ -245,7 +220,7 @@ __global__ void __launch_bounds__(64 * NW) k_pass2(LaunchArgs a)
                 if (x0 >= f.W)
                     break;
                 float acc[S];
-                blur_strip<S, R>(rs, stride4, f.W, col, x0, r, w, acc);
+                blur_strip<S, R>(rs, rows, col, x0, r, w, acc);
 #pragma unroll
                 for (int t = 0; t < S; ++t)
                     if (x0 + t < f.W)
@@ -557,13 +532,13 @@ static KernelSet make_set()
 // wave, waves) for the local-maximum kernel.
 static const KernelSet kSets[] = {
     make_set<12, 4, 4, 1, 4, 4>(),
-    make_set<12, 4, 4, 1, 8, 4>(),
     make_set<12, 6, 4, 1, 4, 4>(),
-    make_set<16, 4, 4, 1, 4, 4>(),
     make_set<16, 3, 4, 1, 4, 4>(),
-    make_set<8, 8, 4, 1, 4, 4>(),
-    make_set<12, 4, 2, 1, 4, 4>(),
+    make_set<16, 4, 4, 1, 4, 4>(),
+    make_set<16, 6, 4, 1, 4, 4>(),
     make_set<20, 3, 4, 1, 4, 4>(),
+    make_set<12, 8, 4, 1, 4, 4>(),
+    make_set<24, 3, 4, 1, 8, 4>(),
 };
 
 }  // namespace dog

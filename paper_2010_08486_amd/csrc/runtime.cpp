@@ -125,6 +125,17 @@ static Variant variant_geometry(int v)
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Half-sample symmetric reflection of index t into [0, n), period 2n: the
+// extended sequence is x[0..n-1], x[n-1..0], x[0..n-1], ...
+static long long reflect_index(long long t, long long n)
+{
+    const long long p = 2 * n;
+    long long u = t % p;
+    if (u < 0)
+        u += p;
+    return u < n ? u : p - 1 - u;
+}
+
 static constexpr size_t kRecBytes = sizeof(CandRec);
 
 // The launch sequence of the current tables on stream st: upload of the
@@ -192,6 +203,14 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
     out->assign(n, {});
     if (n == 0)
         return DOG_OK;
+    if (!c->variant_forced) {
+        const int v = choose_variant(c, frames, P);
+        if (v != c->variant) {
+            const int rc = ctx_set_variant(c, v);
+            if (rc != DOG_OK)
+                return rc;
+        }
+    }
     const Variant V = variant_geometry(c->variant);
     const int n_g = P.n_g;
 
@@ -326,6 +345,32 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
         build_table(r1, &tb1);
         build_table(r2, &tb2);
         build_table(r3, &tb3);
+
+        // reflected row offsets (bytes) for both blur passes: row t of the
+        // table is refl(t - pad) of the plane; one table per distinct shape
+        const int rmax = *std::max_element(P.r.begin(), P.r.end());
+        const int pad = rmax + (dogk_variant_ring(c->variant) + 1) * V.S;
+        std::vector<int> rowtab;
+        std::vector<size_t> rows1_off(n), rows2_off(n);
+        {
+            std::vector<std::pair<std::pair<long long, long long>, size_t>> seen;
+            auto table_for = [&](long long nrows, long long pitch_b) {
+                for (auto& e : seen)
+                    if (e.first.first == nrows && e.first.second == pitch_b)
+                        return e.second;
+                const size_t at = rowtab.size();
+                for (long long t = -pad; t < nrows + pad; ++t)
+                    rowtab.push_back((int)(reflect_index(t, nrows) * pitch_b));
+                while (rowtab.size() % 64)
+                    rowtab.push_back(0);
+                seen.push_back({{nrows, pitch_b}, at});
+                return at;
+            };
+            for (int f = 0; f < n; ++f) {
+                rows1_off[f] = table_for(frames[f].H, frames[f].stride * 4);
+                rows2_off[f] = table_for(frames[f].W, pitch[f] * 4);
+            }
+        }
         const long long t1 = (long long)tb1.size(), t2 = (long long)tb2.size(),
                         t3 = (long long)tb3.size();
         if (t1 > INT32_MAX / 2 || t2 > INT32_MAX / 2 || t3 > INT32_MAX / 2 || n > 65535) {
@@ -339,7 +384,8 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
         const size_t o_t1 = align_up(o_weights + sizeof(float) * P.weights.size(), 256);
         const size_t o_t2 = align_up(o_t1 + sizeof(Tile) * tb1.size(), 256);
         const size_t o_t3 = align_up(o_t2 + sizeof(Tile) * tb2.size(), 256);
-        const size_t tbytes = align_up(o_t3 + sizeof(Tile) * tb3.size(), 256);
+        const size_t o_rows = align_up(o_t3 + sizeof(Tile) * tb3.size(), 256);
+        const size_t tbytes = align_up(o_rows + sizeof(int) * rowtab.size(), 256);
         if ((rc = ctx_alloc(c, &c->tables, tbytes, "launch tables")) != DOG_OK)
             return rc;
         if ((rc = ctx_pin(&c->h_tables, tbytes)) != DOG_OK)
@@ -348,12 +394,23 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
         c->seen_key = key;
         char* dt = static_cast<char*>(c->tables.p);
         char* h = static_cast<char*>(c->h_tables.p);
+        const int* drows = reinterpret_cast<const int*>(dt + o_rows);
+        c->frame_rows.assign(2 * (size_t)n, nullptr);
+        for (int f = 0; f < n; ++f) {
+            c->frame_rows[2 * f] = drows + rows1_off[f];
+            c->frame_rows[2 * f + 1] = drows + rows2_off[f];
+            fd[f].rows1 = drows + rows1_off[f];
+            fd[f].rows2 = drows + rows2_off[f];
+            fd[f].pad = pad;
+        }
+        c->row_pad = pad;
         std::memcpy(h + o_frames, fd.data(), frames_bytes);
         std::memcpy(h + o_ladder, &P.desc, sizeof(LadderDesc));
         std::memcpy(h + o_weights, P.weights.data(), sizeof(float) * P.weights.size());
         std::memcpy(h + o_t1, tb1.data(), sizeof(Tile) * tb1.size());
         std::memcpy(h + o_t2, tb2.data(), sizeof(Tile) * tb2.size());
         std::memcpy(h + o_t3, tb3.data(), sizeof(Tile) * tb3.size());
+        std::memcpy(h + o_rows, rowtab.data(), sizeof(int) * rowtab.size());
         DOG_HIP(hipMemcpyAsync(c->tables.p, h, tbytes, hipMemcpyHostToDevice, c->stream));
         DOG_HIP(hipStreamSynchronize(c->stream));
 
@@ -401,6 +458,11 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
         c->graph_key = key;
         c->tables_ready = true;
     } else {
+        for (int f = 0; f < n; ++f) {
+            fd[f].rows1 = c->frame_rows[2 * f];
+            fd[f].rows2 = c->frame_rows[2 * f + 1];
+            fd[f].pad = c->row_pad;
+        }
         std::memcpy(c->h_tables.p, fd.data(), frames_bytes);
     }
 

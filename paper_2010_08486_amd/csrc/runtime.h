@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -103,7 +104,9 @@ struct dog_context {
     hipStream_t stream = nullptr;
     int n_cu = 0;
     int variant = 0;               // active kernel variant
-    int variant_auto = 0;          // autotuned choice
+    int variant_auto = 0;          // built-in default
+    bool variant_forced = false;   // pinned by dog_set_variant
+    std::map<std::string, int> tuned;  // "HxW|radii" -> autotuned variant
     int occ[3] = {0, 0, 0};        // workgroups per CU of each kernel (active variant)
 
     dog::DevBuf planes;            // T, L (and debug D) planes of all frames
@@ -132,6 +135,8 @@ struct dog_context {
     dog::LaunchArgs args;
     int n_gauss = 0;
     bool debug_planes = false;     // the current tables write the DoG planes
+    std::vector<const int*> frame_rows;  // per frame: pass-1 and pass-2 row tables
+    int row_pad = 0;
     size_t frames_bytes = 0;       // frame table bytes uploaded per launch
     uint32_t guess = 0;            // records read back by the captured sequence
     bool tables_ready = false;     // device tables match graph_key
@@ -151,6 +156,7 @@ int ctx_pin(PinBuf* b, size_t bytes);
 int ctx_plan(dog_context* c, const dog_params* prm, const Plan** out);
 int ctx_set_variant(dog_context* c, int v);
 void drop_graph(dog_context* c);
+int choose_variant(const dog_context* c, const std::vector<FrameIn>& frames, const Plan& P);
 
 // Run the three kernels over `frames` (device pixels) with plan P and read
 // back the candidate records, grouped per frame and sorted by (y, x, scale).

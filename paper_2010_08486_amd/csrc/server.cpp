@@ -272,6 +272,11 @@ int dog_server_create(int device, const dog_params* params, const dog_server_opt
         for (int i = 0; i < sv->opts.slots; ++i) {
             auto sl = std::make_unique<Slot>();
             rc = dog_context_create(device, sv->budget, &sl->ctx);
+            if (rc == DOG_OK && sv->opts.tune_cache) {
+                rc = dog_autotune_load(sl->ctx, sv->opts.tune_cache);
+                if (rc != DOG_OK)
+                    dog_context_destroy(sl->ctx);
+            }
             if (rc != DOG_OK) {
                 for (auto& s : sv->slots)
                     dog_context_destroy(s->ctx);
@@ -287,6 +292,7 @@ int dog_server_create(int device, const dog_params* params, const dog_server_opt
         if (sv->budget == 0)
             sv->budget = 1ull << 40;
     }
+    sv->opts.tune_cache = nullptr;  // read above only; the caller's string may go away
     dog_server* raw = sv.release();
     for (auto& s : raw->slots) {
         Slot* sp = s.get();

@@ -1,0 +1,87 @@
+"""Autotuner: every variant is timed, the winner is used for launches of the
+tuned shape, results never change, and choices survive a save/load round trip
+(and are ignored when the cache names another kernel build)."""
+import json
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+CAMERA = dict(sigma_min=1.0, sigma_max=30.0, sigma_ratio=1.6, threshold=0.05, overlap=0.5)
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    assert torch.cuda.is_available(), "gpu tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def dog():
+    import paper_2010_08486_amd as d
+    return d
+
+
+def _dev(torch, img):
+    return torch.from_numpy(np.ascontiguousarray(img)).cuda()
+
+
+def test_autotune_picks_fastest_and_keeps_results(dog, torch_mod, tmp_path):
+    img = synth.camera_frame(seed=31, H=384, W=448, n_blobs=60)
+    t = _dev(torch_mod, img)
+    prm = dog.Params(**CAMERA)
+    with dog.Context(0) as c:
+        before = c.detect_device(t, prm)
+        default = c.autotune_choice(prm, 384, 448)
+        v, us = c.autotune(t, prm, reps=2)
+        assert len(us) == dog.num_variants()
+        assert all(u > 0 for u in us), us
+        assert 0 <= v < dog.num_variants() and us[v] == min(us)
+        assert c.autotune_choice(prm, 384, 448) == v
+        # nearest tuned shape of the same radii serves an untuned shape
+        assert c.autotune_choice(prm, 400, 440) == v
+        other = dog.Params(**dict(CAMERA, sigma_max=8.0))
+        assert c.autotune_choice(other, 384, 448) == default
+        after = c.detect_device(t, prm)
+        assert after.tobytes() == before.tobytes()
+        path = str(tmp_path / "tune.json")
+        c.autotune_save(path)
+    doc = json.load(open(path))
+    assert doc["arch"] == "gfx950" and len(doc["entries"]) == 1
+    with dog.Context(0) as c2:
+        c2.autotune_load(path)
+        assert c2.autotune_choice(prm, 384, 448) == v
+        # a pinned variant overrides the tuned choice until unpinned
+        pin = (v + 1) % dog.num_variants()
+        c2.set_variant(pin)
+        assert c2.autotune_choice(prm, 384, 448) == v
+        assert c2.detect_device(t, prm).tobytes() == before.tobytes()
+        c2.set_variant(-1)
+    doc["kernels"] = "0000000000000000"
+    stale = str(tmp_path / "stale.json")
+    json.dump(doc, open(stale, "w"))
+    with dog.Context(0) as c3:
+        c3.autotune_load(stale)
+        assert c3.autotune_choice(prm, 384, 448) == default
+
+
+def test_server_loads_tune_cache(dog, torch_mod, tmp_path):
+    img = synth.camera_frame(seed=32, H=256, W=320, n_blobs=30)
+    prm = dog.Params(**CAMERA)
+    with dog.Context(0) as c:
+        ref = c.detect_device(_dev(torch_mod, img), prm)
+        c.autotune(_dev(torch_mod, img), prm, reps=1)
+        path = str(tmp_path / "tune.json")
+        c.autotune_save(path)
+    sv = dog.Server(prm, slots=2, max_batch_frames=4, tune_cache=path)
+    try:
+        tickets = [sv.submit(img) for _ in range(3)]
+        for tk in tickets:
+            blobs, _ = sv.wait(tk)
+            assert blobs.tobytes() == ref.tobytes()
+    finally:
+        sv.close()
