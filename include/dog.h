@@ -79,7 +79,9 @@ typedef struct {
 } dog_params;
 
 /* A frame of a batch or a server request.  on_device = 1: `data` is a device
- * pointer on the context's GPU; 0: a host pointer. */
+ * pointer on the context's GPU; 0: a host pointer (copied into the context's
+ * pinned staging, then to the device); 2: a pinned host pointer (page-locked,
+ * e.g. from hipHostMalloc), copied to the device by DMA with no staging copy. */
 typedef struct {
     const float* data;
     int64_t height;
@@ -236,12 +238,16 @@ int dog_kernel_times(dog_context* ctx, double* ms_out, int64_t* launches_out);
 
 /* ------------------------------------------------------------ serving */
 
-/* Serving loop: host frames are submitted at any time; a dispatcher forms a
+/* Serving loop: frames are submitted at any time; a dispatcher forms a
  * batch from whatever waits (at most max_batch_frames, and only while the
  * device footprint of all batches in flight stays within the admission
  * budget) and hands it to an idle slot.  Each slot owns a context and a
  * stream, so batches overlap on the device; a request that arrives while
  * others run joins the next batch as soon as a slot and memory are free.
+ * Host frames are copied at submit into page-locked buffers the server
+ * pools (up to 4 GiB; beyond that, pageable copies), from which the slot's
+ * upload is a plain DMA.  Device frames (on_device = 1) are borrowed: the
+ * caller keeps them valid and unchanged until the ticket's result is taken.
  * Results are the same as dog_detect on the frame alone. */
 typedef struct {
     int32_t max_batch_frames;   /* frames per launch sequence (<= 0: 16)              */

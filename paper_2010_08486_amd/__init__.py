@@ -396,6 +396,7 @@ class Server:
                  max_wait_ms: float = 0.0, dry_run: bool = False,
                  dry_run_us_per_mpx: float = 0.0, tune_cache: str | None = None):
         self._h = ctypes.c_void_p()
+        self._held = {}
         opts = dog_server_opts(max_batch_frames, slots, queue_capacity, 1 if dry_run else 0,
                                hbm_budget_bytes, max_wait_ms, dry_run_us_per_mpx,
                                os.fsencode(tune_cache) if tune_cache else None)
@@ -407,6 +408,7 @@ class Server:
         if self._h:
             lib().dog_server_destroy(self._h)
             self._h = ctypes.c_void_p()
+        self._held.clear()
 
     def __del__(self):
         try:
@@ -420,15 +422,27 @@ class Server:
     def __exit__(self, *a):
         self.close()
 
-    def submit(self, frame: np.ndarray) -> int:
-        a = np.asarray(frame)
-        if a.dtype != np.float32 or a.ndim != 2:
-            raise TypeError("frames must be 2-D float32 arrays")
-        if a.strides[1] != 4 or a.strides[0] % 4:
-            a = np.ascontiguousarray(a)
-        fr = dog_frame(a.ctypes.data, a.shape[0], a.shape[1], a.strides[0] // 4, 0, 0)
+    def submit(self, frame) -> int:
+        """Queue a 2-D float32 frame: a numpy array (copied at once) or a CUDA
+        tensor (borrowed: held here until its result is taken)."""
+        if isinstance(frame, np.ndarray):
+            a = frame
+            if a.dtype != np.float32 or a.ndim != 2:
+                raise TypeError("frames must be 2-D float32 arrays")
+            if a.strides[1] != 4 or a.strides[0] % 4:
+                a = np.ascontiguousarray(a)
+            fr = dog_frame(a.ctypes.data, a.shape[0], a.shape[1], a.strides[0] // 4, 0, 0)
+            hold = None
+        else:
+            ptr, H, W, st = _tensor_image(frame)
+            fr = dog_frame(ptr, H, W, st, 1, 0)
+            hold = frame
+            import torch
+            torch.cuda.current_stream(frame.device).synchronize()  # pixels written before the server reads
         t = ctypes.c_uint64(0)
         _check(lib().dog_server_submit(self._h, ctypes.byref(fr), ctypes.byref(t)))
+        if hold is not None:
+            self._held[int(t.value)] = hold
         return int(t.value)
 
     @staticmethod
@@ -447,12 +461,15 @@ class Server:
         rc = lib().dog_server_poll(self._h, ticket, ctypes.byref(r))
         if rc == DOG_EAGAIN:
             return None
+        self._held.pop(ticket, None)
         _check(rc)
         return self._unpack(r)
 
     def wait(self, ticket: int):
         r = dog_result()
-        _check(lib().dog_server_wait(self._h, ticket, ctypes.byref(r)))
+        rc = lib().dog_server_wait(self._h, ticket, ctypes.byref(r))
+        self._held.pop(ticket, None)
+        _check(rc)
         return self._unpack(r)
 
     def drain(self) -> None:

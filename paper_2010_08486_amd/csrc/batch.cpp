@@ -90,7 +90,7 @@ int detect_frames(dog_context* ctx, const dog_params* params, int32_t n_frames,
         }
         const uint64_t pitch = ((uint64_t)fr.height + 63) / 64 * 64;
         uint64_t b = 2ull * P->n_g * (uint64_t)fr.width * pitch * sizeof(float) + 256;
-        if (!fr.on_device)
+        if (fr.on_device != 1)
             b += (uint64_t)fr.height * (uint64_t)fr.width * sizeof(float) + 256;
         idx.push_back(f);
         need.push_back(b);
@@ -116,38 +116,82 @@ int detect_frames(dog_context* ctx, const dog_params* params, int32_t n_frames,
             i = j;
             continue;
         }
-        // stage host frames
-        uint64_t in_bytes = 0;
-        for (size_t q = i; q < j; ++q)
-            if (!frames[idx[q]].on_device)
-                in_bytes += ((uint64_t)frames[idx[q]].height * frames[idx[q]].width * sizeof(float) + 255) / 256 * 256;
+        // host frames: pageable ones through the pinned staging buffer (one
+        // upload for all of them), pinned ones by DMA straight into place
+        uint64_t in_bytes = 0, staged_bytes = 0;
+        for (size_t q = i; q < j; ++q) {
+            const dog_frame& fr = frames[idx[q]];
+            const uint64_t b = ((uint64_t)fr.height * fr.width * sizeof(float) + 255) / 256 * 256;
+            if (fr.on_device != 1)
+                in_bytes += b;
+            if (fr.on_device == 0)
+                staged_bytes += b;
+        }
         if (in_bytes) {
-            if ((rc = ctx_pin(&ctx->h_input, in_bytes)) != DOG_OK ||
+            if ((staged_bytes && (rc = ctx_pin(&ctx->h_input, staged_bytes)) != DOG_OK) ||
                 (rc = ctx_alloc(ctx, &ctx->input, in_bytes, "input frames")) != DOG_OK)
                 goto chunk_fail;
         }
         {
             std::vector<FrameIn> fin;
-            uint64_t o = 0;
+            uint64_t o = 0, so = 0;
+            char* const dbase = static_cast<char*>(ctx->input.p);
             for (size_t q = i; q < j; ++q) {
                 const dog_frame& fr = frames[idx[q]];
-                if (fr.on_device) {
+                const size_t row_bytes = (size_t)fr.width * sizeof(float);
+                if (fr.on_device == 1) {
                     fin.push_back({fr.data, (int)fr.height, (int)fr.width, (long long)fr.row_stride});
-                } else {
-                    char* hp = static_cast<char*>(ctx->h_input.p) + o;
-                    for (int64_t y = 0; y < fr.height; ++y)
-                        std::memcpy(hp + (size_t)y * fr.width * sizeof(float), fr.data + y * fr.row_stride,
-                                    (size_t)fr.width * sizeof(float));
-                    fin.push_back({reinterpret_cast<const float*>(static_cast<char*>(ctx->input.p) + o),
-                                   (int)fr.height, (int)fr.width, (long long)fr.width});
-                    o += ((uint64_t)fr.height * fr.width * sizeof(float) + 255) / 256 * 256;
+                    continue;
                 }
+                if (fr.on_device == 2) {
+                    hipError_t e = hipMemcpy2DAsync(dbase + o, row_bytes, fr.data,
+                                                    (size_t)fr.row_stride * sizeof(float), row_bytes,
+                                                    (size_t)fr.height, hipMemcpyHostToDevice, s);
+                    if (e != hipSuccess) {
+                        rc = hip_fail(e, "hipMemcpy2DAsync(pinned input)");
+                        goto chunk_fail;
+                    }
+                } else {
+                    char* hp = static_cast<char*>(ctx->h_input.p) + so;
+                    for (int64_t y = 0; y < fr.height; ++y)
+                        std::memcpy(hp + (size_t)y * row_bytes, fr.data + y * fr.row_stride, row_bytes);
+                    so += ((uint64_t)fr.height * row_bytes + 255) / 256 * 256;
+                }
+                fin.push_back({reinterpret_cast<const float*>(dbase + o), (int)fr.height,
+                               (int)fr.width, (long long)fr.width});
+                o += ((uint64_t)fr.height * row_bytes + 255) / 256 * 256;
             }
-            if (o) {
-                hipError_t e = hipMemcpyAsync(ctx->input.p, ctx->h_input.p, o, hipMemcpyHostToDevice, s);
-                if (e != hipSuccess) {
-                    rc = hip_fail(e, "hipMemcpyAsync(input)");
-                    goto chunk_fail;
+            // staged frames keep their order in the input area, where pinned
+            // frames may sit between them: one upload per run of staged frames
+            if (staged_bytes) {
+                uint64_t d = 0, h = 0, run_d = 0, run_h = 0, run_b = 0;
+                for (size_t q = i; q <= j; ++q) {
+                    const bool end = q == j;
+                    const dog_frame* fr = end ? nullptr : &frames[idx[q]];
+                    if (!end && fr->on_device == 1)
+                        continue;
+                    if ((end || fr->on_device == 2) && run_b) {
+                        hipError_t e = hipMemcpyAsync(dbase + run_d,
+                                                      static_cast<char*>(ctx->h_input.p) + run_h, run_b,
+                                                      hipMemcpyHostToDevice, s);
+                        if (e != hipSuccess) {
+                            rc = hip_fail(e, "hipMemcpyAsync(input)");
+                            goto chunk_fail;
+                        }
+                        run_b = 0;
+                    }
+                    if (end)
+                        break;
+                    const uint64_t b = ((uint64_t)fr->height * fr->width * sizeof(float) + 255) / 256 * 256;
+                    if (fr->on_device == 0) {
+                        if (run_b == 0) {
+                            run_d = d;
+                            run_h = h;
+                        }
+                        run_b += b;
+                        h += b;
+                    }
+                    d += b;
                 }
             }
             std::vector<std::vector<dog_blob>> res;

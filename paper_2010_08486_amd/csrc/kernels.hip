@@ -230,6 +230,226 @@ __global__ void __launch_bounds__(64 * NW) k_pass2(LaunchArgs a)
     }
 }
 
+// ------------------------------------------------------------------------
+// LDS-staged blur (both passes).  A workgroup of NW waves owns 64 columns and
+// NW*S consecutive outputs along the blur direction; wave w computes outputs
+// w*S .. w*S+S-1 of the band for its lane's column.  Input rows stream
+// through an LDS ring of NW+2 chunks of S rows: each chunk is fetched from
+// HBM/L2 once per workgroup with 16-byte loads (one per lane for S = 16,
+// NW = 4), P chunks ahead of use, instead of once per wave with 4-byte loads.
+// Step c multiplies row chunks X_{w+c} and X_{w+c+1} by taps c*S .. c*S+S-1,
+// exactly as blur_chunks does, so results are bitwise identical to the
+// register-ring kernels.  Weights are moved into vector registers once per
+// chunk: gfx950 issues FP32 FMAs whose operands are all vector registers at
+// twice the rate of the form that reads a scalar register.
+
+// Half-sample symmetric reflection of row t into [0, n) (period 2n).
+__device__ __forceinline__ int refl_row(int t, int n)
+{
+    if ((unsigned)t < (unsigned)n)
+        return t;
+    const int p = 2 * n;
+    int u = t % p;
+    if (u < 0)
+        u += p;
+    return u < n ? u : p - 1 - u;
+}
+
+__device__ __forceinline__ float to_vgpr(float s)
+{
+    float v;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
+    return v;
+}
+
+template <int S>
+__device__ __forceinline__ void fma_chunk_v(float (&acc)[S], const float (&lo)[S],
+                                            const float (&hi)[S], const float (&wv)[S])
+{
+#pragma unroll
+    for (int u = 0; u < S; ++u) {
+#pragma unroll
+        for (int t = 0; t < S; ++t)
+            acc[t] = __builtin_fmaf(wv[u], (u + t < S) ? lo[u + t] : hi[u + t - S], acc[t]);
+    }
+}
+
+template <int S, int NW>
+struct StageGeom {
+    static constexpr int Q = NW + 2;                        // LDS ring slots
+    static constexpr int NT = 64 * NW;                      // threads
+    static constexpr int LPL = (16 * S + NT - 1) / NT;      // 16-byte loads per lane per chunk
+};
+
+// Fetch row chunk j (rows base + j*S .. + S-1, reflected into [0, n)) of the
+// 64 columns from col0 into registers: thread q of the chunk holds columns
+// col0 + 4*(q%16) .. +3 of row q/16.  WIDE: every 64-column block lies inside
+// the rows and rows are 16-byte aligned, so one 16-byte load per thread; else
+// four 4-byte loads, which the buffer range check turns into zeros past the
+// plane (such columns are never stored).  The number of loads is fixed, so
+// the compiler can wait for one staged chunk while later ones stay in flight.
+template <int S, int NW, bool WIDE, int L>
+__device__ __forceinline__ void stage_load(float4 (&st)[L], __amdgpu_buffer_rsrc_t rs, int tid,
+                                           int base, int j, int n, int stride, int col0)
+{
+    using G = StageGeom<S, NW>;
+    static_assert(L == G::LPL, "staging registers");
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        const int q = tid + i * G::NT;
+        if ((16 * S) % G::NT == 0 || q < 16 * S) {
+            const int row = refl_row(base + j * S + (q >> 4), n);
+            const unsigned off = (unsigned)(row * stride + col0 + 4 * (q & 15)) * 4u;
+            if (WIDE) {
+                st[i] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0));
+            } else {
+                st[i].x = load_f32(rs, off, 0);
+                st[i].y = load_f32(rs, off + 4u, 0);
+                st[i].z = load_f32(rs, off + 8u, 0);
+                st[i].w = load_f32(rs, off + 12u, 0);
+            }
+        }
+    }
+}
+
+template <int S, int NW, int L>
+__device__ __forceinline__ void stage_store(float4* lds, int slot, const float4 (&st)[L], int tid)
+{
+    using G = StageGeom<S, NW>;
+    static_assert(L == G::LPL, "staging registers");
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        const int q = tid + i * G::NT;
+        if ((16 * S) % G::NT == 0 || q < 16 * S)
+            lds[slot * S * 16 + q] = st[i];
+    }
+}
+
+template <int S>
+__device__ __forceinline__ void lds_rows(float (&v)[S], const float* lds, int slot, int lane)
+{
+#pragma unroll
+    for (int m = 0; m < S; ++m)
+        v[m] = lds[(slot * S + m) * 64 + lane];
+}
+
+// PASS 1: blur down the columns of the input frame into T (transposed);
+// PASS 2: blur down the columns of T_p into L_p (same layout).
+template <int PASS, int S, int NW, int P, bool WIDE>
+__global__ void __launch_bounds__(64 * NW) k_blur_lds(LaunchArgs a)
+{
+    using G = StageGeom<S, NW>;
+    static_assert(S % 4 == 0 && S <= 16 && P >= 1, "tile geometry");
+    __shared__ float4 lds4[G::Q * S * 16];
+    const float* lds = reinterpret_cast<const float*>(lds4);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(tid >> 6));
+    if (PASS == 1 && blockIdx.x == 0 && tid == 0)
+        a.cand->count = 0u;  // read by the local-maximum kernel of this sequence
+    const Tile tl = my_tile(PASS == 1 ? a.tiles1 : a.tiles2);
+    const FrameDesc f = cst(a.frames)[tl.frame];
+    const int p = tl.plane;
+    const int r = cst(a.ladders)[f.ladder].r[p];
+    const cptr_t w = (cptr_t)(a.weights + cst(a.ladders)[f.ladder].woff[p]);
+    const float* src = PASS == 1 ? f.src : f.T + (long long)p * f.W * f.pitch;
+    const int n = PASS == 1 ? f.H : f.W;                       // rows along the blur
+    const int stride = PASS == 1 ? (int)f.src_stride : (int)f.pitch;
+    const int ncols = PASS == 1 ? f.W : (int)f.pitch;
+    const unsigned bytes = PASS == 1
+                               ? (unsigned)(((long long)(f.H - 1) * f.src_stride + f.W) * 4)
+                               : (unsigned)((long long)f.W * f.pitch * 4);
+    const __amdgpu_buffer_rsrc_t rs = plane_rsrc(src, bytes);
+    const int col0 = tl.cb * 64;
+    (void)ncols;
+    const int y0 = tl.band * (NW * S);
+    const int base = y0 - r;
+    const int nch = (2 * r + S) / S;   // tap chunks
+    const int nload = nch + NW;        // row chunks X_0 .. X_{nch+NW-1}
+
+    // X_0 .. X_NW into the ring, X_{NW+1} .. X_{NW+P} into registers.  Loads
+    // past the last chunk fetch the last chunk again (never stored), so every
+    // step issues the same loads.
+#pragma unroll
+    for (int j = 0; j <= NW; ++j) {
+        float4 t[G::LPL];
+        stage_load<S, NW, WIDE>(t, rs, tid, base, j, n, stride, col0);
+        stage_store<S, NW>(lds4, j, t, tid);
+    }
+    float4 stg[P][G::LPL];
+#pragma unroll
+    for (int k = 0; k < P; ++k)
+        stage_load<S, NW, WIDE>(stg[k], rs, tid, base, min(NW + 1 + k, nload - 1), n, stride, col0);
+    __syncthreads();
+
+    float acc[S], lo[S], hi[S], wr[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t)
+        acc[t] = 0.0f;
+    lds_rows<S>(lo, lds, wv, lane);
+    // step c: taps c*S .. c*S+S-1 on X_{w+c}, X_{w+c+1}; then publish
+    // X_{NW+1+c} from staging register set c % P and refill that set
+    auto step = [&](int c, float4 (&st)[G::LPL]) {
+        lds_rows<S>(hi, lds, (wv + c + 1) % G::Q, lane);
+#pragma unroll
+        for (int u = 0; u < S; ++u)
+            wr[u] = to_vgpr(w[c * S + u]);
+        fma_chunk_v<S>(acc, lo, hi, wr);
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            // the accumulators pass through an empty asm statement, so the
+            // multiply-adds cannot sink past the barrier below (two steps'
+            // operands live at once would cost occupancy)
+            asm volatile("" : "+v"(acc[t]));
+            lo[t] = hi[t];
+        }
+        const int j = NW + 1 + c;
+        if (j < nload)
+            stage_store<S, NW>(lds4, j % G::Q, st, tid);
+        stage_load<S, NW, WIDE>(st, rs, tid, base, min(j + P, nload - 1), n, stride, col0);
+        __syncthreads();
+    };
+    // whole groups of P steps issue the same loads every iteration, so each
+    // wait covers exactly the oldest staged chunk
+    int c = 0;
+    for (; c + P <= nch; c += P) {
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+            step(c + k, stg[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < P - 1; ++k)
+        if (c + k < nch)
+            step(c + k, stg[k]);
+
+    const int col = col0 + lane;
+    const int o0 = y0 + wv * S;  // first output of this wave along the blur
+    if (PASS == 1) {
+        if (col < f.W && o0 < f.H) {
+            float* __restrict__ dst = f.T + ((long long)p * f.W + col) * f.pitch + o0;
+            if (o0 + S <= f.H) {
+#pragma unroll
+                for (int t = 0; t < S; t += 4)
+                    *reinterpret_cast<float4*>(dst + t) =
+                        make_float4(acc[t], acc[t + 1], acc[t + 2], acc[t + 3]);
+            } else {
+#pragma unroll
+                for (int t = 0; t < S; ++t)
+                    if (o0 + t < f.H)
+                        dst[t] = acc[t];
+            }
+        }
+    } else {
+        if (col < f.H) {
+            float* __restrict__ dstp = f.L + (long long)p * f.W * f.pitch;
+#pragma unroll
+            for (int t = 0; t < S; ++t)
+                if (o0 + t < f.W)
+                    dstp[(long long)(o0 + t) * f.pitch + col] = acc[t];
+        }
+    }
+}
+
 // Lanes i-1 and i+1 of a wave.  Lanes 0 and 63 receive 0 from outside the
 // wave; they are halo lanes whose results are never used.
 __device__ __forceinline__ float lane_prev(float v)
@@ -503,15 +723,38 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, int n, uint32_t v)
 
 struct KernelSet {
     const void* pass1;
+    const void* pass1w;   // pass 1 when every frame has 16-byte aligned rows and
+                          // a width that is a multiple of 64 (nullptr: same as pass1)
     const void* pass2;
     const void* nms[2][2];  // [ladder of at most DOG_NMS_KMAX planes][debug planes]
     int S, R, NW, BI, BN, NWN;
 };
 
+template <int S, int NW, int P, int BN, int NWN>
+static KernelSet make_lds_set()
+{
+    KernelSet k;
+    k.pass1 = reinterpret_cast<const void*>(&k_blur_lds<1, S, NW, P, false>);
+    k.pass1w = reinterpret_cast<const void*>(&k_blur_lds<1, S, NW, P, true>);
+    k.pass2 = reinterpret_cast<const void*>(&k_blur_lds<2, S, NW, P, true>);
+    k.nms[0][0] = reinterpret_cast<const void*>(&k_nms<BN, NWN, 0, false>);
+    k.nms[0][1] = reinterpret_cast<const void*>(&k_nms<BN, NWN, 0, true>);
+    k.nms[1][0] = reinterpret_cast<const void*>(&k_nms<BN, NWN, DOG_NMS_KMAX, false>);
+    k.nms[1][1] = reinterpret_cast<const void*>(&k_nms<BN, NWN, DOG_NMS_KMAX, true>);
+    k.S = S;
+    k.R = P;
+    k.NW = NW;
+    k.BI = 1;
+    k.BN = BN;
+    k.NWN = NWN;
+    return k;
+}
+
 template <int S, int R, int NW, int BI, int BN, int NWN>
 static KernelSet make_set()
 {
     KernelSet k;
+    k.pass1w = nullptr;
     k.pass1 = reinterpret_cast<const void*>(&k_pass1<S, R, NW, BI>);
     k.pass2 = reinterpret_cast<const void*>(&k_pass2<S, R, NW, BI>);
     k.nms[0][0] = reinterpret_cast<const void*>(&k_nms<BN, NWN, 0, false>);
@@ -539,6 +782,12 @@ static const KernelSet kSets[] = {
     make_set<20, 3, 4, 1, 4, 4>(),
     make_set<12, 8, 4, 1, 4, 4>(),
     make_set<24, 3, 4, 1, 8, 4>(),
+    make_lds_set<16, 4, 2, 4, 4>(),
+    make_lds_set<16, 4, 4, 4, 4>(),
+    make_lds_set<12, 4, 2, 4, 4>(),
+    make_lds_set<8, 8, 2, 4, 4>(),
+    make_lds_set<16, 8, 2, 4, 4>(),
+    make_lds_set<16, 2, 2, 4, 4>(),
 };
 
 }  // namespace dog
@@ -559,22 +808,24 @@ void dogk_variant_geometry(int v, int* S, int* NW, int* BI, int* BN, int* NWN)
 
 int dogk_variant_ring(int v) { return dog::kSets[v].R; }
 
-// Launch pass 1, pass 2 and the local-maximum kernel on `stream` with the
-// given persistent grid sizes (multiples of 8 keep the XCD lists balanced).
+// Launch pass 1, pass 2 and the local-maximum kernel on `stream`, one
+// workgroup per tile of each table.  wide1: every frame's rows are 16-byte
+// aligned and its width is a multiple of 64, so pass 1 may use 16-byte loads.
 // If ev is non-NULL, events ev[0..3] are recorded before, between and after
 // the kernels.  Returns the first launch error.
 hipError_t dogk_launch_sequence(int variant, const dog::LaunchArgs* args, int grid1, int grid2,
-                                int grid3, int max_gauss, int debug, hipStream_t stream,
+                                int grid3, int max_gauss, int debug, int wide1, hipStream_t stream,
                                 hipEvent_t* ev)
 {
     const dog::KernelSet& k = dog::kSets[variant];
+    const void* pass1 = wide1 && k.pass1w ? k.pass1w : k.pass1;
     const void* nms = k.nms[max_gauss <= DOG_NMS_KMAX ? 1 : 0][debug ? 1 : 0];
     void* params[] = {const_cast<dog::LaunchArgs*>(args)};
     hipError_t e = hipSuccess;
     if (ev)
         e = hipEventRecord(ev[0], stream);
     if (e == hipSuccess)
-        e = hipLaunchKernel(k.pass1, dim3(grid1), dim3(64 * k.NW), params, 0, stream);
+        e = hipLaunchKernel(pass1, dim3(grid1), dim3(64 * k.NW), params, 0, stream);
     if (e == hipSuccess && ev)
         e = hipEventRecord(ev[1], stream);
     if (e == hipSuccess)

@@ -150,7 +150,8 @@ static hipError_t enqueue_sequence(dog_context* c, hipStream_t st)
                                   hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = dogk_launch_sequence(c->variant, &a, a.n1, a.n2, a.n3, c->n_gauss,
-                                 c->debug_planes ? 1 : 0, st, c->profiling ? c->ev : nullptr);
+                                 c->debug_planes ? 1 : 0, c->wide1 ? 1 : 0, st,
+                                 c->profiling ? c->ev : nullptr);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->h_cand.p, c->cand.p, sizeof(CandHeader) + kRecBytes * c->guess,
                            hipMemcpyDeviceToHost, st);
@@ -174,8 +175,12 @@ void drop_graph(dog_context* c)
 static std::vector<long long> launch_key(const dog_context* c, const std::vector<FrameIn>& frames,
                                          bool dbg_D)
 {
+    bool wide = true;
+    for (const FrameIn& f : frames)
+        wide = wide && f.W % 64 == 0 && f.stride % 4 == 0 && ((uintptr_t)f.d & 15) == 0;
     std::vector<long long> k;
     k.reserve(16 + 3 * frames.size());
+    k.push_back(wide ? 1 : 0);  // first entry: 16-byte loads in pass 1
     k.push_back((long long)frames.size());
     k.push_back(c->variant);
     k.push_back((long long)c->plan_gen);
@@ -429,6 +434,7 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
         a.n3 = (int)t3;
         c->n_gauss = n_g;
         c->debug_planes = dbg_D;
+        c->wide1 = key[0] != 0;
         // readback size fixed in the captured sequence: header + a guess of
         // the record count (more is copied afterwards if needed)
         c->guess = std::min<uint32_t>(

@@ -87,7 +87,7 @@ int dogk_num_variants();
 void dogk_variant_geometry(int v, int* S, int* NW, int* BI, int* BN, int* NWN);
 int dogk_variant_ring(int v);
 hipError_t dogk_launch_sequence(int variant, const dog::LaunchArgs* args, int grid1, int grid2,
-                                int grid3, int max_gauss, int debug, hipStream_t stream,
+                                int grid3, int max_gauss, int debug, int wide1, hipStream_t stream,
                                 hipEvent_t* ev);
 hipError_t dogk_launch_nms(int variant, const dog::LaunchArgs* args, int grid3, int max_gauss,
                            int debug, hipStream_t stream);
@@ -135,6 +135,7 @@ struct dog_context {
     dog::LaunchArgs args;
     int n_gauss = 0;
     bool debug_planes = false;     // the current tables write the DoG planes
+    bool wide1 = false;            // every frame of the tables allows 16-byte row loads
     std::vector<const int*> frame_rows;  // per frame: pass-1 and pass-2 row tables
     int row_pad = 0;
     size_t frames_bytes = 0;       // frame table bytes uploaded per launch

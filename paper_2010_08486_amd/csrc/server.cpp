@@ -9,7 +9,9 @@
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
+#include <cstdlib>
 #include <deque>
+#include <map>
 #include <memory>
 #include <thread>
 #include <unordered_map>
@@ -26,12 +28,84 @@ int64_t now_ns()
         .count();
 }
 
+// Page-locked host buffers for request copies, reused across requests so a
+// steady stream allocates nothing.  Beyond `cap` bytes pinned, buffers are
+// plain pageable memory (staged by the context instead of DMA'd directly).
+class PinnedPool {
+public:
+    explicit PinnedPool(uint64_t cap) : cap_(cap) {}
+    ~PinnedPool()
+    {
+        for (auto& kv : free_)
+            (void)hipHostFree(kv.second);
+    }
+    // A buffer of at least `bytes`; *pinned tells which kind it is.
+    void* get(size_t bytes, size_t* got, bool* pinned)
+    {
+        const size_t sz = (bytes + kGrain - 1) / kGrain * kGrain;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            auto it = free_.lower_bound(sz);
+            if (it != free_.end() && it->first <= 2 * sz) {
+                void* p = it->second;
+                *got = it->first;
+                free_.erase(it);
+                *pinned = true;
+                return p;
+            }
+            // make room by dropping idle buffers, largest first
+            while (total_ + sz > cap_ && !free_.empty()) {
+                auto last = std::prev(free_.end());
+                (void)hipHostFree(last->second);
+                total_ -= last->first;
+                free_.erase(last);
+            }
+            if (!failed_ && total_ + sz <= cap_) {
+                void* p = nullptr;
+                if (hipHostMalloc(&p, sz, hipHostMallocPortable) == hipSuccess) {
+                    total_ += sz;
+                    *got = sz;
+                    *pinned = true;
+                    return p;
+                }
+                (void)hipGetLastError();
+                failed_ = true;  // no more attempts: pageable from now on
+            }
+        }
+        *got = bytes;
+        *pinned = false;
+        return std::malloc(bytes);
+    }
+    void put(void* p, size_t bytes, bool pinned)
+    {
+        if (!p)
+            return;
+        if (!pinned) {
+            std::free(p);
+            return;
+        }
+        std::lock_guard<std::mutex> lk(mu_);
+        free_.emplace(bytes, p);
+    }
+
+private:
+    static constexpr size_t kGrain = 1u << 20;
+    std::mutex mu_;
+    std::multimap<size_t, void*> free_;
+    uint64_t total_ = 0;
+    uint64_t cap_;
+    bool failed_ = false;
+};
+
 struct Request {
-    uint64_t ticket;
-    std::vector<float> pixels;  // dense copy, row stride = width
-    int64_t H, W;
-    int64_t t_arrive;
-    uint64_t footprint;
+    uint64_t ticket = 0;
+    const float* data = nullptr;  // pinned/pageable copy (owned) or borrowed device frame
+    size_t bytes = 0;             // size of the owned copy
+    bool pinned = false;
+    bool on_device = false;
+    int64_t H = 0, W = 0, stride = 0;
+    int64_t t_arrive = 0;
+    uint64_t footprint = 0;
 };
 
 struct Slot {
@@ -49,6 +123,7 @@ struct dog_server {
     int n_g = 0;
     uint64_t budget = 0;
 
+    std::unique_ptr<PinnedPool> pool;
     std::mutex mu;
     std::condition_variable cv_dispatch;  // queue grew or a slot became idle
     std::condition_variable cv_done;      // a batch completed
@@ -72,11 +147,18 @@ struct dog_server {
 
 namespace {
 
-uint64_t frame_footprint(int n_g, int64_t H, int64_t W)
+uint64_t frame_footprint(int n_g, int64_t H, int64_t W, bool on_device)
 {
     const uint64_t pitch = ((uint64_t)H + 63) / 64 * 64;
     return 2ull * (uint64_t)n_g * (uint64_t)W * pitch * sizeof(float) +
-           (uint64_t)H * (uint64_t)W * sizeof(float) + 4096;
+           (on_device ? 0 : (uint64_t)H * (uint64_t)W * sizeof(float)) + 4096;
+}
+
+void release_request(dog_server* sv, Request& r)
+{
+    if (!r.on_device && r.data)
+        sv->pool->put(const_cast<float*>(r.data), r.bytes, r.pinned);
+    r.data = nullptr;
 }
 
 void run_slot(dog_server* sv, Slot* sl)
@@ -104,15 +186,17 @@ void run_slot(dog_server* sv, Slot* sl)
         } else {
             std::vector<dog_frame> fr(n);
             for (int i = 0; i < n; ++i) {
-                fr[i].data = batch[i].pixels.data();
+                fr[i].data = batch[i].data;
                 fr[i].height = batch[i].H;
                 fr[i].width = batch[i].W;
-                fr[i].row_stride = batch[i].W;
-                fr[i].on_device = 0;
+                fr[i].row_stride = batch[i].stride;
+                fr[i].on_device = batch[i].on_device ? 1 : (batch[i].pinned ? 2 : 0);
                 fr[i].reserved = 0;
             }
             rc = dog::detect_frames(sl->ctx, &sv->prm, n, fr.data(), sl->ctx->stream, res.data());
         }
+        for (Request& r : batch)  // uploads have completed: results were read back
+            release_request(sv, r);
         const int64_t t_done = now_ns();
         uint64_t freed = 0;
         {
@@ -229,7 +313,8 @@ void destroy_server(dog_server* sv)
     for (auto& kv : sv->done)
         std::free(kv.second.blobs);
     for (Request& r : sv->queue)
-        (void)r;
+        release_request(sv, r);
+    sv->queue.clear();
     delete sv;
 }
 
@@ -256,6 +341,7 @@ int dog_server_create(int device, const dog_params* params, const dog_server_opt
     sv->prm = *params;
     if (opts)
         sv->opts = *opts;
+    sv->pool.reset(new PinnedPool(sv->opts.dry_run ? 0 : (4ull << 30)));
     if (sv->opts.max_batch_frames <= 0)
         sv->opts.max_batch_frames = 16;
     if (sv->opts.slots <= 0)
@@ -313,14 +399,15 @@ int dog_server_submit(dog_server* sv, const dog_frame* frame, uint64_t* ticket)
     int rc = dog::check_image(frame->data, frame->height, frame->width, frame->row_stride);
     if (rc != DOG_OK)
         return rc;
-    if (frame->on_device) {
-        dog::set_error("the server takes host frames");
+    if (frame->on_device != 0 && frame->on_device != 1) {
+        dog::set_error("on_device must be 0 (host) or 1 (device) for a server request");
         return DOG_EINVAL;
     }
     Request r;
     r.H = frame->height;
     r.W = frame->width;
-    r.footprint = frame_footprint(sv->n_g, r.H, r.W);
+    r.on_device = frame->on_device == 1;
+    r.footprint = frame_footprint(sv->n_g, r.H, r.W, r.on_device);
     if (r.footprint > sv->budget) {
         std::lock_guard<std::mutex> lk(sv->mu);
         sv->rejected += 1;
@@ -336,10 +423,25 @@ int dog_server_submit(dog_server* sv, const dog_frame* frame, uint64_t* ticket)
         }
     }
     r.t_arrive = now_ns();
-    r.pixels.resize((size_t)r.H * (size_t)r.W);
-    for (int64_t y = 0; y < r.H; ++y)
-        std::memcpy(r.pixels.data() + y * r.W, frame->data + y * frame->row_stride,
-                    (size_t)r.W * sizeof(float));
+    if (r.on_device) {
+        r.data = frame->data;
+        r.stride = frame->row_stride;
+    } else {
+        const size_t row_bytes = (size_t)r.W * sizeof(float);
+        float* p = static_cast<float*>(sv->pool->get(row_bytes * (size_t)r.H, &r.bytes, &r.pinned));
+        if (!p) {
+            dog::set_error("out of host memory");
+            return DOG_ENOMEM;
+        }
+        if (frame->row_stride == r.W) {
+            std::memcpy(p, frame->data, row_bytes * (size_t)r.H);
+        } else {
+            for (int64_t y = 0; y < r.H; ++y)
+                std::memcpy(p + y * r.W, frame->data + y * frame->row_stride, row_bytes);
+        }
+        r.data = p;
+        r.stride = r.W;
+    }
     {
         std::lock_guard<std::mutex> lk(sv->mu);
         r.ticket = sv->next_ticket++;

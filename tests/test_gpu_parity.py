@@ -132,8 +132,11 @@ def test_repeat_runs_bitwise_identical(dog, ctx, torch_mod):
     assert torch_mod.equal(La, Lb) and torch_mod.equal(Da, Db)
 
 
-def test_all_variants_bitwise_identical(dog, ctx, torch_mod):
-    img = synth.camera_frame(seed=4, H=200, W=300, n_blobs=40)
+@pytest.mark.parametrize("shape", [(200, 300), (192, 320)])
+def test_all_variants_bitwise_identical(dog, ctx, torch_mod, shape):
+    # (200, 300): 4-byte loads in pass 1 (width not a multiple of 64);
+    # (192, 320): 16-byte loads in pass 1 for the LDS-staged variants
+    img = synth.camera_frame(seed=4, H=shape[0], W=shape[1], n_blobs=40)
     t = _dev(torch_mod, img)
     prm = dog.Params(**CAMERA)
     ctx.set_variant(0)
