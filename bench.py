@@ -37,12 +37,14 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X figures used for the roofline (see the design notes for the derivation)
+# MI355X figures used for the roofline: 256 CUs at 2.4 GHz, 128 FP32 FMAs per
+# CU per clock.  Plain v_fma_f32 / v_fmac_f32 with vector-register operands
+# reach this rate on gfx950 (a probe measured 138-152 TFLOP/s); the blur
+# kernels use that form, so the published 157.3 TFLOP/s is the peak.
 N_CU = 256
 CLOCK_HZ = 2.4e9
-FP32_FMA_PER_CU_CLK = 64          # 4 SIMD x 16 lanes, one v_fma_f32 each per clock
-PEAK_FP32_TFLOPS = N_CU * CLOCK_HZ * FP32_FMA_PER_CU_CLK * 2 / 1e12   # 78.6: unpacked FP32
-PEAK_FP32_PACKED_TFLOPS = 157.3   # needs v_pk_fma_f32, which this build does not emit
+FP32_FMA_PER_CU_CLK = 128
+PEAK_FP32_TFLOPS = N_CU * CLOCK_HZ * FP32_FMA_PER_CU_CLK * 2 / 1e12   # 157.3
 PEAK_HBM_GBS = 8000.0
 
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "dog_kernels_frame1k_counters.txt")
@@ -153,7 +155,6 @@ def bench_mixed(dog, torch, ctx, prm, k, frames, steps):
         per.append(time.perf_counter() - s0)
     torch.cuda.synchronize()
     tp = time.perf_counter() - t0
-    del dfr
     # host frames: plain per-frame entry point vs the server fed all at once
     for f in frames[:4]:
         dog.detect(f, prm.sigma_min, prm.sigma_max, prm.sigma_ratio, prm.threshold, prm.overlap)
@@ -161,18 +162,30 @@ def bench_mixed(dog, torch, ctx, prm, k, frames, steps):
     for f in frames:
         dog.detect(f, prm.sigma_min, prm.sigma_max, prm.sigma_ratio, prm.threshold, prm.overlap)
     th = time.perf_counter() - t0
-    sv = dog.Server(prm, slots=2, max_batch_frames=32)
-    try:
-        for f in frames[:8]:
-            sv.wait(sv.submit(f))
-        t0 = time.perf_counter()
-        tickets = [sv.submit(f) for f in frames]
-        for tk in tickets:
-            sv.wait(tk)
-        ts = time.perf_counter() - t0
-        st = sv.stats()
-    finally:
-        sv.close()
+
+    def served(fr, reps=2):
+        """Time the server on all frames submitted at once; the first pass
+        warms its pinned request buffers and the slots' workspaces."""
+        sv = dog.Server(prm, slots=2, max_batch_frames=32)
+        try:
+            best, st = None, None
+            for _ in range(reps):
+                b0 = sv.stats()["batches"]
+                t0 = time.perf_counter()
+                tickets = [sv.submit(f) for f in fr]
+                for tk in tickets:
+                    sv.wait(tk)
+                dt = time.perf_counter() - t0
+                s1 = sv.stats()
+                if best is None or dt < best:
+                    best, st = dt, (len(fr) / max(1, s1["batches"] - b0))
+            return best, st
+        finally:
+            sv.close()
+
+    ts, mean_b = served(frames)
+    tsd, mean_bd = served(dfr)
+    del dfr
     return {"frames": len(frames), "mpixel_scales": round(tot, 1),
             "autotuned_variant_per_shape": choice,
             "batched_mpx_scales_per_s": round(tot / tb, 1),
@@ -182,9 +195,12 @@ def bench_mixed(dog, torch, ctx, prm, k, frames, steps):
             "per_frame_device_p50_ms": round(pct(per, 50) * 1e3, 4),
             "per_frame_device_p99_ms": round(pct(per, 99) * 1e3, 4),
             "host_per_frame_mpx_scales_per_s": round(tot / th, 1),
-            "served_saturated_mpx_scales_per_s": round(tot / ts, 1),
-            "served_over_host_per_frame": round(th / ts, 3),
-            "served_mean_batch_frames": round(st["mean_batch_frames"], 2)}
+            "served_host_frames_mpx_scales_per_s": round(tot / ts, 1),
+            "served_host_over_host_per_frame": round(th / ts, 3),
+            "served_host_mean_batch_frames": round(mean_b, 2),
+            "served_device_frames_mpx_scales_per_s": round(tot / tsd, 1),
+            "served_device_over_per_frame_device": round(tp / tsd, 3),
+            "served_device_mean_batch_frames": round(mean_bd, 2)}
 
 
 def bench_serving(dog, prm, k, pool, rate, seconds):
@@ -331,10 +347,21 @@ def main() -> int:
     roofline = {"bound": "alu", "kernel": dname, "achieved": round(achieved, 3),
                 "peak": round(PEAK_FP32_TFLOPS, 1), "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
-                "peak_packed_fp32": PEAK_FP32_PACKED_TFLOPS,
-                "frac_of_packed_peak": round(achieved / PEAK_FP32_PACKED_TFLOPS, 4),
                 "kernel_avg_us": {n: round(m * 1e3, 2) for n, m in zip(names, avg_ms)},
                 "algorithmic_flop_per_launch": flops[dname]}
+    # every kernel against both ceilings: algorithmic flops and bytes per launch
+    n_g = k + 1
+    pitch = (H + 63) // 64 * 64
+    plane_b = 4.0 * W * pitch
+    algo_bytes = {"pass1": 4.0 * H * W + n_g * plane_b, "pass2": 2.0 * n_g * plane_b,
+                  "nms": n_g * plane_b}
+    roofline["per_kernel"] = {
+        n: {"us": round(m * 1e3, 2),
+            "tflops": round(flops[n] / (m * 1e-3) / 1e12, 2),
+            "frac_fp32_peak": round(flops[n] / (m * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
+            "algorithmic_gbs": round(algo_bytes[n] / (m * 1e-3) / 1e9, 1),
+            "frac_hbm_peak": round(algo_bytes[n] / (m * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+        for n, m in zip(names, avg_ms)}
     kernel_sum_ms = sum(avg_ms)
 
     out = {"metric": "Mpixel-scales/s for DoG+NMS on 1 GPU; p99 frame latency, batched vs per-frame",

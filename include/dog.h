@@ -32,8 +32,9 @@
  *     width * (height + 63) < 2^29 (every plane stays below 2 GiB).
  *   - Blob lists are sorted by (y, x, scale), allocated with malloc by the
  *     library and released with dog_blobs_free().
- *   - Streams are hipStream_t values passed as void* (NULL = the context's
- *     own stream).  Device entry points are synchronous with respect to the
+ *   - Streams are hipStream_t values passed as void*; the sequence is
+ *     issued on that stream, after the work already queued there (NULL = the
+ *     null stream).  Device entry points are synchronous with respect to the
  *     host: they return after the results have been copied back.
  */
 #ifndef DOG_H
@@ -151,7 +152,7 @@ int dog_footprint(const dog_params* params, int32_t n_frames, const int64_t* hei
 
 /* Whole detector on a DEVICE image (d_image on the context's GPU, valid until
  * the call returns).  Work is issued on `stream` (hipStream_t, NULL = the
- * context stream); the call returns after the blob list is on the host. */
+ * null stream); the call returns after the blob list is on the host. */
 int dog_detect_device(dog_context* ctx, const float* d_image, int64_t height, int64_t width,
                       int64_t row_stride, const dog_params* params, void* stream,
                       dog_blob** blobs_out, int64_t* count_out);

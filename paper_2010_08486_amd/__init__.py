@@ -211,6 +211,9 @@ def _tensor_image(t):
 
 
 def _stream_ptr(stream=None):
+    """The HIP stream the library runs on: the given torch stream, else the
+    current one (0 = the null stream), so the detector is ordered after the
+    work that produced the input."""
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)

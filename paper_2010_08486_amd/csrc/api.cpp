@@ -11,7 +11,7 @@ using namespace dog;
 
 namespace {
 
-constexpr int kDefaultVariant = 8;  // S = 12, R = 4: fastest on 1024x1024 frames
+constexpr int kDefaultVariant = 8;  // LDS-staged, S = 16, 4 waves, 2 chunks staged
 
 int use_device(dog_context* c)
 {
@@ -19,9 +19,12 @@ int use_device(dog_context* c)
     return DOG_OK;
 }
 
+// The caller's stream as given: NULL is the null (default) stream, so work
+// queued there by the caller, which produced the input, runs first.
 hipStream_t pick_stream(dog_context* c, void* stream)
 {
-    return stream ? static_cast<hipStream_t>(stream) : c->stream;
+    (void)c;
+    return static_cast<hipStream_t>(stream);
 }
 
 void free_context(dog_context* c)
@@ -34,15 +37,15 @@ void free_context(dog_context* c)
     for (DevBuf* b : {&c->planes, &c->input, &c->tables, &c->cand})
         if (b->p)
             (void)hipFree(b->p);
-    for (PinBuf* b : {&c->h_tables, &c->h_cand, &c->h_input})
+    for (PinBuf* b : {&c->h_tables, &c->h_cand, &c->h_ends, &c->h_input})
         if (b->p)
             (void)hipHostFree(b->p);
     drop_graph(c);
     for (hipEvent_t& e : c->ev)
         if (e)
             (void)hipEventDestroy(e);
-    if (c->ev_in)
-        (void)hipEventDestroy(c->ev_in);
+    if (c->ev_done)
+        (void)hipEventDestroy(c->ev_done);
     if (c->stream)
         (void)hipStreamDestroy(c->stream);
     delete c;

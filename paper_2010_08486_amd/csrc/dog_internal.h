@@ -84,15 +84,21 @@ struct CandHeader {
 
 // Arguments of one launch sequence (all pointers are device pointers).
 struct LaunchArgs {
-    const FrameDesc* frames;
+    const FrameDesc* frames;    // frame table, or NULL: the one frame is f0
     const LadderDesc* ladders;
     const float* weights;
     const Tile* tiles1;         // pass 1, one per workgroup
     const Tile* tiles2;         // pass 2
     const Tile* tiles3;         // local maxima
     CandHeader* cand;           // header; records at (CandRec*)(cand + 1)
+    CandRec* host_recs;         // pinned host copy of the first n_host records
+    uint32_t* host_ends;        // pinned host: per local-maximum workgroup, the
+                                // end of its record range (the count is the max)
     uint32_t cap;               // record capacity
+    uint32_t n_host;
     int n1, n2, n3;             // tiles (= workgroups) of each kernel
+    int pad_;
+    FrameDesc f0;               // the frame of a one-frame launch (frames == NULL)
 };
 
 }  // namespace dog

@@ -147,6 +147,13 @@ __device__ __forceinline__ Tile my_tile(const Tile* table)
     return cst(table)[blockIdx.x];
 }
 
+// Descriptor of frame fi: from the frame table, or the one passed inline in
+// the kernel arguments of a one-frame launch.
+__device__ __forceinline__ FrameDesc frame_of(const LaunchArgs& a, int fi)
+{
+    return a.frames ? cst(a.frames)[fi] : a.f0;
+}
+
 // Pass 1: T_p = column blur of the input frame, stored transposed.
 // Tile = 64 columns x (S*NW*BI) rows of one (frame, plane) unit.
 template <int S, int R, int NW, int BI>
@@ -161,7 +168,7 @@ __global__ void __launch_bounds__(64 * NW) k_pass1(LaunchArgs a)
         const Tile tl = my_tile(a.tiles1);
         const int cb = tl.cb;
         const int band = tl.band;
-        const FrameDesc f = cst(a.frames)[tl.frame];
+        const FrameDesc f = frame_of(a, tl.frame);
         const int p = tl.plane;
         const int r = cst(a.ladders)[f.ladder].r[p];
         const float* w = a.weights + cst(a.ladders)[f.ladder].woff[p];
@@ -205,7 +212,7 @@ __global__ void __launch_bounds__(64 * NW) k_pass2(LaunchArgs a)
         const Tile tl = my_tile(a.tiles2);
         const int cb = tl.cb;
         const int band = tl.band;
-        const FrameDesc f = cst(a.frames)[tl.frame];
+        const FrameDesc f = frame_of(a, tl.frame);
         const int p = tl.plane;
         const int r = cst(a.ladders)[f.ladder].r[p];
         const float* w = a.weights + cst(a.ladders)[f.ladder].woff[p];
@@ -262,17 +269,28 @@ __device__ __forceinline__ float to_vgpr(float s)
     return v;
 }
 
+// The same multiply-adds as fma_chunk, issued by window row m = u + t: every
+// product with the register-held chunk `lo` comes before any with `hi`, so
+// the LDS reads of `hi` overlap the first half.  For each output t the taps
+// still arrive in ascending u, so the sums are bitwise those of fma_chunk.
 template <int S>
 __device__ __forceinline__ void fma_chunk_v(float (&acc)[S], const float (&lo)[S],
                                             const float (&hi)[S], const float (&wv)[S])
 {
 #pragma unroll
-    for (int u = 0; u < S; ++u) {
+    for (int m = 0; m < 2 * S - 1; ++m) {
 #pragma unroll
-        for (int t = 0; t < S; ++t)
-            acc[t] = __builtin_fmaf(wv[u], (u + t < S) ? lo[u + t] : hi[u + t - S], acc[t]);
+        for (int t = 0; t < S; ++t) {
+            const int u = m - t;
+            if (u >= 0 && u < S)
+                acc[t] = __builtin_fmaf(wv[u], m < S ? lo[m] : hi[m - S], acc[t]);
+        }
     }
 }
+
+// Taps of one plane kept in LDS by the staged blur (larger planes read them
+// with scalar loads): 512 floats cover radii up to 247.
+constexpr int kLdsWeights = 512;
 
 template <int S, int NW>
 struct StageGeom {
@@ -341,6 +359,7 @@ __global__ void __launch_bounds__(64 * NW) k_blur_lds(LaunchArgs a)
     using G = StageGeom<S, NW>;
     static_assert(S % 4 == 0 && S <= 16 && P >= 1, "tile geometry");
     __shared__ float4 lds4[G::Q * S * 16];
+    __shared__ float4 wl4[kLdsWeights / 4];
     const float* lds = reinterpret_cast<const float*>(lds4);
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -348,7 +367,7 @@ __global__ void __launch_bounds__(64 * NW) k_blur_lds(LaunchArgs a)
     if (PASS == 1 && blockIdx.x == 0 && tid == 0)
         a.cand->count = 0u;  // read by the local-maximum kernel of this sequence
     const Tile tl = my_tile(PASS == 1 ? a.tiles1 : a.tiles2);
-    const FrameDesc f = cst(a.frames)[tl.frame];
+    const FrameDesc f = frame_of(a, tl.frame);
     const int p = tl.plane;
     const int r = cst(a.ladders)[f.ladder].r[p];
     const cptr_t w = (cptr_t)(a.weights + cst(a.ladders)[f.ladder].woff[p]);
@@ -366,6 +385,14 @@ __global__ void __launch_bounds__(64 * NW) k_blur_lds(LaunchArgs a)
     const int base = y0 - r;
     const int nch = (2 * r + S) / S;   // tap chunks
     const int nload = nch + NW;        // row chunks X_0 .. X_{nch+NW-1}
+    // the plane's taps go to LDS when they fit: each step then reads its S
+    // weights as broadcast vector loads, with no scalar-load latency per step
+    const bool w_lds = nch * S <= kLdsWeights;
+    if (w_lds) {
+        const float4* w4 = reinterpret_cast<const float4*>(a.weights + cst(a.ladders)[f.ladder].woff[p]);
+        for (int q = tid; q < nch * S / 4; q += G::NT)
+            wl4[q] = w4[q];
+    }
 
     // X_0 .. X_NW into the ring, X_{NW+1} .. X_{NW+P} into registers.  Loads
     // past the last chunk fetch the last chunk again (never stored), so every
@@ -390,10 +417,23 @@ __global__ void __launch_bounds__(64 * NW) k_blur_lds(LaunchArgs a)
     // step c: taps c*S .. c*S+S-1 on X_{w+c}, X_{w+c+1}; then publish
     // X_{NW+1+c} from staging register set c % P and refill that set
     auto step = [&](int c, float4 (&st)[G::LPL]) {
-        lds_rows<S>(hi, lds, (wv + c + 1) % G::Q, lane);
+        // weights first: LDS returns in order, so the first products (with
+        // `lo` and these weights) need not wait for the rows of `hi`
+        if (w_lds) {
 #pragma unroll
-        for (int u = 0; u < S; ++u)
-            wr[u] = to_vgpr(w[c * S + u]);
+            for (int u = 0; u < S; u += 4) {
+                const float4 q = wl4[(c * S + u) / 4];
+                wr[u] = q.x;
+                wr[u + 1] = q.y;
+                wr[u + 2] = q.z;
+                wr[u + 3] = q.w;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < S; ++u)
+                wr[u] = to_vgpr(w[c * S + u]);
+        }
+        lds_rows<S>(hi, lds, (wv + c + 1) % G::Q, lane);
         fma_chunk_v<S>(acc, lo, hi, wr);
 #pragma unroll
         for (int t = 0; t < S; ++t) {
@@ -578,7 +618,12 @@ __device__ __forceinline__ void emit_plane(const CandSink& snk, const FrameDesc&
 }
 
 // Flush the workgroup's LDS records with one global atomic.
-__device__ __forceinline__ void flush_sink(const CandSink& snk, uint32_t* s_base)
+// The workgroup's records go to the device list and, for the first n_host
+// slots, also straight into pinned host memory, together with the end of the
+// workgroup's range; the host takes the count as the largest end once the
+// kernel has completed, so no readback copy is needed.
+__device__ __forceinline__ void flush_sink(const CandSink& snk, uint32_t* s_base,
+                                           const LaunchArgs& a)
 {
     __syncthreads();
     const uint32_t n = *snk.s_n < DOG_LDS_RECS ? *snk.s_n : DOG_LDS_RECS;
@@ -586,11 +631,16 @@ __device__ __forceinline__ void flush_sink(const CandSink& snk, uint32_t* s_base
         *s_base = n ? atomicAdd(&snk.cand->count, n) : 0u;
     __syncthreads();
     const uint32_t gbase = *s_base;
+    const uint32_t lim_h = snk.cap < a.n_host ? snk.cap : a.n_host;
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
         const uint32_t g = gbase + i;
         if (g < snk.cap)
             snk.recs[g] = snk.s_rec[i];
+        if (g < lim_h)
+            a.host_recs[g] = snk.s_rec[i];
     }
+    if (threadIdx.x == 0)
+        a.host_ends[blockIdx.x] = gbase + n;
 }
 
 // Local maxima of the DoG cube with threshold, compacted into records.
@@ -613,7 +663,7 @@ __global__ void __launch_bounds__(64 * NW) k_nms(LaunchArgs a)
     __syncthreads();
     const CandSink snk{&s_n, s_rec, a.cand, reinterpret_cast<CandRec*>(a.cand + 1), a.cap};
     const Tile tl = my_tile(a.tiles3);
-    const FrameDesc f = cst(a.frames)[tl.frame];
+    const FrameDesc f = frame_of(a, tl.frame);
     const DOG_CONSTANT_AS LadderDesc* ld = cst(a.ladders) + f.ladder;
     const int k = ld->n_g - 1;
     const float thr = ld->thr;
@@ -691,7 +741,7 @@ __global__ void __launch_bounds__(64 * NW) k_nms(LaunchArgs a)
             }
         }
     }
-    flush_sink(snk, &s_base);
+    flush_sink(snk, &s_base, a);
 }
 
 // dst[(p*H + y)*W + x] = src[(p*W + x)*pitch + y]: back to row-major planes.

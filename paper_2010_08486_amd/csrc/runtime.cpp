@@ -1,6 +1,8 @@
 // Host runtime: contexts, device workspace, launch tables and the launch of
 // the three-kernel sequence (pass 1, pass 2, local maxima) over a list of
 // frames, then the readback of the candidate records.
+#include <chrono>
+
 #include "runtime.h"
 
 #include <algorithm>
@@ -137,24 +139,62 @@ static long long reflect_index(long long t, long long n)
 }
 
 static constexpr size_t kRecBytes = sizeof(CandRec);
+static constexpr uint32_t kUnpublished = 0xffffffffu;  // host-side count before a launch
+
+// Wait for the work queued on st: poll an event for up to 20 ms (a frame's
+// sequence takes tens of microseconds, and a blocking wait adds the wake-up
+// latency of an interrupt), then fall back to a blocking wait.
+static int wait_stream(dog_context* c, hipStream_t st)
+{
+    if (!c->ev_done)
+        DOG_HIP(hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming));
+    DOG_HIP(hipEventRecord(c->ev_done, st));
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        const hipError_t e = hipEventQuery(c->ev_done);
+        if (e == hipSuccess)
+            return DOG_OK;
+        if (e != hipErrorNotReady)
+            return hip_fail(e, "hipEventQuery");
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(20)) {
+            DOG_HIP(hipEventSynchronize(c->ev_done));
+            return DOG_OK;
+        }
+    }
+}
+
+// Pinned host destinations of the local-maximum kernel: records after the
+// header slot of h_cand, and one range end per workgroup in h_ends.
+static void host_targets(dog_context* c, LaunchArgs* a)
+{
+    a->host_recs = reinterpret_cast<CandRec*>(static_cast<CandHeader*>(c->h_cand.p) + 1);
+    a->host_ends = static_cast<uint32_t*>(c->h_ends.p);
+    a->n_host = c->guess;
+}
 
 // The launch sequence of the current tables on stream st: upload of the
-// frame table from pinned staging, the three kernels (with timing events when
-// profiling), and the readback of the candidate header and the first
-// `guess` records into pinned memory.  Captured once into a graph, or issued
-// directly when graphs are off.
-static hipError_t enqueue_sequence(dog_context* c, hipStream_t st)
+// frame table from pinned staging (or, for one frame, its descriptor passed
+// inline in the kernel arguments, with no upload), then the three kernels
+// (with timing events when profiling).  The local-maximum kernel writes the
+// first `guess` records and its range ends straight into pinned host memory,
+// so there is no readback copy.  Captured once into a graph, or issued
+// directly.
+static hipError_t enqueue_sequence(dog_context* c, hipStream_t st, const FrameDesc* inline_f0)
 {
-    const LaunchArgs& a = c->args;
-    hipError_t e = hipMemcpyAsync(const_cast<FrameDesc*>(a.frames), c->h_tables.p, c->frames_bytes,
-                                  hipMemcpyHostToDevice, st);
+    LaunchArgs a = c->args;
+    host_targets(c, &a);
+    hipError_t e = hipSuccess;
+    if (inline_f0) {
+        a.frames = nullptr;
+        a.f0 = *inline_f0;
+    } else {
+        e = hipMemcpyAsync(const_cast<FrameDesc*>(a.frames), c->h_tables.p, c->frames_bytes,
+                           hipMemcpyHostToDevice, st);
+    }
     if (e == hipSuccess)
         e = dogk_launch_sequence(c->variant, &a, a.n1, a.n2, a.n3, c->n_gauss,
                                  c->debug_planes ? 1 : 0, c->wide1 ? 1 : 0, st,
                                  c->profiling ? c->ev : nullptr);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(c->h_cand.p, c->cand.p, sizeof(CandHeader) + kRecBytes * c->guess,
-                           hipMemcpyDeviceToHost, st);
     return e;
 }
 
@@ -191,6 +231,7 @@ static std::vector<long long> launch_key(const dog_context* c, const std::vector
     k.push_back((long long)(uintptr_t)c->cand.p);
     k.push_back((long long)(uintptr_t)c->h_tables.p);
     k.push_back((long long)(uintptr_t)c->h_cand.p);
+    k.push_back((long long)(uintptr_t)c->h_ends.p);
     k.push_back((long long)c->cap);
     for (const FrameIn& f : frames) {
         k.push_back(f.H);
@@ -273,8 +314,11 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
     // compositions is launched directly instead of re-capturing each time).
     std::vector<long long> key = launch_key(c, frames, dbg_D);
     const bool have_graph = c->graph_exec != nullptr && key == c->graph_key;
-    const bool use_graph =
-        c->use_graphs && !c->profiling && (have_graph || key == c->seen_key);
+    // one frame goes inline in the kernel arguments and is launched directly
+    // (its pixel pointer would otherwise be baked into a graph)
+    const bool inline_one = n == 1;
+    const bool use_graph = c->use_graphs && !c->profiling && !inline_one &&
+                           (have_graph || key == c->seen_key);
     c->seen_key = key;
     const bool tables_ok = c->tables_ready && key == c->graph_key;
     if (!tables_ok || (use_graph && !have_graph)) {
@@ -395,6 +439,8 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
             return rc;
         if ((rc = ctx_pin(&c->h_tables, tbytes)) != DOG_OK)
             return rc;
+        if ((rc = ctx_pin(&c->h_ends, sizeof(uint32_t) * tb3.size())) != DOG_OK)
+            return rc;
         key = launch_key(c, frames, dbg_D);  // buffers may have moved
         c->seen_key = key;
         char* dt = static_cast<char*>(c->tables.p);
@@ -447,9 +493,9 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
         }
         c->frames_bytes = frames_bytes;
         if (use_graph) {
-            // capture: frame table upload, the three kernels, the readback
+            // capture: frame table upload and the three kernels
             DOG_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-            const hipError_t e = enqueue_sequence(c, c->stream);
+            const hipError_t e = enqueue_sequence(c, c->stream, nullptr);
             hipGraph_t g = nullptr;
             const hipError_t e2 = hipStreamEndCapture(c->stream, &g);
             if (e != hipSuccess) {
@@ -472,22 +518,32 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
         std::memcpy(c->h_tables.p, fd.data(), frames_bytes);
     }
 
-    // ---- run: the caller's stream s orders the input; the sequence runs on
-    // the context stream after it
-    if (s != c->stream) {
-        if (!c->ev_in)
-            DOG_HIP(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
-        DOG_HIP(hipEventRecord(c->ev_in, s));
-        DOG_HIP(hipStreamWaitEvent(c->stream, c->ev_in, 0));
-    }
+    // ---- run on the caller's stream (NULL: the null stream), so the
+    // sequence is ordered after the work that produced the input without a
+    // cross-stream event; every call completes before it returns, so the
+    // workspace is never shared by two streams at once
+    const hipStream_t st = s;
+    uint32_t* ends = static_cast<uint32_t*>(c->h_ends.p);
+    const int n3 = c->args.n3;
+    for (int i = 0; i < n3; ++i)
+        ends[i] = kUnpublished;
     if (use_graph && c->graph_exec)
-        DOG_HIP(hipGraphLaunch(c->graph_exec, c->stream));
+        DOG_HIP(hipGraphLaunch(c->graph_exec, st));
     else
-        DOG_HIP(enqueue_sequence(c, c->stream));
-    DOG_HIP(hipStreamSynchronize(c->stream));
+        DOG_HIP(enqueue_sequence(c, st, inline_one ? &fd[0] : nullptr));
+    if ((rc = wait_stream(c, st)) != DOG_OK)
+        return rc;
     LaunchArgs a = c->args;
+    host_targets(c, &a);
     const uint32_t guess = c->guess;
-    uint32_t count = static_cast<CandHeader*>(c->h_cand.p)->count;
+    uint32_t count = 0;
+    for (int i = 0; i < n3; ++i) {
+        if (ends[i] == kUnpublished) {
+            set_error("a local-maximum workgroup did not publish its candidate range");
+            return DOG_EDEVICE;
+        }
+        count = std::max(count, ends[i]);
+    }
     if (c->profiling) {
         for (int i = 0; i < 3; ++i) {
             float ms = 0.0f;
@@ -509,11 +565,16 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
         drop_graph(c);  // points at the old buffers
         a.cand = static_cast<CandHeader*>(c->cand.p);
         a.cap = c->cap;
-        DOG_HIP(dogk_fill_u32(&a.cand->count, 1, 0u, c->stream));
-        DOG_HIP(dogk_launch_nms(c->variant, &a, a.n3, n_g, c->debug_planes ? 1 : 0, c->stream));
+        host_targets(c, &a);
+        if (inline_one) {
+            a.frames = nullptr;
+            a.f0 = fd[0];
+        }
+        DOG_HIP(dogk_fill_u32(&a.cand->count, 1, 0u, st));
+        DOG_HIP(dogk_launch_nms(c->variant, &a, a.n3, n_g, c->debug_planes ? 1 : 0, st));
         DOG_HIP(hipMemcpyAsync(c->h_cand.p, c->cand.p, sizeof(CandHeader) + kRecBytes * count,
-                               hipMemcpyDeviceToHost, c->stream));
-        DOG_HIP(hipStreamSynchronize(c->stream));
+                               hipMemcpyDeviceToHost, st));
+        DOG_HIP(hipStreamSynchronize(st));
         const uint32_t again = static_cast<CandHeader*>(c->h_cand.p)->count;
         if (again != count) {
             set_error("candidate count changed between identical launches");
@@ -522,9 +583,8 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
     } else if (count > guess) {
         char* hb = static_cast<char*>(c->h_cand.p) + sizeof(CandHeader) + kRecBytes * guess;
         const char* db = static_cast<const char*>(c->cand.p) + sizeof(CandHeader) + kRecBytes * guess;
-        DOG_HIP(hipMemcpyAsync(hb, db, kRecBytes * (count - guess), hipMemcpyDeviceToHost,
-                               c->stream));
-        DOG_HIP(hipStreamSynchronize(c->stream));
+        DOG_HIP(hipMemcpyAsync(hb, db, kRecBytes * (count - guess), hipMemcpyDeviceToHost, st));
+        DOG_HIP(hipStreamSynchronize(st));
     }
     c->last_count = count;
 

@@ -117,6 +117,7 @@ struct dog_context {
 
     dog::PinBuf h_tables;          // staging of the launch tables
     dog::PinBuf h_cand;            // readback of header + records
+    dog::PinBuf h_ends;            // per local-maximum workgroup: end of its record range
     dog::PinBuf h_input;           // staging of host frames
 
     // optional per-kernel timing with HIP events recorded around each kernel
@@ -142,7 +143,7 @@ struct dog_context {
     uint32_t guess = 0;            // records read back by the captured sequence
     bool tables_ready = false;     // device tables match graph_key
     bool use_graphs = true;        // replay a captured graph (else launch directly)
-    hipEvent_t ev_in = nullptr;    // orders the caller's stream before the sequence
+    hipEvent_t ev_done = nullptr;  // recorded after a sequence; polled for completion
 
     bool have_plan = false;
     uint64_t plan_gen = 0;

@@ -219,3 +219,23 @@ def test_kernel_timing_in_both_launch_modes(dog, torch_mod):
             c.set_profiling(False)
             assert n == 3
             assert all(m > 0 for m in ms), ms
+
+
+def test_input_written_on_default_stream_is_seen(dog, ctx, torch_mod):
+    # the frame is written by torch on the default stream behind a long
+    # matrix product; the detector must be ordered after that write
+    torch = torch_mod
+    img = synth.camera_frame(seed=77, H=512, W=512, n_blobs=80)
+    prm = dog.Params(**CAMERA)
+    ref = ctx.detect_device(_dev(torch, img), prm)
+    src = _dev(torch, img)
+    dst = torch.zeros_like(src)
+    torch.cuda.synchronize()
+    a = torch.randn(4096, 4096, device="cuda")
+    for _ in range(4):
+        a = a @ a
+        a = a / a.abs().max()
+    dst.copy_(src)
+    got = ctx.detect_device(dst, prm)
+    assert got.tobytes() == ref.tobytes()
+    float(a.sum().item())
