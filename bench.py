@@ -28,7 +28,6 @@ Also printed in the same JSON line:
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -48,7 +47,7 @@ PEAK_FP32_TFLOPS = N_CU * CLOCK_HZ * FP32_FMA_PER_CU_CLK * 2 / 1e12   # 157.3
 PEAK_HBM_GBS = 8000.0
 
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "dog_kernels_frame1k_counters.txt")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2010_08486_amd", "csrc", "kernels.hip")
+
 
 
 def pct(a, q):
@@ -57,12 +56,14 @@ def pct(a, q):
 
 
 def kernel_source_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+    from paper_2010_08486_amd.build import kernel_hash
+    return kernel_hash()
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, variant: int):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source (else None)."""
+    summary, if it was taken on the current kernel build and kernel variant
+    (else None)."""
     if not os.path.exists(PROFILE_COUNTERS):
         return None
     vals = {}
@@ -72,6 +73,8 @@ def measured_traffic(kernel: str):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    if vals.get("variant") != str(variant):
         return None
     key = "%s_hbm_bytes_per_launch" % kernel
     return float(vals[key]) if key in vals else None
@@ -343,7 +346,7 @@ def main() -> int:
     dom = int(np.argmax(avg_ms[:2]))
     dname = names[dom]
     achieved = flops[dname] / (avg_ms[dom] * 1e-3) / 1e12
-    traffic = measured_traffic(dname)
+    traffic = measured_traffic(dname, tune["variant"] if tune else args.variant)
     roofline = {"bound": "alu", "kernel": dname, "achieved": round(achieved, 3),
                 "peak": round(PEAK_FP32_TFLOPS, 1), "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
