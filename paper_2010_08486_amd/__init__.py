@@ -85,8 +85,14 @@ class Params:
     truncate: float = 4.0
 
     def c(self) -> dog_params:
-        return dog_params(self.sigma_min, self.sigma_max, self.sigma_ratio, self.threshold,
-                          self.overlap, self.truncate)
+        """The C struct (cached while the values stay the same)."""
+        key = (self.sigma_min, self.sigma_max, self.sigma_ratio, self.threshold, self.overlap,
+               self.truncate)
+        cached = self.__dict__.get("_c")
+        if cached is None or cached[0] != key:
+            cached = (key, dog_params(*key))
+            self.__dict__["_c"] = cached
+        return cached[1]
 
 
 _lib = None
@@ -210,13 +216,17 @@ def _tensor_image(t):
     return t.data_ptr(), t.shape[0], t.shape[1], t.stride(0)
 
 
-def _stream_ptr(stream=None):
+def _stream_ptr(stream=None, device=None):
     """The HIP stream the library runs on: the given torch stream, else the
-    current one (0 = the null stream), so the detector is ordered after the
-    work that produced the input."""
+    current one of `device` (0 = the null stream), so the detector is ordered
+    after the work that produced the input."""
     import torch
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return ctypes.c_void_p(s.cuda_stream)
+    if stream is not None:
+        return ctypes.c_void_p(stream.cuda_stream)
+    raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+    if raw is not None:
+        return ctypes.c_void_p(raw(torch.cuda.current_device() if device is None else device))
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
 class Context:
@@ -294,7 +304,8 @@ class Context:
         p = ctypes.POINTER(dog_blob)()
         n = ctypes.c_int64(0)
         prm = params.c()
-        _check(lib().dog_detect_device(self._h, ptr, H, W, st, ctypes.byref(prm), _stream_ptr(stream),
+        _check(lib().dog_detect_device(self._h, ptr, H, W, st, ctypes.byref(prm),
+                                       _stream_ptr(stream, image.device.index),
                                        ctypes.byref(p), ctypes.byref(n)))
         return _blobs(p, n.value)
 

@@ -681,8 +681,15 @@ __global__ void __launch_bounds__(64 * NW) k_nms(LaunchArgs a)
         if constexpr (KMAX > 0) {
             float Lr[KMAX][BN + 2];
 #pragma unroll
-            for (int p = 0; p < KMAX; ++p)
-                load_plane_rows<BN>(Lr[p], f, p <= k ? p : k, x0, voff);
+            for (int p = 0; p < KMAX; ++p) {
+                // planes past the ladder's last are never read: no loads
+                if (p <= k)
+                    load_plane_rows<BN>(Lr[p], f, p, x0, voff);
+                else
+#pragma unroll
+                    for (int j = 0; j < BN + 2; ++j)
+                        Lr[p][j] = 0.0f;
+            }
             dog_rows<BN>(Lr[0], Lr[1], ld->sigma[0], x0, f.W, ycol, s3c, dc);
 #pragma unroll
             for (int i = 0; i + 1 < KMAX; ++i) {
