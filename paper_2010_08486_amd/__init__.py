@@ -336,8 +336,9 @@ class Context:
         return L, D
 
     def detect_batch(self, frames, params: Params, stream=None):
-        """dog_detect_batch over a list of 2-D float32 numpy arrays (host) or
-        CUDA tensors (device).  Returns (list of blob arrays, list of raw counts)."""
+        """dog_detect_batch over a list of 2-D float32 frames: numpy arrays
+        (host), pinned CPU tensors (page-locked host, uploaded by DMA) or CUDA
+        tensors (device).  Returns (list of blob arrays, list of raw counts)."""
         n = len(frames)
         arr = (dog_frame * max(n, 1))()
         keep = []
@@ -350,6 +351,12 @@ class Context:
                     a = np.ascontiguousarray(a)
                 keep.append(a)
                 arr[i] = dog_frame(a.ctypes.data, a.shape[0], a.shape[1], a.strides[0] // 4, 0, 0)
+            elif not fr.is_cuda:
+                import torch
+                if (not fr.is_pinned() or fr.dtype != torch.float32 or fr.dim() != 2
+                        or fr.stride(1) != 1):
+                    raise TypeError("CPU tensor frames must be pinned 2-D float32 with unit column stride")
+                arr[i] = dog_frame(fr.data_ptr(), fr.shape[0], fr.shape[1], fr.stride(0), 2, 0)
             else:
                 ptr, H, W, st = _tensor_image(fr)
                 arr[i] = dog_frame(ptr, H, W, st, 1, 0)
