@@ -72,13 +72,21 @@ void prune_blobs(std::vector<dog_blob>& v, const std::vector<double>& sigma64, d
         if (!alive[a])
             continue;
         const double sa = sigma64[v[a].scale];
-        const double reach = std::sqrt(2.0) * sa + rmax;  // no later blob beyond this row distance can touch a
+        const double ra = std::sqrt(2.0) * sa;
+        const double reach = ra + rmax;  // no later blob beyond this row distance can touch a
         for (size_t b = a + 1; b < n; ++b) {
             if ((double)(v[b].y - v[a].y) >= reach)
                 break;
             if (!alive[b])
                 continue;
             const double sb = sigma64[v[b].scale];
+            // disks that clearly cannot touch have overlap 0 <= `overlap`:
+            // skip them without the square root (the margin keeps every pair
+            // the exact test could see as touching)
+            const double dy = (double)(v[b].y - v[a].y), dx = (double)(v[b].x - v[a].x);
+            const double rs = ra + std::sqrt(2.0) * sb;
+            if (dy * dy + dx * dx > rs * rs * (1.0 + 1e-9))
+                continue;
             const double f = overlap_fraction(v[a].y, v[a].x, sa, v[b].y, v[b].x, sb);
             if (f > overlap) {
                 if (sa < sb) {
