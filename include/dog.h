@@ -50,7 +50,7 @@ extern "C" {
 #define DOG_EINVAL (-1)   /* invalid argument                                  */
 #define DOG_ENOMEM (-2)   /* footprint exceeds the HBM budget / allocation failed */
 #define DOG_EDEVICE (-3)  /* HIP runtime error (message in dog_last_error)      */
-#define DOG_EBUSY (-4)    /* server queue full                                  */
+#define DOG_EBUSY (-4)    /* server queue full, or context awaiting finish      */
 #define DOG_EAGAIN (-5)   /* server result not ready yet                        */
 #define DOG_ENOTFOUND (-6)/* unknown server ticket                              */
 
@@ -157,8 +157,23 @@ int dog_detect_device(dog_context* ctx, const float* d_image, int64_t height, in
                       int64_t row_stride, const dog_params* params, void* stream,
                       dog_blob** blobs_out, int64_t* count_out);
 
+/* dog_detect_device in two halves, so a caller can queue the next frame's
+ * work, or do its own, while the host finishes this one (the device steps
+ * of Sec. 4.1, then the host sort and its overlap pruning).
+ * dog_detect_device_async queues the detector on `stream` (as above) and
+ * returns without waiting; d_image must stay valid and unchanged until the
+ * stream has passed the launch.  dog_detect_device_finish waits for it and
+ * returns the pruned blob list exactly as dog_detect_device would.  One
+ * launch per context at a time: until finish, every other call on the
+ * context returns DOG_EBUSY (dog_context_destroy waits for the launch);
+ * finish with nothing launched returns DOG_EINVAL.  Pipelining takes two
+ * contexts, used in turn. */
+int dog_detect_device_async(dog_context* ctx, const float* d_image, int64_t height, int64_t width,
+                            int64_t row_stride, const dog_params* params, void* stream);
+int dog_detect_device_finish(dog_context* ctx, dog_blob** blobs_out, int64_t* count_out);
+
 /* Whole detector on n_frames frames of any sizes in one launch sequence
- * (three persistent kernels over a work table built for the batch).  Frames
+ * (three kernels over tile tables built for the batch).  Frames
  * larger than the budget allows together are processed in consecutive
  * launch sequences.  results[f] receives frame f's blob list; the return
  * value is DOG_OK if every frame succeeded, else the first frame error. */

@@ -119,6 +119,8 @@ def lib() -> ctypes.CDLL:
         "dog_context_destroy": (None, [vp]),
         "dog_footprint": (i32, [ctypes.POINTER(dog_params), i32, pi64, pi64, ctypes.POINTER(u64)]),
         "dog_detect_device": (i32, [vp, vp, i64, i64, i64, ctypes.POINTER(dog_params), vp, pblob, pi64]),
+        "dog_detect_device_async": (i32, [vp, vp, i64, i64, i64, ctypes.POINTER(dog_params), vp]),
+        "dog_detect_device_finish": (i32, [vp, pblob, pi64]),
         "dog_detect_batch": (i32, [vp, i32, ctypes.POINTER(dog_frame), ctypes.POINTER(dog_params), vp,
                                    ctypes.POINTER(dog_result)]),
         "dog_results_free": (None, [ctypes.POINTER(dog_result), i32]),
@@ -234,13 +236,15 @@ class Context:
 
     def __init__(self, device: int = 0, budget_bytes: int = 0):
         self._h = ctypes.c_void_p()
+        self._inflight = None
         _check(lib().dog_context_create(device, budget_bytes, ctypes.byref(self._h)))
         self.device = device
 
     def close(self) -> None:
         if self._h:
-            lib().dog_context_destroy(self._h)
+            lib().dog_context_destroy(self._h)  # waits for a launch not yet finished
             self._h = ctypes.c_void_p()
+        self._inflight = None
 
     def __del__(self):
         try:
@@ -307,6 +311,25 @@ class Context:
         _check(lib().dog_detect_device(self._h, ptr, H, W, st, ctypes.byref(prm),
                                        _stream_ptr(stream, image.device.index),
                                        ctypes.byref(p), ctypes.byref(n)))
+        return _blobs(p, n.value)
+
+    def detect_device_async(self, image, params: Params, stream=None) -> None:
+        """Queue the detector on `image` and return; `finish()` collects the
+        blobs.  The tensor is held until then."""
+        ptr, H, W, st = _tensor_image(image)
+        prm = params.c()
+        _check(lib().dog_detect_device_async(self._h, ptr, H, W, st, ctypes.byref(prm),
+                                             _stream_ptr(stream, image.device.index)))
+        self._inflight = image
+
+    def finish(self) -> np.ndarray:
+        """Blobs of the launch queued by `detect_device_async`."""
+        p = ctypes.POINTER(dog_blob)()
+        n = ctypes.c_int64(0)
+        try:
+            _check(lib().dog_detect_device_finish(self._h, ctypes.byref(p), ctypes.byref(n)))
+        finally:
+            self._inflight = None
         return _blobs(p, n.value)
 
     def debug_candidates(self, image, params: Params) -> np.ndarray:

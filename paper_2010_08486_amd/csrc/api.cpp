@@ -19,6 +19,17 @@ int use_device(dog_context* c)
     return DOG_OK;
 }
 
+// Entry points that use a context refuse it while a launch of
+// dog_detect_device_async is still to be collected.
+int ctx_idle(dog_context* c)
+{
+    if (c->pending) {
+        set_error("a launch of dog_detect_device_async has not been finished");
+        return DOG_EBUSY;
+    }
+    return DOG_OK;
+}
+
 // The caller's stream as given: NULL is the null (default) stream, so work
 // queued there by the caller, which produced the input, runs first.
 hipStream_t pick_stream(dog_context* c, void* stream)
@@ -32,6 +43,8 @@ void free_context(dog_context* c)
     if (!c)
         return;
     (void)hipSetDevice(c->device);
+    if (c->pending && c->ev_done)
+        (void)hipEventSynchronize(c->ev_done);
     if (c->stream)
         (void)hipStreamSynchronize(c->stream);
     for (DevBuf* b : {&c->planes, &c->input, &c->tables, &c->cand})
@@ -134,7 +147,10 @@ int dog_set_variant(dog_context* ctx, int variant)
         set_error("ctx is NULL");
         return DOG_EINVAL;
     }
-    int rc = use_device(ctx);
+    int rc = ctx_idle(ctx);
+    if (rc != DOG_OK)
+        return rc;
+    rc = use_device(ctx);
     if (rc != DOG_OK)
         return rc;
     if ((rc = ctx_set_variant(ctx, variant)) != DOG_OK)
@@ -149,6 +165,8 @@ int dog_set_profiling(dog_context* ctx, int32_t on)
         set_error("ctx is NULL");
         return DOG_EINVAL;
     }
+    if (ctx->pending)
+        return ctx_idle(ctx);
     if (ctx->profiling != (on != 0))
         drop_graph(ctx);
     ctx->profiling = on != 0;
@@ -164,6 +182,8 @@ int dog_set_graph_mode(dog_context* ctx, int32_t on)
         set_error("ctx is NULL");
         return DOG_EINVAL;
     }
+    if (ctx->pending)
+        return ctx_idle(ctx);
     if (ctx->use_graphs != (on != 0))
         drop_graph(ctx);
     ctx->use_graphs = on != 0;
@@ -276,6 +296,8 @@ int dog_detect_device(dog_context* ctx, const float* d_image, int64_t height, in
     int rc = check_image(d_image, height, width, row_stride);
     if (rc != DOG_OK)
         return rc;
+    if ((rc = ctx_idle(ctx)) != DOG_OK)
+        return rc;
     if ((rc = use_device(ctx)) != DOG_OK)
         return rc;
     const Plan* P = nullptr;
@@ -287,6 +309,51 @@ int dog_detect_device(dog_context* ctx, const float* d_image, int64_t height, in
     if (rc != DOG_OK)
         return rc;
     prune_blobs(res[0], P->sigma, P->prm.overlap);
+    return export_blobs(res[0], blobs_out, count_out);
+}
+
+int dog_detect_device_async(dog_context* ctx, const float* d_image, int64_t height, int64_t width,
+                            int64_t row_stride, const dog_params* params, void* stream)
+{
+    if (!ctx) {
+        set_error("ctx is NULL");
+        return DOG_EINVAL;
+    }
+    int rc = check_image(d_image, height, width, row_stride);
+    if (rc != DOG_OK)
+        return rc;
+    if ((rc = ctx_idle(ctx)) != DOG_OK)
+        return rc;
+    if ((rc = use_device(ctx)) != DOG_OK)
+        return rc;
+    const Plan* P = nullptr;
+    if ((rc = ctx_plan(ctx, params, &P)) != DOG_OK)
+        return rc;
+    std::vector<FrameIn> fr{{d_image, (int)height, (int)width, (long long)row_stride}};
+    return launch_frames(ctx, *P, fr, pick_stream(ctx, stream), false, nullptr, nullptr, nullptr);
+}
+
+int dog_detect_device_finish(dog_context* ctx, dog_blob** blobs_out, int64_t* count_out)
+{
+    if (!ctx || !blobs_out || !count_out) {
+        set_error("invalid argument");
+        return DOG_EINVAL;
+    }
+    *blobs_out = nullptr;
+    *count_out = 0;
+    if (!ctx->pending) {
+        set_error("no launch of dog_detect_device_async to finish");
+        return DOG_EINVAL;
+    }
+    int rc = use_device(ctx);
+    if (rc != DOG_OK) {
+        ctx->pending = false;
+        return rc;
+    }
+    std::vector<std::vector<dog_blob>> res;
+    if ((rc = collect_frames(ctx, ctx->plan, &res)) != DOG_OK)
+        return rc;
+    prune_blobs(res[0], ctx->plan.sigma, ctx->plan.prm.overlap);
     return export_blobs(res[0], blobs_out, count_out);
 }
 
@@ -302,6 +369,8 @@ int dog_debug_candidates(dog_context* ctx, const float* d_image, int64_t height,
     *count_out = 0;
     int rc = check_image(d_image, height, width, row_stride);
     if (rc != DOG_OK)
+        return rc;
+    if ((rc = ctx_idle(ctx)) != DOG_OK)
         return rc;
     if ((rc = use_device(ctx)) != DOG_OK)
         return rc;
@@ -326,6 +395,8 @@ int dog_debug_planes(dog_context* ctx, const float* d_image, int64_t height, int
     }
     int rc = check_image(d_image, height, width, row_stride);
     if (rc != DOG_OK)
+        return rc;
+    if ((rc = ctx_idle(ctx)) != DOG_OK)
         return rc;
     if ((rc = use_device(ctx)) != DOG_OK)
         return rc;
@@ -357,6 +428,9 @@ int dog_detect_batch(dog_context* ctx, int32_t n_frames, const dog_frame* frames
         set_error("invalid argument");
         return DOG_EINVAL;
     }
+    const int rc = ctx_idle(ctx);
+    if (rc != DOG_OK)
+        return rc;
     return detect_frames(ctx, params, n_frames, frames, pick_stream(ctx, stream), results);
 }
 
@@ -396,8 +470,9 @@ int dog_detect(const float* image, int64_t height, int64_t width, int64_t row_st
     for (int64_t y = 0; y < height; ++y)
         std::memcpy(hp + y * width, image + y * row_stride, (size_t)width * sizeof(float));
     DOG_HIP(hipMemcpyAsync(c->input.p, hp, bytes, hipMemcpyHostToDevice, c->stream));
+    // the detector runs on the stream of the upload, after it
     return dog_detect_device(c, static_cast<const float*>(c->input.p), height, width, width, &prm,
-                             nullptr, blobs_out, count_out);
+                             c->stream, blobs_out, count_out);
 }
 
 }  // extern "C"

@@ -97,6 +97,10 @@ int dog_autotune(dog_context* ctx, const dog_params* params, const float* d_imag
     int rc = check_image(d_image, height, width, row_stride);
     if (rc != DOG_OK)
         return rc;
+    if (ctx->pending) {
+        set_error("a launch of dog_detect_device_async has not been finished");
+        return DOG_EBUSY;
+    }
     DOG_HIP(hipSetDevice(ctx->device));
     const Plan* P = nullptr;
     if ((rc = ctx_plan(ctx, params, &P)) != DOG_OK)

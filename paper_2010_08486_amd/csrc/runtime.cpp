@@ -141,14 +141,20 @@ static long long reflect_index(long long t, long long n)
 static constexpr size_t kRecBytes = sizeof(CandRec);
 static constexpr uint32_t kUnpublished = 0xffffffffu;  // host-side count before a launch
 
-// Wait for the work queued on st: poll an event for up to 20 ms (a frame's
-// sequence takes tens of microseconds, and a blocking wait adds the wake-up
-// latency of an interrupt), then fall back to a blocking wait.
-static int wait_stream(dog_context* c, hipStream_t st)
+// Completion of the sequence just queued on st: an event recorded after it.
+static int record_done(dog_context* c, hipStream_t st)
 {
     if (!c->ev_done)
         DOG_HIP(hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming));
     DOG_HIP(hipEventRecord(c->ev_done, st));
+    return DOG_OK;
+}
+
+// Wait for that event: poll it for up to 20 ms (a frame's sequence takes tens
+// of microseconds, and a blocking wait adds the wake-up latency of an
+// interrupt), then fall back to a blocking wait.
+static int wait_done(dog_context* c)
+{
     const auto t0 = std::chrono::steady_clock::now();
     for (;;) {
         const hipError_t e = hipEventQuery(c->ev_done);
@@ -241,14 +247,16 @@ static std::vector<long long> launch_key(const dog_context* c, const std::vector
     return k;
 }
 
-int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames, hipStream_t s,
-               std::vector<std::vector<dog_blob>>* out, bool dbg_D, long long* pitch0,
-               float** L0, float** D0)
+int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames, hipStream_t s,
+                  bool dbg_D, long long* pitch0, float** L0, float** D0)
 {
     const int n = (int)frames.size();
-    out->assign(n, {});
-    if (n == 0)
+    c->pending = false;
+    c->pend_n = n;
+    if (n == 0) {
+        c->pending = true;
         return DOG_OK;
+    }
     if (!c->variant_forced) {
         const int v = choose_variant(c, frames, P);
         if (v != c->variant) {
@@ -520,8 +528,8 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
 
     // ---- run on the caller's stream (NULL: the null stream), so the
     // sequence is ordered after the work that produced the input without a
-    // cross-stream event; every call completes before it returns, so the
-    // workspace is never shared by two streams at once
+    // cross-stream event.  The context takes no other work until the launch
+    // is collected, so the workspace is never shared by two streams at once
     const hipStream_t st = s;
     uint32_t* ends = static_cast<uint32_t*>(c->h_ends.p);
     const int n3 = c->args.n3;
@@ -531,8 +539,34 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
         DOG_HIP(hipGraphLaunch(c->graph_exec, st));
     else
         DOG_HIP(enqueue_sequence(c, st, inline_one ? &fd[0] : nullptr));
-    if ((rc = wait_stream(c, st)) != DOG_OK)
+    if ((rc = record_done(c, st)) != DOG_OK)
         return rc;
+    c->pend_inline = inline_one;
+    c->pend_f0 = fd[0];
+    c->pend_stream = st;
+    c->pending = true;
+    return DOG_OK;
+}
+
+int collect_frames(dog_context* c, const Plan& P, std::vector<std::vector<dog_blob>>* out)
+{
+    if (!c->pending) {
+        set_error("no launch to collect");
+        return DOG_EINVAL;
+    }
+    c->pending = false;
+    const int n = c->pend_n;
+    out->assign(n, {});
+    if (n == 0)
+        return DOG_OK;
+    const bool inline_one = c->pend_inline;
+    const hipStream_t st = c->pend_stream;
+    const int n_g = P.n_g;
+    int rc = wait_done(c);
+    if (rc != DOG_OK)
+        return rc;
+    uint32_t* ends = static_cast<uint32_t*>(c->h_ends.p);
+    const int n3 = c->args.n3;
     LaunchArgs a = c->args;
     host_targets(c, &a);
     const uint32_t guess = c->guess;
@@ -568,7 +602,7 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
         host_targets(c, &a);
         if (inline_one) {
             a.frames = nullptr;
-            a.f0 = fd[0];
+            a.f0 = c->pend_f0;
         }
         DOG_HIP(dogk_fill_u32(&a.cand->count, 1, 0u, st));
         DOG_HIP(dogk_launch_nms(c->variant, &a, a.n3, n_g, c->debug_planes ? 1 : 0, st));
@@ -607,6 +641,16 @@ int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames
     for (auto& v : *out)
         sort_blobs(v);
     return DOG_OK;
+}
+
+int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames, hipStream_t s,
+               std::vector<std::vector<dog_blob>>* out, bool dbg_D, long long* pitch0,
+               float** L0, float** D0)
+{
+    const int rc = launch_frames(c, P, frames, s, dbg_D, pitch0, L0, D0);
+    if (rc != DOG_OK)
+        return rc;
+    return collect_frames(c, P, out);
 }
 
 }  // namespace dog

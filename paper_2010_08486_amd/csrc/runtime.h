@@ -145,6 +145,14 @@ struct dog_context {
     bool use_graphs = true;        // replay a captured graph (else launch directly)
     hipEvent_t ev_done = nullptr;  // recorded after a sequence; polled for completion
 
+    // a launch not yet collected (dog_detect_device_async): frame count,
+    // the one-frame descriptor passed inline, and the stream
+    bool pending = false;
+    int pend_n = 0;
+    bool pend_inline = false;
+    dog::FrameDesc pend_f0{};
+    hipStream_t pend_stream = nullptr;
+
     bool have_plan = false;
     uint64_t plan_gen = 0;
     dog::Plan plan;
@@ -167,6 +175,12 @@ int choose_variant(const dog_context* c, const std::vector<FrameIn>& frames, con
 int run_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames,
                hipStream_t s, std::vector<std::vector<dog_blob>>* out, bool dbg_D,
                long long* pitch0, float** L0, float** D0);
+// The two halves of run_frames: queue the launch sequence on s (returns once
+// it is queued and marks the context pending), then wait for it and turn the
+// candidate records into sorted blob lists per frame.
+int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& frames,
+                  hipStream_t s, bool dbg_D, long long* pitch0, float** L0, float** D0);
+int collect_frames(dog_context* c, const Plan& P, std::vector<std::vector<dog_blob>>* out);
 
 const char* last_error();
 int check_image(const void* p, int64_t h, int64_t w, int64_t stride);
