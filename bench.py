@@ -13,9 +13,10 @@ flight).
 Also printed in the same JSON line:
   * the same steps one synchronous call at a time: per-frame latency p50/p99
     and the unpipelined rate;
-  * roofline of the dominant kernel, from HIP events recorded around each
-    kernel on the library stream during a second run of the same steps
-    (issued directly: events inside a replayed graph cannot be timed);
+  * roofline of the dominant kernel, from HIP start/end events of each
+    kernel's dispatch on the stream it runs on, during a further run of the
+    same steps (issued directly: events inside a replayed graph cannot be
+    timed);
   * the autotuner's per-variant timings for the frame and its choice;
   * a uniform batch of 64 1024x1024 frames through the batched entry point
     vs one frame at a time (throughput ratio and latency);
@@ -65,9 +66,9 @@ def kernel_source_hash() -> str:
 
 
 def measured_traffic(kernel: str, variant: int):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel build and kernel variant
-    (else None)."""
+    """HBM bytes per launch of `kernel` in kernel variant `variant` from the
+    committed rocprofv3 counter summary, if it was taken on the current kernel
+    build and covers that variant (else None)."""
     if not os.path.exists(PROFILE_COUNTERS):
         return None
     vals = {}
@@ -78,9 +79,7 @@ def measured_traffic(kernel: str, variant: int):
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    if vals.get("variant") != str(variant):
-        return None
-    key = "%s_hbm_bytes_per_launch" % kernel
+    key = "v%d.%s_hbm_bytes_per_launch" % (variant, kernel)
     return float(vals[key]) if key in vals else None
 
 
@@ -349,8 +348,8 @@ def main() -> int:
     dt_sync = time.perf_counter() - t0
     assert blobs_sync.tobytes() == blobs.tobytes()
 
-    # ---- kernel-timing region: the same K steps with HIP events recorded
-    # around each kernel on the library stream (events cannot be timed inside
+    # ---- kernel-timing region: the same K steps with HIP start/end events of
+    # each kernel's dispatch on the stream it runs on (events cannot be timed inside
     # a graph, so these steps issue the same kernels directly)
     ctx.set_profiling(True)
     torch.cuda.synchronize()

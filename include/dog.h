@@ -214,7 +214,8 @@ int dog_set_variant(dog_context* ctx, int variant);
  * context's device) with the per-kernel event timing below: one untimed
  * launch then `reps` timed ones (reps = 0 means 5), and records the variant
  * with the least summed kernel time as the choice for (height, width, the
- * blur radii of params).  us_out (may be NULL) receives the mean microseconds
+ * blur radii of params); the built-in default is kept when it is within 2 %
+ * of that time, so repeated tuning does not flip between near-equal variants.  us_out (may be NULL) receives the mean microseconds
  * of every variant (dog_num_variants() doubles); *variant_out (may be NULL)
  * the winner.  A launch whose dominant shape (most pixels) was not tuned uses
  * the choice of the tuned shape with the same radii nearest in pixel count.
@@ -224,7 +225,8 @@ int dog_set_variant(dog_context* ctx, int variant);
  * (a file of another build loads nothing and is not an error).
  * dog_autotune_choice reports the variant automatic selection would take for
  * one frame of the given shape.  Errors: DOG_EINVAL (NULL pointer, bad shape
- * or parameters, unreadable or unwritable file), device errors. */
+ * or parameters, unreadable or unwritable file), DOG_EBUSY (a launch of
+ * dog_detect_device_async not finished), device errors. */
 int dog_autotune(dog_context* ctx, const dog_params* params, const float* d_image, int64_t height,
                  int64_t width, int64_t row_stride, int32_t reps, int32_t* variant_out,
                  double* us_out);

@@ -118,6 +118,7 @@ int dog_autotune(dog_context* ctx, const dog_params* params, const float* d_imag
     int best = -1;
     double best_us = 1e300;
     std::vector<std::vector<dog_blob>> out;
+    std::vector<double> times(dogk_num_variants(), 1e300);
     for (int v = 0; v < dogk_num_variants(); ++v) {
         if ((rc = ctx_set_variant(ctx, v)) != DOG_OK)
             break;
@@ -134,6 +135,7 @@ int dog_autotune(dog_context* ctx, const dog_params* params, const float* d_imag
             break;
         const double us = (ctx->kernel_ms[0] + ctx->kernel_ms[1] + ctx->kernel_ms[2]) * 1e3 /
                           (double)std::max<int64_t>(1, ctx->kernel_launches);
+        times[v] = us;
         if (us_out)
             us_out[v] = us;
         if (us < best_us) {
@@ -141,6 +143,11 @@ int dog_autotune(dog_context* ctx, const dog_params* params, const float* d_imag
             best = v;
         }
     }
+    // the built-in default stands unless another variant beats it by more
+    // than the timing noise (2 %), so repeated tuning gives the same choice
+    if (rc == DOG_OK && best >= 0 && best != ctx->variant_auto &&
+        times[ctx->variant_auto] <= best_us * 1.02)
+        best = ctx->variant_auto;
     ctx->profiling = saved_prof;
     ctx->variant_forced = saved_forced;
     for (double& m : ctx->kernel_ms)

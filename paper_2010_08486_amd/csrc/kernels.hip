@@ -27,6 +27,7 @@
 // interleaved so workgroup b, placed on XCD b mod 8, stays in that XCD's L2.
 // No atomics are needed to distribute work.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include "dog_internal.h"
 
@@ -868,8 +869,9 @@ int dogk_variant_ring(int v) { return dog::kSets[v].R; }
 // Launch pass 1, pass 2 and the local-maximum kernel on `stream`, one
 // workgroup per tile of each table.  wide1: every frame's rows are 16-byte
 // aligned and its width is a multiple of 64, so pass 1 may use 16-byte loads.
-// If ev is non-NULL, events ev[0..3] are recorded before, between and after
-// the kernels.  Returns the first launch error.
+// If ev is non-NULL, ev[2i] and ev[2i+1] take the start and end of kernel i's
+// execution (the dispatch's own timestamps, so the launch gap before a kernel
+// is not counted).  Returns the first launch error.
 hipError_t dogk_launch_sequence(int variant, const dog::LaunchArgs* args, int grid1, int grid2,
                                 int grid3, int max_gauss, int debug, int wide1, hipStream_t stream,
                                 hipEvent_t* ev)
@@ -878,22 +880,18 @@ hipError_t dogk_launch_sequence(int variant, const dog::LaunchArgs* args, int gr
     const void* pass1 = wide1 && k.pass1w ? k.pass1w : k.pass1;
     const void* nms = k.nms[max_gauss <= DOG_NMS_KMAX ? 1 : 0][debug ? 1 : 0];
     void* params[] = {const_cast<dog::LaunchArgs*>(args)};
-    hipError_t e = hipSuccess;
-    if (ev)
-        e = hipEventRecord(ev[0], stream);
-    if (e == hipSuccess)
-        e = hipLaunchKernel(pass1, dim3(grid1), dim3(64 * k.NW), params, 0, stream);
-    if (e == hipSuccess && ev)
-        e = hipEventRecord(ev[1], stream);
-    if (e == hipSuccess)
-        e = hipLaunchKernel(k.pass2, dim3(grid2), dim3(64 * k.NW), params, 0, stream);
-    if (e == hipSuccess && ev)
-        e = hipEventRecord(ev[2], stream);
-    if (e == hipSuccess)
-        e = hipLaunchKernel(nms, dim3(grid3), dim3(64 * k.NWN), params, 0, stream);
-    if (e == hipSuccess && ev)
-        e = hipEventRecord(ev[3], stream);
-    return e;
+    const void* fn[3] = {pass1, k.pass2, nms};
+    const int grid[3] = {grid1, grid2, grid3};
+    const int block[3] = {64 * k.NW, 64 * k.NW, 64 * k.NWN};
+    for (int i = 0; i < 3; ++i) {
+        const hipError_t e =
+            ev ? hipExtLaunchKernel(fn[i], dim3(grid[i]), dim3(block[i]), params, 0, stream,
+                                    ev[2 * i], ev[2 * i + 1], 0)
+               : hipLaunchKernel(fn[i], dim3(grid[i]), dim3(block[i]), params, 0, stream);
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t dogk_launch_nms(int variant, const dog::LaunchArgs* args, int grid3, int max_gauss,

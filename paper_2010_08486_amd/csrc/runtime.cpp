@@ -495,7 +495,7 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
             c->cap, std::max<uint32_t>(2048, c->last_count + c->last_count / 2 + 256));
 
         if (c->profiling) {
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 6; ++i)
                 if (!c->ev[i])
                     DOG_HIP(hipEventCreate(&c->ev[i]));
         }
@@ -581,7 +581,7 @@ int collect_frames(dog_context* c, const Plan& P, std::vector<std::vector<dog_bl
     if (c->profiling) {
         for (int i = 0; i < 3; ++i) {
             float ms = 0.0f;
-            DOG_HIP(hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
+            DOG_HIP(hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]));
             c->kernel_ms[i] += ms;
         }
         c->kernel_launches += 1;

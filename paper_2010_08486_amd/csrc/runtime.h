@@ -120,10 +120,10 @@ struct dog_context {
     dog::PinBuf h_ends;            // per local-maximum workgroup: end of its record range
     dog::PinBuf h_input;           // staging of host frames
 
-    // optional per-kernel timing with HIP events recorded around each kernel
-    // on the stream it is launched on
+    // optional per-kernel timing: start and end events of each kernel's
+    // dispatch, on the stream it is launched on
     bool profiling = false;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     double kernel_ms[3] = {0.0, 0.0, 0.0};
     int64_t kernel_launches = 0;
 

@@ -40,7 +40,9 @@ def test_autotune_picks_fastest_and_keeps_results(dog, torch_mod, tmp_path):
         v, us = c.autotune(t, prm, reps=2)
         assert len(us) == dog.num_variants()
         assert all(u > 0 for u in us), us
-        assert 0 <= v < dog.num_variants() and us[v] == min(us)
+        # the fastest variant, or the default when it is within 2 % of it
+        assert 0 <= v < dog.num_variants()
+        assert us[v] == min(us) or (v == default and us[v] <= min(us) * 1.02)
         assert c.autotune_choice(prm, 384, 448) == v
         # nearest tuned shape of the same radii serves an untuned shape
         assert c.autotune_choice(prm, 400, 440) == v
