@@ -463,24 +463,47 @@ __global__ void __launch_bounds__(64 * NW) k_blur_lds(LaunchArgs a)
         if (c + k < nch)
             step(c + k, stg[k]);
 
-    const int col = col0 + lane;
-    const int o0 = y0 + wv * S;  // first output of this wave along the blur
     if (PASS == 1) {
-        if (col < f.W && o0 < f.H) {
-            float* __restrict__ dst = f.T + ((long long)p * f.W + col) * f.pitch + o0;
-            if (o0 + S <= f.H) {
+        // T is stored transposed: output column x is a row of T.  The tile
+        // (64 columns x NW*S outputs) goes through LDS (the ring is free after
+        // the last barrier) so that consecutive threads write consecutive
+        // 16-byte pieces of each T row; a direct store from the accumulators
+        // would scatter every store instruction over 64 rows of T.
+        constexpr int TS = NW * S + 4;   // LDS floats per column (padded)
+        constexpr int Q4 = NW * S / 4;   // 16-byte pieces per column
+        constexpr int NQ = 64 * Q4;
+        static_assert(64 * TS <= G::Q * S * 64, "transpose tile fits the ring");
+        float* tr = reinterpret_cast<float*>(lds4);
 #pragma unroll
-                for (int t = 0; t < S; t += 4)
-                    *reinterpret_cast<float4*>(dst + t) =
-                        make_float4(acc[t], acc[t + 1], acc[t + 2], acc[t + 3]);
-            } else {
+        for (int t = 0; t < S; t += 4)
+            *reinterpret_cast<float4*>(tr + lane * TS + wv * S + t) =
+                make_float4(acc[t], acc[t + 1], acc[t + 2], acc[t + 3]);
+        __syncthreads();
 #pragma unroll
-                for (int t = 0; t < S; ++t)
-                    if (o0 + t < f.H)
-                        dst[t] = acc[t];
+        for (int i = 0; i < (NQ + G::NT - 1) / G::NT; ++i) {
+            const int q = tid + i * G::NT;
+            if (NQ % G::NT == 0 || q < NQ) {
+                const int cx = q / Q4, y4 = q - cx * Q4;
+                const int x = col0 + cx, y = y0 + 4 * y4;
+                if (x < f.W && y < f.H) {
+                    const float4 v = *reinterpret_cast<const float4*>(tr + cx * TS + 4 * y4);
+                    float* __restrict__ dst = f.T + ((long long)p * f.W + x) * f.pitch + y;
+                    if (y + 4 <= f.H) {
+                        *reinterpret_cast<float4*>(dst) = v;
+                    } else {
+                        dst[0] = v.x;
+                        if (y + 1 < f.H)
+                            dst[1] = v.y;
+                        if (y + 2 < f.H)
+                            dst[2] = v.z;
+                    }
+                }
             }
         }
     } else {
+        // L rows are contiguous along the lanes: direct coalesced stores
+        const int col = col0 + lane;
+        const int o0 = y0 + wv * S;  // first output of this wave along the blur
         if (col < f.H) {
             float* __restrict__ dstp = f.L + (long long)p * f.W * f.pitch;
 #pragma unroll
