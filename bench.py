@@ -6,9 +6,9 @@ Headline: Mpixel-scales/s of the whole detector path (blur stack, DoG,
 pruning) on one 1024x1024 fp32 camera frame (500 blobs, sigma 1..30, ratio
 1.6 -> 8 DoG planes, threshold 0.05, overlap 0.5) already resident in HBM.
 Mpixel-scales = H * W * k per frame.  A step is one frame from launch to its
-pruned blob list on the host; two contexts are used in turn, so step i+1's
-kernels are queued before step i's blobs are collected (two frames in
-flight).
+pruned blob list on the host; three contexts, each on its own stream, are
+used in turn, so steps i+1 and i+2 are queued before step i's blobs are
+collected (three frames in flight, --inflight).
 
 Also printed in the same JSON line:
   * the same steps one synchronous call at a time: per-frame latency p50/p99
@@ -172,7 +172,7 @@ def bench_mixed(dog, torch, ctx, prm, k, frames, steps):
     def served(fr, reps=2):
         """Time the server on all frames submitted at once; the first pass
         warms its pinned request buffers and the slots' workspaces."""
-        sv = dog.Server(prm, slots=2, max_batch_frames=32)
+        sv = dog.Server(prm, max_batch_frames=32)
         try:
             best, st = None, None
             for _ in range(reps):
@@ -214,7 +214,7 @@ def bench_serving(dog, prm, k, pool, rate, seconds):
     of uneven frames, submitted at their arrival times."""
     import synth
     arrivals = synth.poisson_arrivals(rate=rate, duration=seconds)
-    sv = dog.Server(prm, slots=2, max_batch_frames=16)
+    sv = dog.Server(prm, max_batch_frames=16)
     try:
         for f in pool[:8]:
             sv.wait(sv.submit(f))
@@ -259,6 +259,8 @@ def main() -> int:
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--variant", type=int, default=-1)
+    ap.add_argument("--inflight", type=int, default=3,
+                    help="frames in flight in the timed steps (contexts and streams used in turn)")
     ap.add_argument("--pmc-workload", type=int, default=0,
                     help="only run N detector steps on the 1024x1024 frame, then a plain 256 MiB "
                          "device copy (the calibration for rocprofv3 byte counters), and exit")
@@ -311,27 +313,35 @@ def main() -> int:
         print("pmc workload done", flush=True)
         return 0
 
-    # a second context with the same kernel variant: frame i+1 is queued on
-    # one context before frame i's blobs are collected from the other
-    ctx2 = dog.Context(0)
-    ctx2.set_variant(tune["variant"] if tune else args.variant)
+    # N contexts with the same kernel variant, each launching on its own
+    # stream: frames i+1 .. i+N-1 are queued before frame i's blobs are
+    # collected, so the host work of one frame and the kernels of the others
+    # overlap, and kernels of different frames share the GPU (one frame's
+    # local-maximum pass, bound by memory, beside another's blur)
+    nf = args.inflight
+    if nf < 1:
+        print("--inflight must be at least 1", file=sys.stderr)
+        return 2
+    ctxs = [ctx] + [dog.Context(0) for _ in range(nf - 1)]
+    for c in ctxs[1:]:
+        c.set_variant(tune["variant"] if tune else args.variant)
+    streams = [torch.cuda.Stream(device=dev) for _ in range(nf)]
+    torch.cuda.synchronize()
     for _ in range(args.warmup):
-        ctx.detect_device(t_img, prm)
-        ctx2.detect_device(t_img, prm)
+        for c, st in zip(ctxs, streams):
+            c.detect_device(t_img, prm, stream=st)
     torch.cuda.synchronize()
 
     # ---- timed region: K whole-path steps, each one frame from launch to its
-    # pruned blob list on the host, two contexts in turn so that the host
-    # work of step i (completion, count, sort, prune, export) overlaps the
-    # kernels of step i+1
-    ctxs = (ctx, ctx2)
+    # pruned blob list on the host
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ctxs[0].detect_device_async(t_img, prm)
-    for i in range(1, args.steps + 1):
+    for i in range(nf - 1):
+        ctxs[i].detect_device_async(t_img, prm, stream=streams[i])
+    for i in range(nf - 1, args.steps + nf - 1):
         if i < args.steps:
-            ctxs[i % 2].detect_device_async(t_img, prm)
-        blobs = ctxs[(i - 1) % 2].finish()
+            ctxs[i % nf].detect_device_async(t_img, prm, stream=streams[i % nf])
+        blobs = ctxs[(i - nf + 1) % nf].finish()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
 
@@ -411,7 +421,7 @@ def main() -> int:
                                   "500 blobs), sigma 1..30 ratio 1.6 (8 DoG planes), threshold "
                                   "0.05, overlap 0.5", "frames_per_step": 1, "height": H,
                       "width": W, "dog_planes": k, "parallelism": "single GPU",
-                      "frames_in_flight": 2},
+                      "frames_in_flight": nf},
            "roofline": roofline,
            "latency_ms": {"p50": round(pct(lat, 50) * 1e3, 4), "p99": round(pct(lat, 99) * 1e3, 4)},
            "sync_ms_per_step": round(dt_sync / args.steps * 1e3, 4),
@@ -464,8 +474,8 @@ def main() -> int:
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(img, prm, k)
-    ctx.close()
-    ctx2.close()
+    for c in ctxs:
+        c.close()
     print(json.dumps(out))
     return 0
 

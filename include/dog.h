@@ -269,7 +269,7 @@ int dog_kernel_times(dog_context* ctx, double* ms_out, int64_t* launches_out);
  * Results are the same as dog_detect on the frame alone. */
 typedef struct {
     int32_t max_batch_frames;   /* frames per launch sequence (<= 0: 16)              */
-    int32_t slots;              /* launch sequences in flight (<= 0: 2)               */
+    int32_t slots;              /* launch sequences in flight (<= 0: 3)               */
     int32_t queue_capacity;     /* waiting requests before DOG_EBUSY (<= 0: 4096)    */
     int32_t dry_run;            /* test hook: no GPU work; a batch takes
                                    dry_run_us_per_mpx per Mpixel and finds no blobs  */
@@ -278,6 +278,10 @@ typedef struct {
     double dry_run_us_per_mpx;
     const char* tune_cache;     /* autotuner choices (dog_autotune_save) loaded into
                                    every slot context, or NULL                        */
+    int64_t max_batch_pixels;   /* pixels per launch sequence (0: 2^21, two 1024x1024
+                                   frames, so a batch's planes stay close to the
+                                   256 MB Infinity Cache between its kernels; < 0:
+                                   no cap); a batch always takes at least one frame  */
 } dog_server_opts;
 
 typedef struct {

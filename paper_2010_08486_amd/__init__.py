@@ -62,7 +62,8 @@ class dog_server_opts(ctypes.Structure):
     _fields_ = [("max_batch_frames", ctypes.c_int32), ("slots", ctypes.c_int32),
                 ("queue_capacity", ctypes.c_int32), ("dry_run", ctypes.c_int32),
                 ("hbm_budget_bytes", ctypes.c_uint64), ("max_wait_ms", ctypes.c_double),
-                ("dry_run_us_per_mpx", ctypes.c_double), ("tune_cache", ctypes.c_char_p)]
+                ("dry_run_us_per_mpx", ctypes.c_double), ("tune_cache", ctypes.c_char_p),
+                ("max_batch_pixels", ctypes.c_int64)]
 
 
 class dog_stats(ctypes.Structure):
@@ -436,14 +437,16 @@ class Server:
     """dog_server: continuous batching of host frames (see include/dog.h)."""
 
     def __init__(self, params: Params, device: int = 0, max_batch_frames: int = 16,
-                 slots: int = 2, queue_capacity: int = 4096, hbm_budget_bytes: int = 0,
+                 slots: int = 3, queue_capacity: int = 4096, hbm_budget_bytes: int = 0,
                  max_wait_ms: float = 0.0, dry_run: bool = False,
-                 dry_run_us_per_mpx: float = 0.0, tune_cache: str | None = None):
+                 dry_run_us_per_mpx: float = 0.0, tune_cache: str | None = None,
+                 max_batch_pixels: int = 0):
         self._h = ctypes.c_void_p()
         self._held = {}
         opts = dog_server_opts(max_batch_frames, slots, queue_capacity, 1 if dry_run else 0,
                                hbm_budget_bytes, max_wait_ms, dry_run_us_per_mpx,
-                               os.fsencode(tune_cache) if tune_cache else None)
+                               os.fsencode(tune_cache) if tune_cache else None,
+                               max_batch_pixels)
         prm = params.c()
         _check(lib().dog_server_create(device, ctypes.byref(prm), ctypes.byref(opts),
                                        ctypes.byref(self._h)))

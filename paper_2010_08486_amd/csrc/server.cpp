@@ -263,10 +263,16 @@ void run_dispatcher(dog_server* sv)
         }
         std::vector<Request> batch;
         uint64_t fp = 0;
+        int64_t px = 0;
         while (!sv->queue.empty() && (int)batch.size() < sv->opts.max_batch_frames) {
             const Request& r = sv->queue.front();
             if (sv->reserved + fp + r.footprint > sv->budget)
                 break;  // admission: wait until running batches free memory
+            const int64_t rpx = (int64_t)r.H * (int64_t)r.W;
+            if (!batch.empty() && sv->opts.max_batch_pixels > 0 &&
+                px + rpx > sv->opts.max_batch_pixels)
+                break;  // the batch's planes would outgrow the cache
+            px += rpx;
             fp += r.footprint;
             batch.push_back(std::move(sv->queue.front()));
             sv->queue.pop_front();
@@ -345,7 +351,9 @@ int dog_server_create(int device, const dog_params* params, const dog_server_opt
     if (sv->opts.max_batch_frames <= 0)
         sv->opts.max_batch_frames = 16;
     if (sv->opts.slots <= 0)
-        sv->opts.slots = 2;
+        sv->opts.slots = 3;
+    if (sv->opts.max_batch_pixels == 0)
+        sv->opts.max_batch_pixels = (int64_t)1 << 21;
     if (sv->opts.queue_capacity <= 0)
         sv->opts.queue_capacity = 4096;
     if (sv->opts.max_wait_ms < 0.0 || sv->opts.dry_run_us_per_mpx < 0.0) {

@@ -102,3 +102,27 @@ def test_invalid_server_arguments():
     with dog.Server(PRM, dry_run=True) as sv:
         with pytest.raises(dog.DogError):
             sv.submit(np.zeros((0, 4), np.float32))
+
+
+def test_pixel_cap_bounds_batch_size():
+    # 1024x1024 frames: the default cap of 2^21 pixels gives at most two
+    # frames per batch; a negative cap lets max_batch_frames decide
+    with dog.Server(PRM, dry_run=True, dry_run_us_per_mpx=20000.0, slots=1,
+                    max_batch_frames=8) as sv:
+        for f in _frames(9, 1024, 1024):
+            sv.submit(f)
+        sv.drain()
+        st = sv.stats()
+        assert st["completed"] == 9 and st["batches"] >= 5
+    with dog.Server(PRM, dry_run=True, dry_run_us_per_mpx=20000.0, slots=1,
+                    max_batch_frames=8, max_batch_pixels=-1) as sv:
+        for f in _frames(9, 1024, 1024):
+            sv.submit(f)
+        sv.drain()
+        st = sv.stats()
+        assert st["completed"] == 9 and st["batches"] <= 3
+    # a frame larger than the cap still runs, alone
+    with dog.Server(PRM, dry_run=True, slots=1, max_batch_pixels=1000) as sv:
+        t = sv.submit(_frames(1, 64, 64)[0])
+        blobs, info = sv.wait(t)
+        assert info["status"] == 0
