@@ -62,6 +62,7 @@ def _load():
         "orc_lens_area": (dbl, [dbl, dbl, dbl]),
         "orc_overlap_fraction": (dbl, [dbl, dbl, dbl, dbl, dbl, dbl]),
         "orc_prune": (i64, [i64, vp, vp, vp, dbl, vp]),
+        "orc_prune_coalesce": (i64, [i64, vp, vp, vp, dbl, vp, vp]),
         "orc_detect": (i64, [vp, i64, i64, i64, dbl, dbl, dbl, dbl, dbl, dbl,
                              vp, vp, vp, i64, vp]),
     }
@@ -186,13 +187,19 @@ def overlap_fraction(y1, x1, s1, y2, x2, s2) -> float:
     return float(_load().orc_overlap_fraction(y1, x1, s1, y2, x2, s2))
 
 
-def prune(y, x, sigma, overlap: float) -> np.ndarray:
-    """Keep mask (bool) after overlap pruning of blobs given in (y, x, scale) order."""
+def prune(y, x, sigma, overlap: float, coalesce: bool = False):
+    """Keep mask (bool) after overlap pruning of blobs given in (y, x, scale)
+    order.  With coalesce (Sec. 4.1, averaging the radius), returns
+    (keep mask, final sigma of every blob)."""
     yy = np.ascontiguousarray(y, dtype=np.int32)
     xx = np.ascontiguousarray(x, dtype=np.int32)
     ss = np.ascontiguousarray(sigma, dtype=np.float64)
     n = len(yy)
     keep = np.empty(max(n, 1), np.uint8)
+    if coalesce:
+        out = np.empty(max(n, 1), np.float64)
+        _load().orc_prune_coalesce(n, _p(yy), _p(xx), _p(ss), overlap, _p(keep), _p(out))
+        return keep[:n].astype(bool), out[:n]
     _load().orc_prune(n, _p(yy), _p(xx), _p(ss), overlap, _p(keep))
     return keep[:n].astype(bool)
 

@@ -333,6 +333,49 @@ int64_t orc_prune(int64_t n, const int32_t *y, const int32_t *x,
     return m;
 }
 
+/* Coalescing form of the overlap step (Sec. 4.1: overlapping blobs are
+ * coalesced by averaging the radius; reading R7b).  Same visiting order and
+ * overlap test as orc_prune, on the blobs' current sigmas: of an overlapping
+ * pair the blob with the smaller sigma is removed (b on a tie) and the other
+ * takes the mean of the two sigmas, which later pairs then see.  sigma_out[n]
+ * receives every blob's final sigma (meaningful for survivors).  Returns the
+ * number kept. */
+int64_t orc_prune_coalesce(int64_t n, const int32_t *y, const int32_t *x,
+                           const double *sigma, double overlap, uint8_t *keep,
+                           double *sigma_out)
+{
+    for (int64_t a = 0; a < n; ++a) {
+        keep[a] = 1;
+        sigma_out[a] = sigma[a];
+    }
+    if (overlap < 1.0) {
+        for (int64_t a = 0; a < n; ++a) {
+            if (!keep[a])
+                continue;
+            for (int64_t b = a + 1; b < n; ++b) {
+                if (!keep[b])
+                    continue;
+                double f = orc_overlap_fraction(y[a], x[a], sigma_out[a],
+                                                y[b], x[b], sigma_out[b]);
+                if (f > overlap) {
+                    double mean = 0.5 * (sigma_out[a] + sigma_out[b]);
+                    if (sigma_out[a] < sigma_out[b]) {
+                        keep[a] = 0;
+                        sigma_out[b] = mean;
+                        break;
+                    }
+                    keep[b] = 0;
+                    sigma_out[a] = mean;
+                }
+            }
+        }
+    }
+    int64_t m = 0;
+    for (int64_t a = 0; a < n; ++a)
+        m += keep[a];
+    return m;
+}
+
 /* Whole detector on one fp32 image: ladder, planes, DoG, local maxima,
  * threshold, then pruning.  Writes up to cap blobs (y, x, i) with sigma and
  * response, sorted by (y, x, i).  *n_raw receives the count before pruning.

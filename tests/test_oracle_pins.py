@@ -319,3 +319,50 @@ def test_p8_prune_invariants_random():
     for i in np.nonzero(~keep)[0]:
         assert any(oracle.overlap_fraction(y[i], x[i], s[i], y[j], x[j], s[j]) > 0.5 and s[j] >= s[i]
                    for j in range(n) if j != i)
+
+
+def test_p8_coalesce_rules():
+    # Sec. 4.1: overlapping blobs are coalesced by averaging the radius
+    # (reading R7b: the blob with the smaller sigma goes, the other takes the
+    # mean sigma, and later pairs see the new sigma)
+    keep, s = oracle.prune([5, 5], [5, 5], [1.0, 3.0], 0.5, coalesce=True)
+    assert keep.tolist() == [False, True] and s[1] == 2.0
+    keep, s = oracle.prune([5, 5], [5, 5], [3.0, 1.0], 0.5, coalesce=True)
+    assert keep.tolist() == [True, False] and s[0] == 2.0
+    # chain A(2)-B(3)-C(2) on a row, 2 px apart: B absorbs A (sigma 2.5),
+    # then C (sigma 2.25)
+    keep, s = oracle.prune([10, 10, 10], [10, 12, 14], [2.0, 3.0, 2.0], 0.5, coalesce=True)
+    assert keep.tolist() == [False, True, False] and s[1] == 2.25
+    # the shrunken blob no longer reaches a third one: A(1) and B(4)
+    # concentric, C(1.5) 4 px away overlaps B(4) by 0.93 but B(2.5) by 0.31
+    y, x, sg = [10, 10, 10], [10, 10, 14], [1.0, 4.0, 1.5]
+    assert oracle.overlap_fraction(10, 10, 4.0, 10, 14, 1.5) > 0.5
+    assert oracle.overlap_fraction(10, 10, 2.5, 10, 14, 1.5) < 0.5
+    assert oracle.prune(y, x, sg, 0.5).tolist() == [False, True, False]
+    keep, s = oracle.prune(y, x, sg, 0.5, coalesce=True)
+    assert keep.tolist() == [False, True, True] and s[1] == 2.5 and s[2] == 1.5
+    # overlap >= 1: nothing changes
+    keep, s = oracle.prune([5, 5], [5, 5], [1.0, 3.0], 1.0, coalesce=True)
+    assert keep.tolist() == [True, True] and s.tolist() == [1.0, 3.0]
+
+
+def test_p8_coalesce_reduces_to_prune_for_equal_sigmas():
+    # with one sigma for every blob the mean is that sigma, so coalescing
+    # keeps exactly the blobs pruning keeps
+    rng = np.random.default_rng(5)
+    pts = sorted(set(zip(rng.integers(0, 40, 200).tolist(), rng.integers(0, 40, 200).tolist())))
+    y = np.array([p[0] for p in pts])
+    x = np.array([p[1] for p in pts])
+    s = np.full(len(pts), 2.56)
+    keep_c, s_c = oracle.prune(y, x, s, 0.5, coalesce=True)
+    assert keep_c.tolist() == oracle.prune(y, x, s, 0.5).tolist()
+    assert np.all(s_c == 2.56)
+
+
+def test_p1_arithmetic_ladder_of_the_paper():
+    # Sec. 4 Eq. 1 with n_bin = 10 over 1..30: step 2.9, last sigma = max
+    s = oracle.sigmas_arithmetic(1.0, 30.0, 10)
+    assert len(s) == 11 and s[0] == 1.0 and s[-1] == 30.0
+    np.testing.assert_allclose(np.diff(s), 2.9, rtol=1e-14)
+    # n_bin = 1: just the two ends
+    assert oracle.sigmas_arithmetic(2.0, 5.0, 1).tolist() == [2.0, 5.0]
