@@ -25,10 +25,13 @@ Also printed in the same JSON line:
     the plain host entry point frame by frame;
   * the server fed by a Poisson stream of mixed frames (200 frames/s):
     p50/p99 latency and sustained frames/s;
+  * the paper's own configuration (arithmetic ladder of Eq. 1 with n_bin = 10,
+    truncate 5, coalescing) on the same frame;
   * the FP64 CPU oracle timed on this host on a bounded sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-batch] [--no-mixed]
-                    [--no-serve] [--serve-seconds S] [--no-cpu] [--variant V]
+                    [--no-serve] [--no-paper] [--serve-seconds S] [--no-cpu] [--variant V]
+                    [--inflight N]
 """
 from __future__ import annotations
 
@@ -209,6 +212,51 @@ def bench_mixed(dog, torch, ctx, prm, k, frames, steps):
             "served_device_mean_batch_frames": round(mean_bd, 2)}
 
 
+def bench_paper_config(dog, torch, t_img, steps, nf):
+    """The paper's own configuration on the same frame: arithmetic ladder of
+    Sec. 4 Eq. 1 (n_bin = 10 over sigma 1..30), truncate 5, coalescing by
+    averaging the radius; threshold 0.05 as in the headline workload.  Same
+    pipelined steps as the headline (nf frames in flight)."""
+    prm = dog.Params.paper(1.0, 30.0, 10, threshold=0.05)
+    info = dog.plan_info(prm)
+    k = info["k"]
+    H, W = t_img.shape
+    ctxs = [dog.Context(0) for _ in range(nf)]
+    streams = [torch.cuda.Stream() for _ in range(nf)]
+    try:
+        v, _ = ctxs[0].autotune(t_img, prm, reps=3)
+        for c, st in zip(ctxs, streams):
+            c.set_variant(v)
+            for _ in range(3):
+                c.detect_device(t_img, prm, stream=st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(nf - 1):
+            ctxs[i].detect_device_async(t_img, prm, stream=streams[i])
+        for i in range(nf - 1, steps + nf - 1):
+            if i < steps:
+                ctxs[i % nf].detect_device_async(t_img, prm, stream=streams[i % nf])
+            blobs = ctxs[(i - nf + 1) % nf].finish()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        ctxs[0].set_profiling(True)
+        for _ in range(20):
+            ctxs[0].detect_device(t_img, prm)
+        kms, n = ctxs[0].kernel_times()
+        taps = int((2 * info["radii"] + 1).sum())
+        return {"ladder": "arithmetic n_bin=10, sigma 1..30, truncate 5, coalesce",
+                "dog_planes": k, "taps_per_pass": taps, "variant": v,
+                "mpx_scales_per_s": round(H * W * k / dt / 1e6, 1),
+                "ms_per_frame": round(dt * 1e3, 4),
+                "kernel_avg_us": {nm: round(m / max(n, 1) * 1e3, 2)
+                                  for nm, m in zip(("pass1", "pass2", "nms"), kms)},
+                "blur_tflops": round(2.0 * taps * H * W / (kms[0] / max(n, 1) * 1e-3) / 1e12, 2),
+                "blobs": int(len(blobs))}
+    finally:
+        for c in ctxs:
+            c.close()
+
+
 def bench_serving(dog, prm, k, pool, rate, seconds):
     """The server fed by a Poisson stream: frames drawn in turn from the pool
     of uneven frames, submitted at their arrival times."""
@@ -255,6 +303,7 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-paper", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -433,6 +482,9 @@ def main() -> int:
            "host_entry_mpx_scales_per_s": round(mpx / dt_host, 1),
            "blobs": int(len(blobs)),
            "autotune": tune}
+
+    if not args.no_paper:
+        out["paper_config"] = bench_paper_config(dog, torch, t_img, args.steps, nf)
 
     # ---- uniform batch of 64 frames: batched entry point vs frame by frame
     if not args.no_batch:

@@ -66,10 +66,20 @@ typedef struct {
     float response;
 } dog_blob;
 
-/* Detector hyper-parameters (Sec. 4: min_sigma, max_sigma; Sec. 4.1:
+/* Detector hyper-parameters (Sec. 4: min_sigma, max_sigma, n_bin; Sec. 4.1:
  * truncate, threshold default 0.1, overlap default 0.5).  truncate == 0
- * selects 4.0.  Valid: 0 < sigma_min <= sigma_max, sigma_ratio > 1, at most
- * 63 DoG planes, finite threshold, 0 <= overlap <= 1, truncate >= 0. */
+ * selects 4.0.  Valid: 0 < sigma_min <= sigma_max, finite threshold,
+ * 0 <= overlap <= 1, truncate >= 0, at most 63 DoG planes, and
+ *   ladder 0 (geometric): sigma_ratio > 1; sigma_i = sigma_min sigma_ratio^i,
+ *     k = floor(ln(sigma_max/sigma_min)/ln(sigma_ratio)) + 1 DoG planes;
+ *   ladder 1 (arithmetic, Sec. 4 Eq. 1): n_bin >= 1; the n_bin + 1 sigmas
+ *     sigma_min + i (sigma_max - sigma_min)/n_bin, i = 0..n_bin, k = n_bin
+ *     (sigma_ratio is not used).
+ * coalesce 0: of two blobs overlapping more than `overlap`, the one with the
+ * smaller sigma is removed; 1: it is coalesced into the other, whose sigma
+ * becomes the mean of the two (Sec. 4.1, averaging the radius) and is what
+ * later pairs see.  reserved must be 0.  All-zero new fields give the
+ * geometric ladder with pruning. */
 typedef struct {
     double sigma_min;
     double sigma_max;
@@ -77,6 +87,10 @@ typedef struct {
     double threshold;
     double overlap;
     double truncate;
+    int32_t ladder;
+    int32_t n_bin;
+    int32_t coalesce;
+    int32_t reserved;
 } dog_params;
 
 /* A frame of a batch or a server request.  on_device = 1: `data` is a device
@@ -120,9 +134,11 @@ int dog_detect(const float* image, int64_t height, int64_t width, int64_t row_st
 void dog_blobs_free(dog_blob* blobs);
 
 /* Host step on its own: sort blobs[0..n) by (y, x, scale) and apply the
- * overlap pruning above in place, with sigma taken as the FP64 ladder value
- * of each blob's scale index under `params` (the fp32 sigma field is
- * ignored and rewritten).  *n_out receives the surviving count. */
+ * overlap pruning above in place (coalescing when params->coalesce is 1),
+ * with sigma taken as the FP64 ladder value of each blob's scale index under
+ * `params` (the fp32 sigma field is ignored and rewritten; with coalescing
+ * it receives the survivor's final sigma).  *n_out receives the surviving
+ * count. */
 int dog_prune(const dog_params* params, dog_blob* blobs, int64_t n, int64_t* n_out);
 
 /* Description of the last error on the calling thread ("" if none). */

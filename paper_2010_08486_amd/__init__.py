@@ -37,7 +37,9 @@ class DogError(RuntimeError):
 class dog_params(ctypes.Structure):
     _fields_ = [("sigma_min", ctypes.c_double), ("sigma_max", ctypes.c_double),
                 ("sigma_ratio", ctypes.c_double), ("threshold", ctypes.c_double),
-                ("overlap", ctypes.c_double), ("truncate", ctypes.c_double)]
+                ("overlap", ctypes.c_double), ("truncate", ctypes.c_double),
+                ("ladder", ctypes.c_int32), ("n_bin", ctypes.c_int32),
+                ("coalesce", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class dog_blob(ctypes.Structure):
@@ -77,18 +79,34 @@ class dog_stats(ctypes.Structure):
 @dataclass
 class Params:
     """Detector hyper-parameters; defaults follow Sec. 4.1 (threshold 0.1,
-    overlap 0.5) and the geometric ladder ratio 1.6 with truncate 4."""
+    overlap 0.5) and the geometric ladder ratio 1.6 with truncate 4.
+    ladder = "arithmetic" takes the paper's Eq. 1 ladder of n_bin + 1 sigmas
+    (sigma_ratio unused); coalesce = True merges overlapping blobs by
+    averaging the radius instead of removing the smaller one."""
     sigma_min: float = 1.0
     sigma_max: float = 30.0
     sigma_ratio: float = 1.6
     threshold: float = 0.1
     overlap: float = 0.5
     truncate: float = 4.0
+    ladder: str = "geometric"
+    n_bin: int = 0
+    coalesce: bool = False
+
+    @classmethod
+    def paper(cls, sigma_min: float = 1.0, sigma_max: float = 30.0, n_bin: int = 10,
+              threshold: float = 0.1, overlap: float = 0.5) -> "Params":
+        """The paper's own configuration: arithmetic ladder (Eq. 1),
+        truncate 5, coalescing by averaging the radius (Sec. 4.1)."""
+        return cls(sigma_min, sigma_max, 1.6, threshold, overlap, 5.0, "arithmetic", n_bin, True)
 
     def c(self) -> dog_params:
         """The C struct (cached while the values stay the same)."""
+        if self.ladder not in ("geometric", "arithmetic"):
+            raise ValueError("ladder must be 'geometric' or 'arithmetic'")
         key = (self.sigma_min, self.sigma_max, self.sigma_ratio, self.threshold, self.overlap,
-               self.truncate)
+               self.truncate, 1 if self.ladder == "arithmetic" else 0, int(self.n_bin),
+               1 if self.coalesce else 0, 0)
         cached = self.__dict__.get("_c")
         if cached is None or cached[0] != key:
             cached = (key, dog_params(*key))

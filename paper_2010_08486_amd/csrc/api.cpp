@@ -226,7 +226,7 @@ int dog_prune(const dog_params* params, dog_blob* blobs, int64_t n, int64_t* n_o
         b.sigma = (float)P.sigma[b.scale];
     }
     sort_blobs(v);
-    prune_blobs(v, P.sigma, P.prm.overlap);
+    prune_blobs(v, P.sigma, P.prm.overlap, P.prm.coalesce != 0);
     std::copy(v.begin(), v.end(), blobs);
     *n_out = (int64_t)v.size();
     return DOG_OK;
@@ -308,7 +308,7 @@ int dog_detect_device(dog_context* ctx, const float* d_image, int64_t height, in
     rc = run_frames(ctx, *P, fr, pick_stream(ctx, stream), &res, false, nullptr, nullptr, nullptr);
     if (rc != DOG_OK)
         return rc;
-    prune_blobs(res[0], P->sigma, P->prm.overlap);
+    prune_blobs(res[0], P->sigma, P->prm.overlap, P->prm.coalesce != 0);
     return export_blobs(res[0], blobs_out, count_out);
 }
 
@@ -353,7 +353,7 @@ int dog_detect_device_finish(dog_context* ctx, dog_blob** blobs_out, int64_t* co
     std::vector<std::vector<dog_blob>> res;
     if ((rc = collect_frames(ctx, ctx->plan, &res)) != DOG_OK)
         return rc;
-    prune_blobs(res[0], ctx->plan.sigma, ctx->plan.prm.overlap);
+    prune_blobs(res[0], ctx->plan.sigma, ctx->plan.prm.overlap, ctx->plan.prm.coalesce != 0);
     return export_blobs(res[0], blobs_out, count_out);
 }
 

@@ -202,7 +202,7 @@ int detect_frames(dog_context* ctx, const dog_params* params, int32_t n_frames,
                 dog_result& R = results[idx[q]];
                 std::vector<dog_blob>& v = res[q - i];
                 R.raw_count = (int64_t)v.size();
-                prune_blobs(v, P->sigma, P->prm.overlap);
+                prune_blobs(v, P->sigma, P->prm.overlap, P->prm.coalesce != 0);
                 R.status = export_blobs(v, &R.blobs, &R.count);
             }
         }

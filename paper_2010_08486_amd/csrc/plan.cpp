@@ -1,8 +1,9 @@
 // Planning of a detector launch: the sigma ladder, kernel radii, fp32
 // weights and the threshold in kernel precision.
 //
-// Ladder (Sec. 4, Eq. 1, in geometric form): k = floor(ln(smax/smin)/ln(rho))
-// + 1 DoG planes over k+1 Gaussian planes sigma_i = smin * rho^i.
+// Ladder (Sec. 4, Eq. 1): geometric, k = floor(ln(smax/smin)/ln(rho)) + 1
+// DoG planes over k+1 Gaussian planes sigma_i = smin * rho^i; or the paper's
+// arithmetic form, n_bin+1 planes sigma_i = smin + i (smax - smin)/n_bin.
 // Kernels (Sec. 4.1): sampled out to radius r = floor(truncate*sigma + 0.5)
 // and normalised over that support; computed in FP64 and rounded once to
 // fp32, mirrored so the fp32 vector is exactly symmetric.
@@ -26,8 +27,16 @@ bool validate_params(const dog_params& p, std::string* err)
         return bad("sigma_min must be finite and > 0");
     if (!std::isfinite(p.sigma_max) || !(p.sigma_max >= p.sigma_min))
         return bad("sigma_max must be finite and >= sigma_min");
-    if (!std::isfinite(p.sigma_ratio) || !(p.sigma_ratio > 1.0))
+    if (p.ladder != 0 && p.ladder != 1)
+        return bad("ladder must be 0 (geometric) or 1 (arithmetic)");
+    if (p.ladder == 0 && (!std::isfinite(p.sigma_ratio) || !(p.sigma_ratio > 1.0)))
         return bad("sigma_ratio must be finite and > 1");
+    if (p.ladder == 1 && (p.n_bin < 1 || p.n_bin + 1 > DOG_MAX_GAUSS))
+        return bad("n_bin must be in 1..63 for the arithmetic ladder");
+    if (p.coalesce != 0 && p.coalesce != 1)
+        return bad("coalesce must be 0 or 1");
+    if (p.reserved != 0)
+        return bad("reserved must be 0");
     if (!std::isfinite(p.threshold))
         return bad("threshold must be finite");
     if (!std::isfinite(p.overlap) || p.overlap < 0.0 || p.overlap > 1.0)
@@ -50,7 +59,8 @@ int build_plan(const dog_params& prm, Plan* plan, std::string* err)
     P.prm = prm;
     if (P.prm.truncate == 0.0)
         P.prm.truncate = 4.0;
-    const int k = dog_planes_for(prm.sigma_min, prm.sigma_max, prm.sigma_ratio);
+    const int k = prm.ladder == 1 ? prm.n_bin
+                                  : dog_planes_for(prm.sigma_min, prm.sigma_max, prm.sigma_ratio);
     if (k < 1 || k + 1 > DOG_MAX_GAUSS) {
         *err = "ladder has " + std::to_string(k) + " DoG planes; at most " +
                std::to_string(DOG_MAX_GAUSS - 1) + " are supported";
@@ -64,7 +74,11 @@ int build_plan(const dog_params& prm, Plan* plan, std::string* err)
     std::memset(&P.desc, 0, sizeof(P.desc));
     P.desc.n_g = P.n_g;
     for (int i = 0; i < P.n_g; ++i) {
-        const double s = prm.sigma_min * std::pow(prm.sigma_ratio, (double)i);
+        // Eq. 1: arithmetic, step (max - min)/n_bin; else geometric
+        const double s = prm.ladder == 1
+                             ? prm.sigma_min + (double)i * ((prm.sigma_max - prm.sigma_min) /
+                                                            (double)prm.n_bin)
+                             : prm.sigma_min * std::pow(prm.sigma_ratio, (double)i);
         const double rr = std::floor(P.prm.truncate * s + 0.5);
         if (!(rr <= (double)kMaxRadius)) {
             *err = "kernel radius above " + std::to_string(kMaxRadius);

@@ -9,7 +9,9 @@
 // scan stops.  Pairs whose disks cannot touch (centre distance >= sum of
 // radii) are skipped without evaluation, using the row order to stop each
 // scan early; skipping them does not change the outcome because their
-// overlap is 0 and overlap >= 0.
+// overlap is 0 and overlap >= 0.  In coalescing mode (Sec. 4.1: coalescing
+// by averaging the radius) the same visits take place, and the survivor of
+// each removal takes the mean of the pair's sigmas.
 #include <algorithm>
 #include <cmath>
 
@@ -57,50 +59,65 @@ void sort_blobs(std::vector<dog_blob>& v)
 }
 
 // sigma64[i] is the FP64 sigma of ladder index i (the fp32 copy in dog_blob
-// is for output only).
-void prune_blobs(std::vector<dog_blob>& v, const std::vector<double>& sigma64, double overlap)
+// is for output only).  coalesce: the removed blob of an overlapping pair is
+// merged into the survivor, whose sigma becomes the mean of the two (Sec.
+// 4.1, averaging the radius); later pairs see the new sigma, and survivors'
+// sigma fields carry it.  Sigmas only shrink under this rule (the survivor
+// has the larger one), so the row-distance bound taken from the starting
+// sigmas stays valid.
+void prune_blobs(std::vector<dog_blob>& v, const std::vector<double>& sigma64, double overlap,
+                 bool coalesce)
 {
     const size_t n = v.size();
     if (overlap >= 1.0 || n < 2)
         return;
+    std::vector<double> sg(n);
     double smax = 0.0;
-    for (const dog_blob& b : v)
-        smax = std::max(smax, sigma64[b.scale]);
+    for (size_t i = 0; i < n; ++i) {
+        sg[i] = sigma64[v[i].scale];
+        smax = std::max(smax, sg[i]);
+    }
     const double rmax = std::sqrt(2.0) * smax;
     std::vector<char> alive(n, 1);
     for (size_t a = 0; a < n; ++a) {
         if (!alive[a])
             continue;
-        const double sa = sigma64[v[a].scale];
-        const double ra = std::sqrt(2.0) * sa;
-        const double reach = ra + rmax;  // no later blob beyond this row distance can touch a
+        const double reach = std::sqrt(2.0) * sg[a] + rmax;  // no later blob beyond this row distance can touch a
         for (size_t b = a + 1; b < n; ++b) {
             if ((double)(v[b].y - v[a].y) >= reach)
                 break;
             if (!alive[b])
                 continue;
-            const double sb = sigma64[v[b].scale];
+            const double sa = sg[a], sb = sg[b];
             // disks that clearly cannot touch have overlap 0 <= `overlap`:
             // skip them without the square root (the margin keeps every pair
             // the exact test could see as touching)
             const double dy = (double)(v[b].y - v[a].y), dx = (double)(v[b].x - v[a].x);
-            const double rs = ra + std::sqrt(2.0) * sb;
+            const double rs = std::sqrt(2.0) * (sa + sb);
             if (dy * dy + dx * dx > rs * rs * (1.0 + 1e-9))
                 continue;
             const double f = overlap_fraction(v[a].y, v[a].x, sa, v[b].y, v[b].x, sb);
             if (f > overlap) {
+                const double mean = 0.5 * (sa + sb);
                 if (sa < sb) {
                     alive[a] = 0;
+                    if (coalesce)
+                        sg[b] = mean;
                     break;
                 }
                 alive[b] = 0;
+                if (coalesce)
+                    sg[a] = mean;
             }
         }
     }
     size_t o = 0;
     for (size_t i = 0; i < n; ++i)
-        if (alive[i])
+        if (alive[i]) {
+            if (coalesce)
+                v[i].sigma = (float)sg[i];
             v[o++] = v[i];
+        }
     v.resize(o);
 }
 

@@ -32,7 +32,8 @@ int dog_planes_for(double smin, double smax, double ratio);
 // ---------------------------------------------------------------- prune
 double overlap_fraction(int y1, int x1, double s1, int y2, int x2, double s2);
 void sort_blobs(std::vector<dog_blob>& v);
-void prune_blobs(std::vector<dog_blob>& v, const std::vector<double>& sigma64, double overlap);
+void prune_blobs(std::vector<dog_blob>& v, const std::vector<double>& sigma64, double overlap,
+                 bool coalesce);
 
 // ---------------------------------------------------------------- errors
 void set_error(const std::string& msg);

@@ -84,3 +84,62 @@ def test_no_gpu_context_fails_cleanly():
         dog.Context()
     assert e.value.code in (dog.DOG_EDEVICE, dog.DOG_EINVAL)
     assert dog.lib().dog_last_error()
+
+
+@pytest.mark.parametrize("p", [(1.0, 30.0, 10), (1.0, 8.0, 7), (2.0, 2.0, 3), (0.5, 12.0, 40)])
+def test_arithmetic_plan_matches_oracle_ladder(p):
+    # Sec. 4 Eq. 1 with the paper's truncate 5
+    prm = dog.Params(p[0], p[1], 1.6, 0.1, 0.5, 5.0, "arithmetic", p[2], True)
+    info = dog.plan_info(prm)
+    s = oracle.sigmas_arithmetic(*p)
+    assert info["k"] == p[2] == len(s) - 1
+    assert np.array_equal(info["sigmas"], s)
+    assert info["radii"].tolist() == [oracle.radius(x, 5.0) for x in s]
+    assert dog.plan_info(dog.Params.paper())["k"] == 10
+
+
+@pytest.mark.parametrize("bad", [dict(ladder="arithmetic", n_bin=0), dict(ladder="arithmetic", n_bin=64),
+                                 dict(ladder="arithmetic", n_bin=-3)])
+def test_invalid_arithmetic_params_rejected(bad):
+    kw = dict(sigma_min=1.0, sigma_max=8.0, sigma_ratio=1.6, threshold=0.1, overlap=0.5, truncate=5.0)
+    kw.update(bad)
+    with pytest.raises(dog.DogError) as e:
+        dog.plan_info(dog.Params(**kw))
+    assert e.value.code == dog.DOG_EINVAL
+    # sigma_ratio is not used by the arithmetic ladder
+    dog.plan_info(dog.Params(1.0, 8.0, 0.5, 0.1, 0.5, 5.0, "arithmetic", 4))
+    c = dog.Params(1.0, 8.0).c()
+    for field, v in (("ladder", 2), ("coalesce", 2), ("reserved", 1)):
+        raw = dog.dog_params(c.sigma_min, c.sigma_max, c.sigma_ratio, c.threshold, c.overlap,
+                             c.truncate, 0, 0, 0, 0)
+        setattr(raw, field, v)
+        k = ctypes.c_int32(0)
+        assert dog.lib().dog_plan_info(ctypes.byref(raw), ctypes.byref(k), None, None, 0) == dog.DOG_EINVAL
+
+
+@pytest.mark.parametrize("seed,overlap,ladder", [(0, 0.5, "geometric"), (1, 0.5, "arithmetic"),
+                                                 (2, 0.0, "arithmetic"), (3, 0.9, "geometric")])
+def test_coalescing_prune_matches_oracle(seed, overlap, ladder):
+    rng = np.random.default_rng(seed)
+    n = 400
+    prm = (dog.Params(1, 30, 1.6, 0.05, overlap, 4.0, "geometric", 0, True) if ladder == "geometric"
+           else dog.Params(1, 30, 1.6, 0.05, overlap, 5.0, "arithmetic", 10, True))
+    sig = dog.plan_info(prm)["sigmas"]
+    k = len(sig) - 1
+    b = np.zeros(n, dog.BLOB_DTYPE)
+    b["y"] = rng.integers(0, 120, n)
+    b["x"] = rng.integers(0, 120, n)
+    b["scale"] = rng.integers(0, k, n)
+    _, u = np.unique(b[["y", "x", "scale"]], return_index=True)
+    b = b[np.sort(u)]
+    rng.shuffle(b)
+    got = dog.prune(prm, b)
+    order = np.lexsort((b["scale"], b["x"], b["y"]))
+    s = b[order]
+    keep, s_out = oracle.prune(s["y"], s["x"], sig[s["scale"]], overlap, coalesce=True)
+    exp = s[keep]
+    assert got[["y", "x", "scale"]].tolist() == exp[["y", "x", "scale"]].tolist()
+    assert np.array_equal(got["sigma"], s_out[keep].astype(np.float32))
+    if overlap < 1.0 and len(exp) < len(s):
+        # some survivors really were coalesced (their sigma left the ladder)
+        assert np.any(got["sigma"] != sig[got["scale"]].astype(np.float32))
