@@ -63,6 +63,7 @@ def _load():
         "orc_overlap_fraction": (dbl, [dbl, dbl, dbl, dbl, dbl, dbl]),
         "orc_prune": (i64, [i64, vp, vp, vp, dbl, vp]),
         "orc_prune_coalesce": (i64, [i64, vp, vp, vp, dbl, vp, vp]),
+        "orc_preprocess": (ctypes.c_int, [vp, i64, i64, i64, dbl, dbl, vp, vp, vp]),
         "orc_detect": (i64, [vp, i64, i64, i64, dbl, dbl, dbl, dbl, dbl, dbl,
                              vp, vp, vp, i64, vp]),
     }
@@ -202,6 +203,19 @@ def prune(y, x, sigma, overlap: float, coalesce: bool = False):
         return keep[:n].astype(bool), out[:n]
     _load().orc_prune(n, _p(yy), _p(xx), _p(ss), overlap, _p(keep))
     return keep[:n].astype(bool)
+
+
+def preprocess(image: np.ndarray, sigma: float = 1.0, saturated: float = 0.0035):
+    """Preprocessing of Sec. 4.1 (reading R11): (stretched output, smoothed
+    image, lo, hi), all FP64."""
+    a = _as_f32(image)
+    H, W = a.shape
+    out = np.empty((H, W), np.float64)
+    sm = np.empty((H, W), np.float64)
+    lh = np.empty(2, np.float64)
+    if _load().orc_preprocess(_p(a), H, W, W, sigma, saturated, _p(sm), _p(out), _p(lh)) != 0:
+        raise ValueError("bad oracle input")
+    return out, sm, float(lh[0]), float(lh[1])
 
 
 BLOB_DTYPE = np.dtype([("y", np.int32), ("x", np.int32), ("scale", np.int32),

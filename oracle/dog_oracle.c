@@ -36,6 +36,15 @@
  *      pairs visited in (y, x, scale) order; when the overlap exceeds the
  *      limit the blob with the smaller sigma is removed (the later one on a
  *      tie).  overlap >= 1 disables pruning.
+ *   R7b coalescing: the same visits; the survivor takes the mean sigma of
+ *      the pair, which later pairs see.
+ *   R11 preprocessing (the optional first step of Sec. 4.1): Gaussian
+ *      smoothing (sigma given, truncate 4, reflection), then a contrast
+ *      stretch that saturates the given fraction of pixels, half at each
+ *      end: with N pixels and m = floor(fraction * N / 2), lo and hi are the
+ *      m-th smallest and m-th largest smoothed values (0-based order
+ *      statistics m and N-1-m), and out = clamp((s - lo)/(hi - lo), 0, 1)
+ *      (0 everywhere when hi == lo).
  *
  * Everything is FP64 with round-to-nearest-even.  The only parallelism is an
  * OpenMP loop over independent output rows; every output value is computed by
@@ -374,6 +383,63 @@ int64_t orc_prune_coalesce(int64_t n, const int32_t *y, const int32_t *x,
     for (int64_t a = 0; a < n; ++a)
         m += keep[a];
     return m;
+}
+
+static int orc_cmp_double(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+/* Preprocessing (Sec. 4.1, optional first step; reading R11).  image: H x W
+ * fp32 with row stride `stride`; sigma 0 skips the smoothing.  smoothed and
+ * out are H x W (smoothed may be NULL); lo_hi[0..1] receive the stretch
+ * limits.  Returns 0, or -1 on bad input. */
+int orc_preprocess(const float *image, int64_t H, int64_t W, int64_t stride,
+                   double sigma, double saturated, double *smoothed, double *out,
+                   double *lo_hi)
+{
+    if (H < 1 || W < 1 || stride < W || !(sigma >= 0.0) || !(saturated >= 0.0) ||
+        !(saturated < 1.0))
+        return -1;
+    int64_t N = H * W;
+    double *in = (double *)malloc(sizeof(double) * (size_t)N);
+    double *s = (double *)malloc(sizeof(double) * (size_t)N);
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)N);
+    double *sorted = (double *)malloc(sizeof(double) * (size_t)N);
+    for (int64_t y = 0; y < H; ++y)
+        for (int64_t x = 0; x < W; ++x)
+            in[y * W + x] = (double)image[y * stride + x];
+    if (sigma > 0.0)
+        orc_blur(in, H, W, sigma, 4.0, tmp, s);
+    else
+        memcpy(s, in, sizeof(double) * (size_t)N);
+    memcpy(sorted, s, sizeof(double) * (size_t)N);
+    qsort(sorted, (size_t)N, sizeof(double), orc_cmp_double);
+    int64_t m = (int64_t)floor(saturated * (double)N / 2.0);
+    if (m > (N - 1) / 2)
+        m = (N - 1) / 2;
+    double lo = sorted[m], hi = sorted[N - 1 - m];
+    for (int64_t i = 0; i < N; ++i) {
+        double v = 0.0;
+        if (hi > lo) {
+            v = (s[i] - lo) / (hi - lo);
+            if (v < 0.0)
+                v = 0.0;
+            if (v > 1.0)
+                v = 1.0;
+        }
+        out[i] = v;
+    }
+    if (smoothed)
+        memcpy(smoothed, s, sizeof(double) * (size_t)N);
+    lo_hi[0] = lo;
+    lo_hi[1] = hi;
+    free(in);
+    free(s);
+    free(tmp);
+    free(sorted);
+    return 0;
 }
 
 /* Whole detector on one fp32 image: ladder, planes, DoG, local maxima,

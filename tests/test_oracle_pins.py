@@ -366,3 +366,41 @@ def test_p1_arithmetic_ladder_of_the_paper():
     np.testing.assert_allclose(np.diff(s), 2.9, rtol=1e-14)
     # n_bin = 1: just the two ends
     assert oracle.sigmas_arithmetic(2.0, 5.0, 1).tolist() == [2.0, 5.0]
+
+
+def test_r11_stretch_on_a_permutation():
+    # no smoothing, distinct values 0..N-1: with N = 10000 and 0.35 %
+    # saturation, m = floor(17.5) = 17 pixels below lo at each end
+    rng = np.random.default_rng(7)
+    img = rng.permutation(10000).astype(np.float32).reshape(100, 100)
+    out, sm, lo, hi = oracle.preprocess(img, sigma=0.0, saturated=0.0035)
+    assert (lo, hi) == (17.0, 9982.0)
+    np.testing.assert_array_equal(sm, img.astype(np.float64))
+    np.testing.assert_allclose(out, np.clip((img.astype(np.float64) - 17.0) / 9965.0, 0.0, 1.0),
+                               rtol=0, atol=1e-15)
+    assert int((out == 0.0).sum()) == 18 and int((out == 1.0).sum()) == 18
+    # no saturation: the stretch spans the full range
+    _, _, lo0, hi0 = oracle.preprocess(img, sigma=0.0, saturated=0.0)
+    assert (lo0, hi0) == (0.0, 9999.0)
+
+
+def test_r11_smoothing_matches_scipy_and_limits_match_numpy():
+    from scipy import ndimage
+    img = synth.camera_frame(seed=8, H=96, W=80, n_blobs=10) * 65535.0
+    out, sm, lo, hi = oracle.preprocess(img.astype(np.float32), sigma=1.5, saturated=0.0035)
+    ref = ndimage.gaussian_filter(img.astype(np.float32).astype(np.float64), 1.5,
+                                  mode="reflect", truncate=4.0)
+    np.testing.assert_allclose(sm, ref, rtol=1e-12, atol=1e-9)
+    m = int(np.floor(0.0035 * sm.size / 2))
+    srt = np.sort(sm.ravel())
+    assert lo == srt[m] and hi == srt[-1 - m]
+    assert out.min() == 0.0 and out.max() == 1.0
+
+
+def test_r11_constant_image_and_affine_invariance():
+    out, _, lo, hi = oracle.preprocess(np.full((20, 30), 7.0, np.float32), sigma=1.0)
+    assert lo == hi == pytest.approx(7.0) and np.all(out == 0.0)
+    img = synth.small_frame(seed=9, H=64, W=64).astype(np.float32)
+    a, _, _, _ = oracle.preprocess(img, sigma=1.0)
+    b, _, _, _ = oracle.preprocess((img * 4.0 + 3.0).astype(np.float32), sigma=1.0)
+    np.testing.assert_allclose(a, b, rtol=0, atol=1e-6)
