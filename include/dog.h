@@ -188,6 +188,28 @@ int dog_detect_device_async(dog_context* ctx, const float* d_image, int64_t heig
                             int64_t row_stride, const dog_params* params, void* stream);
 int dog_detect_device_finish(dog_context* ctx, dog_blob** blobs_out, int64_t* count_out);
 
+/* Preprocessing (Sec. 4.1, the optional first step): Gaussian smoothing of
+ * the device image (sigma smooth_sigma, radius floor(4 sigma + 0.5) <= 16,
+ * normalised weights, half-sample reflection; 0 = no smoothing), then a
+ * contrast stretch to [0, 1] that saturates the fraction `saturated` of the
+ * pixels (the paper uses 0.0035), half at each end: with N pixels and
+ * m = floor(saturated N / 2), lo and hi are the m-th smallest and m-th
+ * largest smoothed values (exact order statistics of the fp32 smoothed
+ * image), and d_out = clamp((S - lo)/(hi - lo), 0, 1), or 0 where hi == lo.
+ * d_out (device, height x width, dense rows) receives the result and may
+ * then go to dog_detect_device on the same stream; d_smoothed (device, same
+ * shape, may be NULL) receives S.  Work is queued on `stream` as in
+ * dog_detect_device; if limits_out (host, 2 floats) is non-NULL the call
+ * waits and stores lo and hi there, else it returns without waiting.
+ * d_image and the outputs must not overlap.  Successive calls on one
+ * context share its scratch: a call on another stream waits on the device
+ * for the previous one.  Errors: DOG_EINVAL (bad
+ * pointer, shape, sigma or fraction; radius above 16), DOG_EBUSY (a launch
+ * of dog_detect_device_async not finished), device errors. */
+int dog_preprocess(dog_context* ctx, const float* d_image, int64_t height, int64_t width,
+                   int64_t row_stride, double smooth_sigma, double saturated, float* d_out,
+                   float* d_smoothed, float* limits_out, void* stream);
+
 /* Whole detector on n_frames frames of any sizes in one launch sequence
  * (three kernels over tile tables built for the batch).  Frames
  * larger than the budget allows together are processed in consecutive

@@ -140,6 +140,7 @@ def lib() -> ctypes.CDLL:
         "dog_detect_device": (i32, [vp, vp, i64, i64, i64, ctypes.POINTER(dog_params), vp, pblob, pi64]),
         "dog_detect_device_async": (i32, [vp, vp, i64, i64, i64, ctypes.POINTER(dog_params), vp]),
         "dog_detect_device_finish": (i32, [vp, pblob, pi64]),
+        "dog_preprocess": (i32, [vp, vp, i64, i64, i64, dbl, dbl, vp, vp, vp, vp]),
         "dog_detect_batch": (i32, [vp, i32, ctypes.POINTER(dog_frame), ctypes.POINTER(dog_params), vp,
                                    ctypes.POINTER(dog_result)]),
         "dog_results_free": (None, [ctypes.POINTER(dog_result), i32]),
@@ -350,6 +351,23 @@ class Context:
         finally:
             self._inflight = None
         return _blobs(p, n.value)
+
+    def preprocess(self, image, sigma: float = 1.0, saturated: float = 0.0035, out=None,
+                   smoothed=None, stream=None, limits: bool = False):
+        """Smoothing and contrast stretch of a device image (Sec. 4.1): returns
+        the stretched CUDA tensor, and (lo, hi) when `limits` is set."""
+        import torch
+        ptr, H, W, st = _tensor_image(image)
+        if out is None:
+            out = torch.empty((H, W), dtype=torch.float32, device=image.device)
+        lim = (ctypes.c_float * 2)() if limits else None
+        _check(lib().dog_preprocess(self._h, ptr, H, W, st, float(sigma), float(saturated),
+                                    out.data_ptr(),
+                                    smoothed.data_ptr() if smoothed is not None else None,
+                                    lim, _stream_ptr(stream, image.device.index)))
+        if limits:
+            return out, (lim[0], lim[1])
+        return out
 
     def debug_candidates(self, image, params: Params) -> np.ndarray:
         import torch

@@ -19,8 +19,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdog.so")
 
-SOURCES = ["kernels.hip", "plan.cpp", "prune.cpp", "runtime.cpp", "batch.cpp", "api.cpp", "server.cpp",
-           "autotune.cpp"]
+SOURCES = ["kernels.hip", "preprocess.hip", "plan.cpp", "prune.cpp", "runtime.cpp", "batch.cpp",
+           "api.cpp", "server.cpp", "autotune.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

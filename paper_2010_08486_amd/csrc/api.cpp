@@ -1,9 +1,12 @@
 // C ABI exports (declared in include/dog.h).
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
+#include <string>
+#include <vector>
 
 #include "runtime.h"
 
@@ -45,9 +48,11 @@ void free_context(dog_context* c)
     (void)hipSetDevice(c->device);
     if (c->pending && c->ev_done)
         (void)hipEventSynchronize(c->ev_done);
+    if (c->ev_prep)
+        (void)hipEventSynchronize(c->ev_prep);
     if (c->stream)
         (void)hipStreamSynchronize(c->stream);
-    for (DevBuf* b : {&c->planes, &c->input, &c->tables, &c->cand})
+    for (DevBuf* b : {&c->planes, &c->input, &c->tables, &c->cand, &c->prep})
         if (b->p)
             (void)hipFree(b->p);
     for (PinBuf* b : {&c->h_tables, &c->h_cand, &c->h_ends, &c->h_input})
@@ -59,6 +64,8 @@ void free_context(dog_context* c)
             (void)hipEventDestroy(e);
     if (c->ev_done)
         (void)hipEventDestroy(c->ev_done);
+    if (c->ev_prep)
+        (void)hipEventDestroy(c->ev_prep);
     if (c->stream)
         (void)hipStreamDestroy(c->stream);
     delete c;
@@ -355,6 +362,80 @@ int dog_detect_device_finish(dog_context* ctx, dog_blob** blobs_out, int64_t* co
         return rc;
     prune_blobs(res[0], ctx->plan.sigma, ctx->plan.prm.overlap, ctx->plan.prm.coalesce != 0);
     return export_blobs(res[0], blobs_out, count_out);
+}
+
+int dog_preprocess(dog_context* ctx, const float* d_image, int64_t height, int64_t width,
+                   int64_t row_stride, double smooth_sigma, double saturated, float* d_out,
+                   float* d_smoothed, float* limits_out, void* stream)
+{
+    if (!ctx || !d_out) {
+        set_error("invalid argument");
+        return DOG_EINVAL;
+    }
+    int rc = check_image(d_image, height, width, row_stride);
+    if (rc != DOG_OK)
+        return rc;
+    if (!std::isfinite(smooth_sigma) || smooth_sigma < 0.0 || !(saturated >= 0.0) ||
+        !(saturated < 1.0)) {
+        set_error("smooth_sigma must be finite and >= 0, saturated in [0, 1)");
+        return DOG_EINVAL;
+    }
+    const int r = smooth_sigma > 0.0 ? (int)std::floor(4.0 * smooth_sigma + 0.5) : 0;
+    if (r > dogk_preprocess_max_radius()) {
+        set_error("smoothing radius above " + std::to_string(dogk_preprocess_max_radius()));
+        return DOG_EINVAL;
+    }
+    if ((rc = ctx_idle(ctx)) != DOG_OK)
+        return rc;
+    if ((rc = use_device(ctx)) != DOG_OK)
+        return rc;
+    const size_t scratch = dogk_preprocess_scratch_bytes();
+    void* const had = ctx->prep.p;
+    if ((rc = ctx_alloc(ctx, &ctx->prep, scratch + 64 * sizeof(float), "preprocessing scratch")) !=
+        DOG_OK)
+        return rc;
+    if (ctx->prep.p != had) {
+        // fresh scratch: the kernels expect zero histograms (each call
+        // leaves them zero for the next)
+        DOG_HIP(hipMemset(ctx->prep.p, 0, scratch));
+        ctx->prep_sigma = -1.0;
+    }
+    float* d_w = reinterpret_cast<float*>(static_cast<char*>(ctx->prep.p) + scratch);
+    hipStream_t st = pick_stream(ctx, stream);
+    // the scratch is the context's: a call on another stream first waits
+    // (on the device) for the previous call to be done with it
+    if (!ctx->ev_prep)
+        DOG_HIP(hipEventCreateWithFlags(&ctx->ev_prep, hipEventDisableTiming));
+    else
+        DOG_HIP(hipStreamWaitEvent(st, ctx->ev_prep, 0));
+    if (ctx->prep_sigma != smooth_sigma) {
+        // the detector's kernel rule: exp(-j^2 / (2 s^2)) in FP64, normalised
+        // over the truncated support, rounded once to fp32 (no smoothing:
+        // the single weight 1)
+        std::vector<double> g(2 * r + 1, 1.0);
+        double total = r > 0 ? 0.0 : 1.0;
+        for (int j = -r; r > 0 && j <= r; ++j)
+            total += (g[j + r] = std::exp(-((double)j * j) / (2.0 * smooth_sigma * smooth_sigma)));
+        std::vector<float> wf(2 * r + 1);
+        for (int j = 0; j <= 2 * r; ++j)
+            wf[j] = (float)(g[j] / total);
+        DOG_HIP(hipMemcpyAsync(d_w, wf.data(), wf.size() * sizeof(float), hipMemcpyHostToDevice, st));
+        DOG_HIP(hipStreamSynchronize(st));
+        ctx->prep_sigma = smooth_sigma;
+    }
+    const long long N = (long long)height * width;
+    long long m = (long long)std::floor(saturated * (double)N / 2.0);
+    m = std::min(m, (N - 1) / 2);
+    float* d_s = d_smoothed ? d_smoothed : d_out;
+    DOG_HIP(dogk_preprocess(d_image, (int)height, (int)width, (long long)row_stride, d_w, r, d_s,
+                            d_out, ctx->prep.p, (uint32_t)m, (uint32_t)(N - 1 - m), st));
+    DOG_HIP(hipEventRecord(ctx->ev_prep, st));
+    if (limits_out) {
+        DOG_HIP(hipMemcpyAsync(limits_out, static_cast<char*>(ctx->prep.p) + 16, 2 * sizeof(float),
+                               hipMemcpyDeviceToHost, st));
+        DOG_HIP(hipStreamSynchronize(st));
+    }
+    return DOG_OK;
 }
 
 int dog_debug_candidates(dog_context* ctx, const float* d_image, int64_t height, int64_t width,

@@ -96,6 +96,11 @@ hipError_t dogk_untranspose(const float* src, float* dst, int n_planes, int H, i
                             long long pitch, hipStream_t stream);
 hipError_t dogk_fill_u32(uint32_t* p, int n, uint32_t v, hipStream_t stream);
 hipError_t dogk_occupancy(int variant, int* wg1, int* wg2, int* wg3);
+size_t dogk_preprocess_scratch_bytes();
+int dogk_preprocess_max_radius();
+hipError_t dogk_preprocess(const float* d_in, int H, int W, long long stride, const float* d_w,
+                           int r, float* d_s, float* d_out, void* d_scratch, uint32_t rank_lo,
+                           uint32_t rank_hi, hipStream_t stream);
 }
 
 struct dog_context {
@@ -120,6 +125,9 @@ struct dog_context {
     dog::PinBuf h_cand;            // readback of header + records
     dog::PinBuf h_ends;            // per local-maximum workgroup: end of its record range
     dog::PinBuf h_input;           // staging of host frames
+    dog::DevBuf prep;              // preprocessing: select state, histograms, weights
+    double prep_sigma = -1.0;      // smoothing sigma whose weights `prep` holds
+    hipEvent_t ev_prep = nullptr;  // recorded after the last preprocessing launch
 
     // optional per-kernel timing: start and end events of each kernel's
     // dispatch, on the stream it is launched on
