@@ -1,0 +1,110 @@
+"""The target workloads at their full sizes, in the launch configurations the
+benchmark times: the 64-frame 1024x1024 batch as one launch sequence, an
+uneven batch of frames with the mixed workload's sizes (up to 2048x2048), and
+three frames in flight on three contexts and streams.  Every frame of a
+batch must equal the same frame run alone (bitwise), and sampled frames are
+checked in full against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import check_candidates, check_pruned
+
+pytestmark = pytest.mark.gpu
+
+CAMERA = dict(sigma_min=1.0, sigma_max=30.0, sigma_ratio=1.6, threshold=0.05, overlap=0.5)
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    assert torch.cuda.is_available(), "gpu tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def dog():
+    import paper_2010_08486_amd as d
+    return d
+
+
+def _oracle_check(c, t, img, prm):
+    L_o, D_o, sig = oracle.planes(img, prm.sigma_min, prm.sigma_max, prm.sigma_ratio, 4.0)
+    max_abs = float(np.abs(img).max())
+    raw = c.debug_candidates(t, prm)
+    exempt = check_candidates(raw, D_o, prm.threshold, sig, max_abs)
+    return raw, D_o, sig, exempt
+
+
+def test_batch64_full_size(dog, torch_mod):
+    torch = torch_mod
+    prm = dog.Params(**CAMERA)
+    frames = synth.batch64(n_frames=64)
+    dev = [torch.from_numpy(f).cuda() for f in frames]
+    print("batch64: 64 frames generated", flush=True)
+    with dog.Context(0) as c:
+        first, raw_n = c.detect_batch(dev, prm)
+        second, _ = c.detect_batch(dev, prm)      # replayed from the captured graph
+        for f in range(64):
+            alone = c.detect_device(dev[f], prm)
+            assert first[f].tobytes() == alone.tobytes() == second[f].tobytes(), f
+        for f in (0, 31, 63):
+            raw, D_o, sig, exempt = _oracle_check(c, dev[f], frames[f], prm)
+            assert len(raw) == raw_n[f]
+            check_pruned(first[f], raw, D_o, prm.threshold, sig, prm.overlap, exempt)
+            print("batch64 frame %d: raw %d pruned %d exempt %d" % (f, len(raw), len(first[f]), exempt),
+                  flush=True)
+
+
+def test_uneven_batch_full_sizes(dog, torch_mod):
+    torch = torch_mod
+    prm = dog.Params(**CAMERA)
+    shapes = synth.mixed_shapes()[:32]
+    frames = [synth.mixed_frame(f, H, W) for f, (H, W) in enumerate(shapes)]
+    dev = [torch.from_numpy(f).cuda() for f in frames]
+    print("uneven: %d frames, %.1f Mpx" % (len(frames), sum(h * w for h, w in shapes) / 1e6), flush=True)
+    with dog.Context(0) as c:
+        res, raw_n = c.detect_batch(dev, prm)
+        for f in range(len(frames)):
+            assert res[f].tobytes() == c.detect_device(dev[f], prm).tobytes(), (f, shapes[f])
+        # the largest square, a 2:1 crop and a mid-size frame against the oracle
+        picks = [max(range(len(shapes)), key=lambda i: shapes[i][0] * shapes[i][1] *
+                     (shapes[i][0] == shapes[i][1]))]
+        picks += [i for i in range(len(shapes)) if shapes[i][0] * 2 == shapes[i][1]][:1]
+        picks += [i for i in range(len(shapes)) if shapes[i] == (768, 768)][:1]
+        for f in picks:
+            raw, D_o, sig, exempt = _oracle_check(c, dev[f], frames[f], prm)
+            assert len(raw) == raw_n[f]
+            check_pruned(res[f], raw, D_o, prm.threshold, sig, prm.overlap, exempt)
+            print("uneven frame %d %s: raw %d pruned %d exempt %d" % (f, shapes[f], len(raw),
+                                                                     len(res[f]), exempt), flush=True)
+
+
+def test_three_in_flight_full_size(dog, torch_mod):
+    # the benchmark's timed configuration: three contexts, each on its own
+    # stream, steps queued before the previous ones are collected
+    torch = torch_mod
+    prm = dog.Params(**CAMERA)
+    imgs = [synth.camera_frame(seed=s) for s in (1, 2, 3, 4, 5)]
+    dev = [torch.from_numpy(a).cuda() for a in imgs]
+    ctxs = [dog.Context(0) for _ in range(3)]
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    try:
+        ref = [ctxs[0].detect_device(t, prm) for t in dev]
+        torch.cuda.synchronize()
+        steps, nf = 12, 3
+        got = []
+        for i in range(nf - 1):
+            ctxs[i].detect_device_async(dev[i % 5], prm, stream=streams[i])
+        for i in range(nf - 1, steps + nf - 1):
+            if i < steps:
+                ctxs[i % nf].detect_device_async(dev[i % 5], prm, stream=streams[i % nf])
+            got.append(ctxs[(i - nf + 1) % nf].finish())
+        for i, b in enumerate(got):
+            assert b.tobytes() == ref[i % 5].tobytes(), i
+        raw, D_o, sig, exempt = _oracle_check(ctxs[0], dev[1], imgs[1], prm)
+        check_pruned(ref[1], raw, D_o, prm.threshold, sig, prm.overlap, exempt)
+    finally:
+        for c in ctxs:
+            c.close()
