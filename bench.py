@@ -556,6 +556,17 @@ def main() -> int:
             res, _ = ctx.detect_batch(dfr, prm)
         torch.cuda.synchronize()
         tb = (time.perf_counter() - t0) / args.batch_steps
+        # the same batch as one launch sequence of all 64 frames
+        ctx.set_batch_grouping(0)
+        ctx.detect_batch(dfr, prm)
+        ctx.detect_batch(dfr, prm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.batch_steps):
+            ctx.detect_batch(dfr, prm)
+        torch.cuda.synchronize()
+        tb1 = (time.perf_counter() - t0) / args.batch_steps
+        ctx.set_batch_grouping(1 << 20, 3)
         t0 = time.perf_counter()
         per = []
         for f in dfr:
@@ -566,6 +577,8 @@ def main() -> int:
         tp = time.perf_counter() - t0
         tot = sum(f.shape[0] * f.shape[1] for f in frames) * k / 1e6
         out["batch64"] = {"batched_mpx_scales_per_s": round(tot / tb, 1),
+                          "batched_grouping": "groups of 2^20 px on 3 lanes",
+                          "one_sequence_mpx_scales_per_s": round(tot / tb1, 1),
                           "per_frame_mpx_scales_per_s": round(tot / tp, 1),
                           "batched_over_per_frame": round(tp / tb, 3),
                           "batched_ms_per_batch": round(tb * 1e3, 3),

@@ -210,13 +210,29 @@ int dog_preprocess(dog_context* ctx, const float* d_image, int64_t height, int64
                    int64_t row_stride, double smooth_sigma, double saturated, float* d_out,
                    float* d_smoothed, float* limits_out, void* stream);
 
-/* Whole detector on n_frames frames of any sizes in one launch sequence
- * (three kernels over tile tables built for the batch).  Frames
+/* Whole detector on n_frames frames of any sizes.  The frames are cut into
+ * consecutive groups of at most dog_set_batch_grouping's pixel count (by
+ * default 2^20, one 1024x1024 frame; a larger frame forms a group alone),
+ * and each group is one launch sequence (three kernels over tile tables
+ * built for it) on one of the context's lanes: child contexts with their own
+ * streams and workspaces, so several groups run at once and each group's
+ * planes stay close to the Infinity Cache between its kernels.  The lanes
+ * start after the work queued on `stream`; the call returns when every
+ * group is done.  With grouping 0, one frame group, or profiling on, the
+ * batch is one launch sequence on `stream`.  Frames
  * larger than the budget allows together are processed in consecutive
  * launch sequences.  results[f] receives frame f's blob list; the return
  * value is DOG_OK if every frame succeeded, else the first frame error. */
 int dog_detect_batch(dog_context* ctx, int32_t n_frames, const dog_frame* frames,
                      const dog_params* params, void* stream, dog_result* results);
+
+/* Batch grouping of the context (see dog_detect_batch): groups of at most
+ * max_group_pixels pixels (0: the whole batch, or each budget-sized chunk
+ * of it, as one launch sequence) on `lanes` concurrent lanes (1..16; 1 runs
+ * the groups one after another).  Default 2^20 pixels on 3 lanes (three
+ * sequences of 2^20 pixels hold ~225 MB of planes).  Each lane
+ * holds its own workspace, at most a quarter of the context's budget. */
+int dog_set_batch_grouping(dog_context* ctx, int64_t max_group_pixels, int32_t lanes);
 
 /* Release the blob arrays of n results (sets them to NULL). */
 void dog_results_free(dog_result* results, int32_t n);
@@ -316,10 +332,11 @@ typedef struct {
     double dry_run_us_per_mpx;
     const char* tune_cache;     /* autotuner choices (dog_autotune_save) loaded into
                                    every slot context, or NULL                        */
-    int64_t max_batch_pixels;   /* pixels per launch sequence (0: 2^21, two 1024x1024
-                                   frames, so a batch's planes stay close to the
-                                   256 MB Infinity Cache between its kernels; < 0:
-                                   no cap); a batch always takes at least one frame  */
+    int64_t max_batch_pixels;   /* pixels per launch sequence (0: 2^20, one 1024x1024
+                                   frame, so the planes of three slots' batches stay
+                                   close to the 256 MB Infinity Cache between their
+                                   kernels; < 0: no cap); a batch always takes at
+                                   least one frame                                    */
 } dog_server_opts;
 
 typedef struct {

@@ -163,6 +163,7 @@ def lib() -> ctypes.CDLL:
         "dog_set_variant": (ctypes.c_int, [vp, ctypes.c_int]),
         "dog_set_profiling": (ctypes.c_int, [vp, i32]),
         "dog_set_graph_mode": (ctypes.c_int, [vp, i32]),
+        "dog_set_batch_grouping": (ctypes.c_int, [vp, i64, i32]),
         "dog_kernel_times": (ctypes.c_int, [vp, ctypes.POINTER(dbl), pi64]),
         "dog_autotune": (i32, [vp, ctypes.POINTER(dog_params), vp, i64, i64, i64, i32,
                                ctypes.POINTER(i32), ctypes.POINTER(dbl)]),
@@ -309,6 +310,11 @@ class Context:
         prm = params.c()
         _check(lib().dog_autotune_choice(self._h, ctypes.byref(prm), height, width, ctypes.byref(v)))
         return v.value
+
+    def set_batch_grouping(self, max_group_pixels: int, lanes: int = 3) -> None:
+        """Frames per launch sequence in detect_batch (by pixels; 0 = one
+        sequence) and how many sequences run at once."""
+        _check(lib().dog_set_batch_grouping(self._h, int(max_group_pixels), int(lanes)))
 
     def set_graph_mode(self, on: bool) -> None:
         _check(lib().dog_set_graph_mode(self._h, 1 if on else 0))

@@ -50,6 +50,12 @@ void free_context(dog_context* c)
         (void)hipEventSynchronize(c->ev_done);
     if (c->ev_prep)
         (void)hipEventSynchronize(c->ev_prep);
+    for (dog_context* l : c->lanes)
+        free_context(l);
+    c->lanes.clear();
+    if (c->ev_fork)
+        (void)hipEventDestroy(c->ev_fork);
+    (void)hipSetDevice(c->device);
     if (c->stream)
         (void)hipStreamSynchronize(c->stream);
     for (DevBuf* b : {&c->planes, &c->input, &c->tables, &c->cand, &c->prep})
@@ -180,6 +186,19 @@ int dog_set_profiling(dog_context* ctx, int32_t on)
     for (double& m : ctx->kernel_ms)
         m = 0.0;
     ctx->kernel_launches = 0;
+    return DOG_OK;
+}
+
+int dog_set_batch_grouping(dog_context* ctx, int64_t max_group_pixels, int32_t lanes)
+{
+    if (!ctx || max_group_pixels < 0 || lanes < 1 || lanes > 16) {
+        set_error("invalid argument");
+        return DOG_EINVAL;
+    }
+    if (ctx->pending)
+        return ctx_idle(ctx);
+    ctx->group_pixels = max_group_pixels;
+    ctx->lane_count = lanes;
     return DOG_OK;
 }
 

@@ -54,6 +54,109 @@ int export_blobs(const std::vector<dog_blob>& v, dog_blob** out, int64_t* n)
 }
 
 
+// The frames of a batch chunk, already on the device, as consecutive groups
+// of at most ctx->group_pixels pixels (at least one frame each) run on the
+// context's lanes in turn: each lane is a child context with its own stream
+// and workspace, so up to lane_count groups are in flight and a group's
+// planes (about 72 bytes per pixel) stay near the Infinity Cache between its
+// three kernels.  The lanes start after everything queued on s so far (the
+// staged uploads), and every group is collected before the call returns.
+// One group, a grouping of 0 pixels, or per-kernel timing run the chunk as
+// one launch sequence on s instead.
+// Results come back sorted and pruned, with each frame's count before
+// pruning in raw[]; a group is pruned while the later groups run.
+static int run_grouped(dog_context* ctx, const Plan& P, const std::vector<FrameIn>& fin,
+                       hipStream_t s, std::vector<std::vector<dog_blob>>* res,
+                       std::vector<int64_t>* raw)
+{
+    raw->assign(fin.size(), 0);
+    auto finish = [&](size_t q) {
+        (*raw)[q] = (int64_t)(*res)[q].size();
+        prune_blobs((*res)[q], P.sigma, P.prm.overlap, P.prm.coalesce != 0);
+    };
+    const int64_t cap = ctx->group_pixels;
+    std::vector<size_t> cut{0};
+    int64_t px = 0;
+    for (size_t q = 0; q < fin.size(); ++q) {
+        const int64_t fpx = (int64_t)fin[q].H * fin[q].W;
+        if (q > cut.back() && px + fpx > cap) {
+            cut.push_back(q);
+            px = 0;
+        }
+        px += fpx;
+    }
+    cut.push_back(fin.size());
+    const size_t groups = cut.size() - 1;
+    if (cap <= 0 || groups < 2 || ctx->lane_count < 2 || ctx->profiling) {
+        const int rc = run_frames(ctx, P, fin, s, res, false, nullptr, nullptr, nullptr);
+        if (rc == DOG_OK)
+            for (size_t q = 0; q < fin.size(); ++q)
+                finish(q);
+        return rc;
+    }
+
+    const int K = std::min<int>(ctx->lane_count, (int)groups);
+    while ((int)ctx->lanes.size() < K) {
+        dog_context* l = nullptr;
+        int rc = dog_context_create(ctx->device, std::max<uint64_t>(ctx->budget / 4, 1ull << 28), &l);
+        if (rc != DOG_OK)
+            return rc;
+        ctx->lanes.push_back(l);
+    }
+    if (!ctx->ev_fork)
+        DOG_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+    DOG_HIP(hipEventRecord(ctx->ev_fork, s));
+    for (int k = 0; k < K; ++k) {
+        dog_context* l = ctx->lanes[k];
+        l->tuned = ctx->tuned;
+        l->use_graphs = ctx->use_graphs;
+        if (ctx->variant_forced) {
+            int rc = ctx_set_variant(l, ctx->variant);
+            if (rc != DOG_OK)
+                return rc;
+        }
+        l->variant_forced = ctx->variant_forced;
+        DOG_HIP(hipStreamWaitEvent(l->stream, ctx->ev_fork, 0));
+    }
+    res->assign(fin.size(), {});
+    std::vector<size_t> lane_group(K, 0);
+    int rc = DOG_OK;
+    auto collect = [&](int k) {
+        dog_context* l = ctx->lanes[k];
+        if (!l->pending)
+            return DOG_OK;
+        std::vector<std::vector<dog_blob>> out;
+        const int r = collect_frames(l, l->plan, &out);
+        if (r != DOG_OK)
+            return r;
+        const size_t g = lane_group[k];
+        for (size_t q = cut[g]; q < cut[g + 1]; ++q) {
+            (*res)[q] = std::move(out[q - cut[g]]);
+            finish(q);
+        }
+        return DOG_OK;
+    };
+    for (size_t g = 0; g < groups && rc == DOG_OK; ++g) {
+        const int k = (int)(g % K);
+        dog_context* l = ctx->lanes[k];
+        if ((rc = collect(k)) != DOG_OK)
+            break;
+        const Plan* LP = nullptr;
+        if ((rc = ctx_plan(l, &P.prm, &LP)) != DOG_OK)
+            break;
+        const std::vector<FrameIn> part(fin.begin() + cut[g], fin.begin() + cut[g + 1]);
+        lane_group[k] = g;
+        rc = launch_frames(l, *LP, part, l->stream, false, nullptr, nullptr, nullptr);
+    }
+    // every launch is collected, also after an error
+    for (int k = 0; k < K; ++k) {
+        const int r = collect(k);
+        if (rc == DOG_OK)
+            rc = r;
+    }
+    return rc;
+}
+
 int detect_frames(dog_context* ctx, const dog_params* params, int32_t n_frames,
                   const dog_frame* frames, hipStream_t s, dog_result* results)
 {
@@ -195,15 +298,14 @@ int detect_frames(dog_context* ctx, const dog_params* params, int32_t n_frames,
                 }
             }
             std::vector<std::vector<dog_blob>> res;
-            rc = run_frames(ctx, *P, fin, s, &res, false, nullptr, nullptr, nullptr);
+            std::vector<int64_t> raw;
+            rc = run_grouped(ctx, *P, fin, s, &res, &raw);
             if (rc != DOG_OK)
                 goto chunk_fail;
             for (size_t q = i; q < j; ++q) {
                 dog_result& R = results[idx[q]];
-                std::vector<dog_blob>& v = res[q - i];
-                R.raw_count = (int64_t)v.size();
-                prune_blobs(v, P->sigma, P->prm.overlap, P->prm.coalesce != 0);
-                R.status = export_blobs(v, &R.blobs, &R.count);
+                R.raw_count = raw[q - i];
+                R.status = export_blobs(res[q - i], &R.blobs, &R.count);
             }
         }
         i = j;

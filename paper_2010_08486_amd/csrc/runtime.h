@@ -162,6 +162,14 @@ struct dog_context {
     dog::FrameDesc pend_f0{};
     hipStream_t pend_stream = nullptr;
 
+    // batches: frames are cut into groups of at most group_pixels pixels,
+    // run concurrently on `lane_count` child contexts (each with its own
+    // stream and workspace); group_pixels 0 runs a batch as one sequence
+    int64_t group_pixels = (int64_t)1 << 20;
+    int lane_count = 3;
+    std::vector<dog_context*> lanes;
+    hipEvent_t ev_fork = nullptr;
+
     bool have_plan = false;
     uint64_t plan_gen = 0;
     dog::Plan plan;

@@ -353,7 +353,7 @@ int dog_server_create(int device, const dog_params* params, const dog_server_opt
     if (sv->opts.slots <= 0)
         sv->opts.slots = 3;
     if (sv->opts.max_batch_pixels == 0)
-        sv->opts.max_batch_pixels = (int64_t)1 << 21;
+        sv->opts.max_batch_pixels = (int64_t)1 << 20;
     if (sv->opts.queue_capacity <= 0)
         sv->opts.queue_capacity = 4096;
     if (sv->opts.max_wait_ms < 0.0 || sv->opts.dry_run_us_per_mpx < 0.0) {

@@ -44,11 +44,18 @@ def test_batch64_full_size(dog, torch_mod):
     dev = [torch.from_numpy(f).cuda() for f in frames]
     print("batch64: 64 frames generated", flush=True)
     with dog.Context(0) as c:
-        first, raw_n = c.detect_batch(dev, prm)
-        second, _ = c.detect_batch(dev, prm)      # replayed from the captured graph
+        first, raw_n = c.detect_batch(dev, prm)   # one frame per group, three lanes
+        second, _ = c.detect_batch(dev, prm)      # the lanes replay captured graphs
+        c.set_batch_grouping(0)
+        one, _ = c.detect_batch(dev, prm)         # one launch sequence of 64 frames
+        one2, _ = c.detect_batch(dev, prm)        # ... replayed from its graph
+        c.set_batch_grouping(3 << 20, 1)          # groups of three, one at a time
+        seq, _ = c.detect_batch(dev, prm)
+        c.set_batch_grouping(1 << 20, 3)
         for f in range(64):
             alone = c.detect_device(dev[f], prm)
-            assert first[f].tobytes() == alone.tobytes() == second[f].tobytes(), f
+            for other in (second, one, one2, seq):
+                assert first[f].tobytes() == alone.tobytes() == other[f].tobytes(), f
         for f in (0, 31, 63):
             raw, D_o, sig, exempt = _oracle_check(c, dev[f], frames[f], prm)
             assert len(raw) == raw_n[f]

@@ -105,15 +105,15 @@ def test_invalid_server_arguments():
 
 
 def test_pixel_cap_bounds_batch_size():
-    # 1024x1024 frames: the default cap of 2^21 pixels gives at most two
-    # frames per batch; a negative cap lets max_batch_frames decide
+    # 1024x1024 frames: the default cap of 2^20 pixels gives one frame per
+    # batch; a negative cap lets max_batch_frames decide
     with dog.Server(PRM, dry_run=True, dry_run_us_per_mpx=20000.0, slots=1,
                     max_batch_frames=8) as sv:
         for f in _frames(9, 1024, 1024):
             sv.submit(f)
         sv.drain()
         st = sv.stats()
-        assert st["completed"] == 9 and st["batches"] >= 5
+        assert st["completed"] == 9 and st["batches"] == 9
     with dog.Server(PRM, dry_run=True, dry_run_us_per_mpx=20000.0, slots=1,
                     max_batch_frames=8, max_batch_pixels=-1) as sv:
         for f in _frames(9, 1024, 1024):
