@@ -64,6 +64,7 @@ def _load():
         "orc_prune": (i64, [i64, vp, vp, vp, dbl, vp]),
         "orc_prune_coalesce": (i64, [i64, vp, vp, vp, dbl, vp, vp]),
         "orc_preprocess": (ctypes.c_int, [vp, i64, i64, i64, dbl, dbl, vp, vp, vp]),
+        "orc_radius_histogram": (None, [ctypes.c_int, vp, i64, vp, vp]),
         "orc_detect": (i64, [vp, i64, i64, i64, dbl, dbl, dbl, dbl, dbl, dbl,
                              vp, vp, vp, i64, vp]),
     }
@@ -216,6 +217,16 @@ def preprocess(image: np.ndarray, sigma: float = 1.0, saturated: float = 0.0035)
     if _load().orc_preprocess(_p(a), H, W, W, sigma, saturated, _p(sm), _p(out), _p(lh)) != 0:
         raise ValueError("bad oracle input")
     return out, sm, float(lh[0]), float(lh[1])
+
+
+def radius_histogram(ladder, blob_sigma) -> np.ndarray:
+    """Counts of blob radii per ladder radius sqrt(2)*sigma_i (nearest
+    centre; reading R12).  ladder: the k DoG-scale sigmas."""
+    lad = np.ascontiguousarray(ladder, dtype=np.float64)
+    bs = np.ascontiguousarray(blob_sigma, dtype=np.float64)
+    out = np.empty(len(lad), np.int64)
+    _load().orc_radius_histogram(len(lad), _p(lad), len(bs), _p(bs) if len(bs) else None, _p(out))
+    return out
 
 
 BLOB_DTYPE = np.dtype([("y", np.int32), ("x", np.int32), ("scale", np.int32),

@@ -45,6 +45,8 @@
  *      m-th smallest and m-th largest smoothed values (0-based order
  *      statistics m and N-1-m), and out = clamp((s - lo)/(hi - lo), 0, 1)
  *      (0 everywhere when hi == lo).
+ *   R12 radius histogram: bin centres sqrt(2)*sigma_i for the k DoG scales;
+ *      a blob goes to the nearest centre, the lower one on a tie.
  *
  * Everything is FP64 with round-to-nearest-even.  The only parallelism is an
  * OpenMP loop over independent output rows; every output value is computed by
@@ -440,6 +442,31 @@ int orc_preprocess(const float *image, int64_t H, int64_t W, int64_t stride,
     free(tmp);
     free(sorted);
     return 0;
+}
+
+/* Radius histogram (Sec. 4.1: blobs are histogrammed with bin centres at
+ * the detectable radii sqrt(2)*sigma_i, i = 0..k-1; reading R12): each blob's
+ * radius sqrt(2)*s goes to the nearest centre, the lower one on a tie.  The
+ * common factor sqrt(2) is left out: the nearest radius is the nearest
+ * sigma.  counts[k] receives the bin counts. */
+void orc_radius_histogram(int k, const double *ladder, int64_t n, const double *blob_sigma,
+                          int64_t *counts)
+{
+    for (int i = 0; i < k; ++i)
+        counts[i] = 0;
+    for (int64_t b = 0; b < n; ++b) {
+        double s = blob_sigma[b];
+        int best = 0;
+        double bd = fabs(s - ladder[0]);
+        for (int i = 1; i < k; ++i) {
+            double d = fabs(s - ladder[i]);
+            if (d < bd) {
+                bd = d;
+                best = i;
+            }
+        }
+        counts[best] += 1;
+    }
 }
 
 /* Whole detector on one fp32 image: ladder, planes, DoG, local maxima,

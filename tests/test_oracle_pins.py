@@ -404,3 +404,16 @@ def test_r11_constant_image_and_affine_invariance():
     a, _, _, _ = oracle.preprocess(img, sigma=1.0)
     b, _, _, _ = oracle.preprocess((img * 4.0 + 3.0).astype(np.float32), sigma=1.0)
     np.testing.assert_allclose(a, b, rtol=0, atol=1e-6)
+
+
+def test_r12_radius_histogram():
+    # Sec. 4.1: bin centres at the ladder radii sqrt(2)*sigma_i
+    lad = [1.0, 2.0, 4.0]
+    # blobs exactly at the ladder sigmas land in their own bins
+    assert oracle.radius_histogram(lad, [1.0, 4.0, 4.0, 2.0, 1.0]).tolist() == [2, 1, 2]
+    # coalesced sigmas go to the nearest centre: 1.4 -> 1, 1.6 -> 2, 3.1 -> 4;
+    # a tie (1.5, midway between 1 and 2) goes to the lower bin
+    assert oracle.radius_histogram(lad, [1.4, 1.6, 3.1, 1.5]).tolist() == [2, 1, 1]
+    # beyond the ends: the end bins
+    assert oracle.radius_histogram(lad, [0.1, 50.0]).tolist() == [1, 0, 1]
+    assert oracle.radius_histogram(lad, []).tolist() == [0, 0, 0]
