@@ -33,7 +33,7 @@ Also printed in the same JSON line:
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-batch] [--no-mixed]
                     [--no-serve] [--no-paper] [--serve-seconds S] [--no-cpu] [--variant V]
-                    [--inflight N]
+                    [--inflight N] [--only paper|preprocess]
 """
 from __future__ import annotations
 
@@ -359,6 +359,9 @@ def main() -> int:
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-paper", action="store_true")
+    ap.add_argument("--only", choices=("paper", "preprocess"), default=None,
+                    help="run only the paper-configuration or the preprocessing section "
+                         "(for a profile of its kernels) and print its JSON")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -381,7 +384,7 @@ def main() -> int:
     import paper_2010_08486_amd as dog
     import synth
 
-    pmc = args.pmc_workload > 0
+    pmc = args.pmc_workload > 0 or args.only is not None
     want_mixed = not pmc and not (args.no_mixed and args.no_serve)
     batch_frames, mixed_frames = generate_inputs(not pmc and not args.no_batch, want_mixed,
                                                  workers=min(16, os.cpu_count() or 1))
@@ -403,6 +406,17 @@ def main() -> int:
         v, us = ctx.autotune(t_img, prm, reps=5)
         tune = {"variant": v, "geometry": dog.variant_info(v),
                 "kernel_us_per_variant": [round(u, 2) for u in us]}
+
+    if args.only:
+        # one section alone (for a profile of its kernels), as its JSON line
+        nf = max(1, args.inflight)
+        if args.only == "paper":
+            sec = bench_paper_config(dog, torch, t_img, args.steps, nf)
+        else:
+            sec = bench_preprocess(dog, torch, img, prm, k, args.steps, nf)
+        ctx.close()
+        print(json.dumps({"section": args.only, args.only: sec}))
+        return 0
 
     if args.pmc_workload > 0:
         for _ in range(args.pmc_workload):

@@ -141,6 +141,16 @@ void dog_blobs_free(dog_blob* blobs);
  * count. */
 int dog_prune(const dog_params* params, dog_blob* blobs, int64_t n, int64_t* n_out);
 
+/* Radius histogram (Sec. 4.1: blobs are histogrammed with bin centres at
+ * the detectable radii sqrt(2) sigma_i of the ladder's k DoG scales):
+ * counts_out[0..k) receives, for each scale, the number of blobs[0..n)
+ * whose radius sqrt(2) sigma (their sigma field, ladder values or coalesced
+ * means) is nearest that scale's, the lower scale on a tie.  k as in
+ * dog_plan_info.  DOG_EINVAL on NULL pointers, bad parameters or a
+ * non-finite sigma. */
+int dog_radius_histogram(const dog_params* params, const dog_blob* blobs, int64_t n,
+                         int64_t* counts_out);
+
 /* Description of the last error on the calling thread ("" if none). */
 const char* dog_last_error(void);
 

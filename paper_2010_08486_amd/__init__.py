@@ -150,6 +150,7 @@ def lib() -> ctypes.CDLL:
         "dog_plan_info": (i32, [ctypes.POINTER(dog_params), ctypes.POINTER(i32),
                                 ctypes.POINTER(dbl), ctypes.POINTER(i32), i32]),
         "dog_prune": (i32, [ctypes.POINTER(dog_params), vp, i64, pi64]),
+        "dog_radius_histogram": (i32, [ctypes.POINTER(dog_params), vp, i64, pi64]),
         "dog_server_create": (i32, [ctypes.c_int, ctypes.POINTER(dog_params),
                                     ctypes.POINTER(dog_server_opts), ctypes.POINTER(vp)]),
         "dog_server_submit": (i32, [vp, ctypes.POINTER(dog_frame), ctypes.POINTER(u64)]),
@@ -452,6 +453,17 @@ def prune(params: Params, blobs: np.ndarray) -> np.ndarray:
     prm = params.c()
     _check(lib().dog_prune(ctypes.byref(prm), b.ctypes.data, len(b), ctypes.byref(n)))
     return b[:n.value].copy()
+
+
+def radius_histogram(params: Params, blobs: np.ndarray) -> np.ndarray:
+    """Blob counts per ladder radius sqrt(2)*sigma_i (nearest centre), k bins."""
+    b = np.ascontiguousarray(blobs, dtype=BLOB_DTYPE)
+    k = plan_info(params)["k"]
+    out = np.zeros(k, np.int64)
+    prm = params.c()
+    _check(lib().dog_radius_histogram(ctypes.byref(prm), b.ctypes.data if len(b) else None,
+                                      len(b), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+    return out
 
 
 def plan_info(params: Params) -> dict:

@@ -258,6 +258,29 @@ int dog_prune(const dog_params* params, dog_blob* blobs, int64_t n, int64_t* n_o
     return DOG_OK;
 }
 
+int dog_radius_histogram(const dog_params* params, const dog_blob* blobs, int64_t n,
+                         int64_t* counts_out)
+{
+    if (!params || !counts_out || n < 0 || (n > 0 && !blobs)) {
+        set_error("invalid argument");
+        return DOG_EINVAL;
+    }
+    Plan P;
+    std::string err;
+    const int rc = build_plan(*params, &P, &err);
+    if (rc != DOG_OK) {
+        set_error(err);
+        return rc;
+    }
+    for (int64_t b = 0; b < n; ++b)
+        if (!std::isfinite(blobs[b].sigma)) {
+            set_error("blob sigma is not finite");
+            return DOG_EINVAL;
+        }
+    radius_histogram(P.sigma, P.k, blobs, n, counts_out);
+    return DOG_OK;
+}
+
 int dog_plan_info(const dog_params* params, int32_t* k_out, double* sigmas_out,
                   int32_t* radii_out, int32_t cap)
 {

@@ -121,4 +121,25 @@ void prune_blobs(std::vector<dog_blob>& v, const std::vector<double>& sigma64, d
     v.resize(o);
 }
 
+// Radius histogram (Sec. 4.1: blobs are histogrammed with bin centres at the
+// radii sqrt(2) sigma_i of the ladder's k DoG scales): each blob counts in
+// the bin of the nearest centre, the lower one on a tie; comparing sigmas
+// gives the same bins, since every radius carries the factor sqrt(2).
+void radius_histogram(const std::vector<double>& ladder, int k, const dog_blob* v, int64_t n,
+                      int64_t* counts)
+{
+    std::fill(counts, counts + k, (int64_t)0);
+    for (int64_t b = 0; b < n; ++b) {
+        const double s = (double)v[b].sigma;
+        // ladders increase: the first centre past s and the one before it
+        const auto it = std::lower_bound(ladder.begin(), ladder.begin() + k, s);
+        int i = (int)(it - ladder.begin());
+        if (i == k)
+            i = k - 1;
+        else if (i > 0 && s - ladder[i - 1] <= ladder[i] - s)
+            i = i - 1;
+        counts[i] += 1;
+    }
+}
+
 }  // namespace dog

@@ -34,6 +34,8 @@ double overlap_fraction(int y1, int x1, double s1, int y2, int x2, double s2);
 void sort_blobs(std::vector<dog_blob>& v);
 void prune_blobs(std::vector<dog_blob>& v, const std::vector<double>& sigma64, double overlap,
                  bool coalesce);
+void radius_histogram(const std::vector<double>& ladder, int k, const dog_blob* v, int64_t n,
+                      int64_t* counts);
 
 // ---------------------------------------------------------------- errors
 void set_error(const std::string& msg);

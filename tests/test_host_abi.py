@@ -143,3 +143,20 @@ def test_coalescing_prune_matches_oracle(seed, overlap, ladder):
     if overlap < 1.0 and len(exp) < len(s):
         # some survivors really were coalesced (their sigma left the ladder)
         assert np.any(got["sigma"] != sig[got["scale"]].astype(np.float32))
+
+
+@pytest.mark.parametrize("seed,ladder", [(0, "geometric"), (1, "arithmetic")])
+def test_radius_histogram_matches_oracle(seed, ladder):
+    rng = np.random.default_rng(seed)
+    prm = (dog.Params(1, 30, 1.6, 0.05, 0.5) if ladder == "geometric"
+           else dog.Params.paper(1.0, 30.0, 10))
+    sig = dog.plan_info(prm)["sigmas"]
+    k = len(sig) - 1
+    b = np.zeros(500, dog.BLOB_DTYPE)
+    # ladder sigmas and coalesced means between them (as float32, like the output)
+    b["sigma"] = np.where(rng.random(500) < 0.5, sig[rng.integers(0, k, 500)],
+                          rng.uniform(0.5, sig[k - 1] * 1.2, 500)).astype(np.float32)
+    got = dog.radius_histogram(prm, b)
+    exp = oracle.radius_histogram(sig[:k], b["sigma"].astype(np.float64))
+    assert got.tolist() == exp.tolist() and got.sum() == 500
+    assert dog.radius_histogram(prm, b[:0]).tolist() == [0] * k
