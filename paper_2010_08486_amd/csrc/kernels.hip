@@ -670,11 +670,10 @@ __device__ __forceinline__ void flush_sink(const CandSink& snk, uint32_t* s_base
 // Local maxima of the DoG cube with threshold, compacted into records.
 // Tile = 62 output columns (y; lanes 1..62, lanes 0 and 63 are the halo)
 // x (BN*NW) rows (x) of one frame; every wave walks all scales.
-// KMAX > 0: ladders of at most KMAX Gaussian planes; all planes' rows are
-// loaded up front, so a wave waits for memory once.  KMAX == 0: any ladder;
-// plane i+3 is loaded while plane i+1's DoG is formed.  DBG also writes the
-// DoG planes (parity tests only).
-template <int BN, int NW, int KMAX, bool DBG>
+// Plane i+3 is loaded while plane i+1's DoG is formed, so loads overlap the
+// comparisons (measured faster than loading every plane up front, also for
+// short ladders).  DBG also writes the DoG planes (parity tests only).
+template <int BN, int NW, bool DBG>
 __global__ void __launch_bounds__(64 * NW) k_nms(LaunchArgs a)
 {
     __shared__ uint32_t s_n;
@@ -702,73 +701,35 @@ __global__ void __launch_bounds__(64 * NW) k_nms(LaunchArgs a)
 #pragma unroll
         for (int j = 0; j < BN; ++j)
             s3m[j] = -INFINITY;
-        if constexpr (KMAX > 0) {
-            float Lr[KMAX][BN + 2];
+        float La[BN + 2], Lb[BN + 2], Lc[BN + 2], Ld[BN + 2];
+        load_plane_rows<BN>(La, f, 0, x0, voff);
+        load_plane_rows<BN>(Lb, f, 1, x0, voff);
+        load_plane_rows<BN>(Lc, f, k >= 2 ? 2 : 1, x0, voff);
+        dog_rows<BN>(La, Lb, ld->sigma[0], x0, f.W, ycol, s3c, dc);
+        for (int i = 0; i < k; ++i) {
+            // Lb = L_{i+1}, Lc = L_{i+2} (when i + 2 <= k)
+            if (i + 1 < k) {
+                load_plane_rows<BN>(Ld, f, i + 3 <= k ? i + 3 : k, x0, voff);
+                dog_rows<BN>(Lb, Lc, ld->sigma[i + 1], x0, f.W, ycol, s3n, dn);
 #pragma unroll
-            for (int p = 0; p < KMAX; ++p) {
-                // planes past the ladder's last are never read: no loads
-                if (p <= k)
-                    load_plane_rows<BN>(Lr[p], f, p, x0, voff);
-                else
-#pragma unroll
-                    for (int j = 0; j < BN + 2; ++j)
-                        Lr[p][j] = 0.0f;
-            }
-            dog_rows<BN>(Lr[0], Lr[1], ld->sigma[0], x0, f.W, ycol, s3c, dc);
-#pragma unroll
-            for (int i = 0; i + 1 < KMAX; ++i) {
-                if (i < k) {
-                    if (i + 1 < k) {
-                        dog_rows<BN>(Lr[i + 1], Lr[(i + 2) < KMAX ? i + 2 : i + 1],
-                                     ld->sigma[i + 1], x0, f.W, ycol, s3n, dn);
-                    } else {
-#pragma unroll
-                        for (int j = 0; j < BN; ++j) {
-                            s3n[j] = -INFINITY;
-                            dn[j] = -INFINITY;
-                        }
-                    }
-                    emit_plane<BN, DBG>(snk, f, lane, y, x0, i, yout, dc, s3m, s3c, s3n, thr,
-                                        plane_sz);
-#pragma unroll
-                    for (int j = 0; j < BN; ++j) {
-                        s3m[j] = s3c[j];
-                        s3c[j] = s3n[j];
-                        dc[j] = dn[j];
-                    }
+                for (int j = 0; j < BN + 2; ++j) {
+                    Lb[j] = Lc[j];
+                    Lc[j] = Ld[j];
                 }
-            }
-        } else {
-            float La[BN + 2], Lb[BN + 2], Lc[BN + 2], Ld[BN + 2];
-            load_plane_rows<BN>(La, f, 0, x0, voff);
-            load_plane_rows<BN>(Lb, f, 1, x0, voff);
-            load_plane_rows<BN>(Lc, f, k >= 2 ? 2 : 1, x0, voff);
-            dog_rows<BN>(La, Lb, ld->sigma[0], x0, f.W, ycol, s3c, dc);
-            for (int i = 0; i < k; ++i) {
-                // Lb = L_{i+1}, Lc = L_{i+2} (when i + 2 <= k)
-                if (i + 1 < k) {
-                    load_plane_rows<BN>(Ld, f, i + 3 <= k ? i + 3 : k, x0, voff);
-                    dog_rows<BN>(Lb, Lc, ld->sigma[i + 1], x0, f.W, ycol, s3n, dn);
-#pragma unroll
-                    for (int j = 0; j < BN + 2; ++j) {
-                        Lb[j] = Lc[j];
-                        Lc[j] = Ld[j];
-                    }
-                } else {
-#pragma unroll
-                    for (int j = 0; j < BN; ++j) {
-                        s3n[j] = -INFINITY;
-                        dn[j] = -INFINITY;
-                    }
-                }
-                emit_plane<BN, DBG>(snk, f, lane, y, x0, i, yout, dc, s3m, s3c, s3n, thr,
-                                    plane_sz);
+            } else {
 #pragma unroll
                 for (int j = 0; j < BN; ++j) {
-                    s3m[j] = s3c[j];
-                    s3c[j] = s3n[j];
-                    dc[j] = dn[j];
+                    s3n[j] = -INFINITY;
+                    dn[j] = -INFINITY;
                 }
+            }
+            emit_plane<BN, DBG>(snk, f, lane, y, x0, i, yout, dc, s3m, s3c, s3n, thr,
+                                plane_sz);
+#pragma unroll
+            for (int j = 0; j < BN; ++j) {
+                s3m[j] = s3c[j];
+                s3c[j] = s3n[j];
+                dc[j] = dn[j];
             }
         }
     }
@@ -798,16 +759,13 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, int n, uint32_t v)
 }
 
 // ---------------------------------------------------------------- launchers
-// Local-maximum kernels that hold every plane in registers handle ladders of
-// up to DOG_NMS_KMAX Gaussian planes; longer ladders use the rolling kernel.
-#define DOG_NMS_KMAX 10
 
 struct KernelSet {
     const void* pass1;
     const void* pass1w;   // pass 1 when every frame has 16-byte aligned rows and
                           // a width that is a multiple of 64 (nullptr: same as pass1)
     const void* pass2;
-    const void* nms[2][2];  // [ladder of at most DOG_NMS_KMAX planes][debug planes]
+    const void* nms[2];     // [debug planes]
     int S, R, NW, BI, BN, NWN;
 };
 
@@ -818,10 +776,8 @@ static KernelSet make_lds_set()
     k.pass1 = reinterpret_cast<const void*>(&k_blur_lds<1, S, NW, P, false>);
     k.pass1w = reinterpret_cast<const void*>(&k_blur_lds<1, S, NW, P, true>);
     k.pass2 = reinterpret_cast<const void*>(&k_blur_lds<2, S, NW, P, true>);
-    k.nms[0][0] = reinterpret_cast<const void*>(&k_nms<BN, NWN, 0, false>);
-    k.nms[0][1] = reinterpret_cast<const void*>(&k_nms<BN, NWN, 0, true>);
-    k.nms[1][0] = reinterpret_cast<const void*>(&k_nms<BN, NWN, DOG_NMS_KMAX, false>);
-    k.nms[1][1] = reinterpret_cast<const void*>(&k_nms<BN, NWN, DOG_NMS_KMAX, true>);
+    k.nms[0] = reinterpret_cast<const void*>(&k_nms<BN, NWN, false>);
+    k.nms[1] = reinterpret_cast<const void*>(&k_nms<BN, NWN, true>);
     k.S = S;
     k.R = P;
     k.NW = NW;
@@ -838,10 +794,8 @@ static KernelSet make_set()
     k.pass1w = nullptr;
     k.pass1 = reinterpret_cast<const void*>(&k_pass1<S, R, NW, BI>);
     k.pass2 = reinterpret_cast<const void*>(&k_pass2<S, R, NW, BI>);
-    k.nms[0][0] = reinterpret_cast<const void*>(&k_nms<BN, NWN, 0, false>);
-    k.nms[0][1] = reinterpret_cast<const void*>(&k_nms<BN, NWN, 0, true>);
-    k.nms[1][0] = reinterpret_cast<const void*>(&k_nms<BN, NWN, DOG_NMS_KMAX, false>);
-    k.nms[1][1] = reinterpret_cast<const void*>(&k_nms<BN, NWN, DOG_NMS_KMAX, true>);
+    k.nms[0] = reinterpret_cast<const void*>(&k_nms<BN, NWN, false>);
+    k.nms[1] = reinterpret_cast<const void*>(&k_nms<BN, NWN, true>);
     k.S = S;
     k.R = R;
     k.NW = NW;
@@ -901,7 +855,8 @@ hipError_t dogk_launch_sequence(int variant, const dog::LaunchArgs* args, int gr
 {
     const dog::KernelSet& k = dog::kSets[variant];
     const void* pass1 = wide1 && k.pass1w ? k.pass1w : k.pass1;
-    const void* nms = k.nms[max_gauss <= DOG_NMS_KMAX ? 1 : 0][debug ? 1 : 0];
+    const void* nms = k.nms[debug ? 1 : 0];
+    (void)max_gauss;
     void* params[] = {const_cast<dog::LaunchArgs*>(args)};
     const void* fn[3] = {pass1, k.pass2, nms};
     const int grid[3] = {grid1, grid2, grid3};
@@ -922,7 +877,8 @@ hipError_t dogk_launch_nms(int variant, const dog::LaunchArgs* args, int grid3, 
 {
     const dog::KernelSet& k = dog::kSets[variant];
     void* params[] = {const_cast<dog::LaunchArgs*>(args)};
-    return hipLaunchKernel(k.nms[max_gauss <= DOG_NMS_KMAX ? 1 : 0][debug ? 1 : 0], dim3(grid3),
+    (void)max_gauss;
+    return hipLaunchKernel(k.nms[debug ? 1 : 0], dim3(grid3),
                            dim3(64 * k.NWN), params, 0, stream);
 }
 
@@ -936,7 +892,7 @@ hipError_t dogk_occupancy(int variant, int* wg1, int* wg2, int* wg3)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(wg2, k.pass2, 64 * k.NW, 0);
     if (e != hipSuccess)
         return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(wg3, k.nms[1][0], 64 * k.NWN, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(wg3, k.nms[0], 64 * k.NWN, 0);
 }
 
 hipError_t dogk_untranspose(const float* src, float* dst, int n_planes, int H, int W,
