@@ -366,6 +366,10 @@ int dog_server_create(int device, const dog_params* params, const dog_server_opt
         for (int i = 0; i < sv->opts.slots; ++i) {
             auto sl = std::make_unique<Slot>();
             rc = dog_context_create(device, sv->budget, &sl->ctx);
+            // slots already run batches side by side: each batch is one
+            // launch sequence, not split again over lanes of its own
+            if (rc == DOG_OK)
+                sl->ctx->group_pixels = 0;
             if (rc == DOG_OK && sv->opts.tune_cache) {
                 rc = dog_autotune_load(sl->ctx, sv->opts.tune_cache);
                 if (rc != DOG_OK)
