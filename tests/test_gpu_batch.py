@@ -87,3 +87,27 @@ def test_server_device_frames_and_tight_budget(dog, torch_mod):
         assert 0 < st["peak_reserved_bytes"] <= budget
     finally:
         sv.close()
+
+
+def test_grouped_batch_with_host_and_pinned_frames(dog, torch_mod):
+    # frames of 2^20 pixels each form their own groups, run on the lanes; the
+    # host and pinned frames are staged on the caller's stream first, and the
+    # lanes must see them
+    torch = torch_mod
+    prm = dog.Params(**CAMERA)
+    frames = [synth.camera_frame(seed=1400 + i, H=512, W=2048, n_blobs=200) for i in range(6)]
+    pinned = []
+    for f in frames:
+        t = torch.empty(f.shape, dtype=torch.float32, pin_memory=True)
+        t.copy_(torch.from_numpy(f))
+        pinned.append(t)
+    dev = [torch.from_numpy(f).cuda() for f in frames]
+    mixed = [frames[0], pinned[1], dev[2], frames[3], pinned[4], dev[5]]
+    with dog.Context(0) as c:
+        alone = [c.detect_device(t, prm) for t in dev]
+        got, _ = c.detect_batch(mixed, prm)
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            got_s, _ = c.detect_batch(mixed, prm)
+    for i in range(len(frames)):
+        assert got[i].tobytes() == alone[i].tobytes() == got_s[i].tobytes(), i

@@ -75,6 +75,21 @@ def test_preprocess_matches_oracle(dog, torch_mod, shape, sigma, sat):
     assert O.min() >= 0.0 and O.max() <= 1.0
 
 
+def test_preprocess_strided_view(dog, torch_mod):
+    # a crop of a wider frame: rows of the view are row_stride floats apart
+    torch = torch_mod
+    img = _counts(80, 120, 200, 20)
+    full = torch.from_numpy(img).cuda()
+    view = full[:, 13:170]
+    with dog.Context(0) as c:
+        a, lim_a = c.preprocess(view, 1.0, 0.0035, limits=True)
+        b, lim_b = c.preprocess(view.contiguous(), 1.0, 0.0035, limits=True)
+        torch.cuda.synchronize()
+    assert view.stride(0) == 200 and torch.equal(a, b) and lim_a == lim_b
+    o_out, _, o_lo, o_hi = oracle.preprocess(np.ascontiguousarray(img[:, 13:170]), 1.0, 0.0035)
+    assert np.max(np.abs(a.cpu().numpy() - o_out)) <= 1e-4
+
+
 def test_preprocess_constant_image(dog, torch_mod):
     img = np.full((50, 70), 1234.0, np.float32)
     O, lo, hi = _check(dog, torch_mod, img, 1.0, 0.0035)
