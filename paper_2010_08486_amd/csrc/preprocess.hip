@@ -47,10 +47,15 @@ struct SelectState {
 // Scratch layout: state, then the digit histograms of the three passes:
 // pass 0 (top 11 bits, one histogram: both targets see every key), pass 1
 // (next 11 bits, one per target), pass 2 (low 10 bits, one per target).
+// Each histogram of nb bins is followed by its nb/32 sums of 32 bins, so a
+// pick reads 32-bin sums and then one block of 32 bins, not the whole
+// histogram (every workgroup picks; whole histograms made them crowd the
+// few L2 channels holding them).
+constexpr int hwords(int nb) { return nb + nb / 32; }
 constexpr size_t kOffH0 = 256;
-constexpr size_t kOffH1 = kOffH0 + kBins * 4;
-constexpr size_t kOffH2 = kOffH1 + 2 * kBins * 4;
-constexpr size_t kScratch = kOffH2 + 2 * 1024 * 4;
+constexpr size_t kOffH1 = kOffH0 + hwords(kBins) * 4;
+constexpr size_t kOffH2 = kOffH1 + 2 * hwords(kBins) * 4;
+constexpr size_t kScratch = kOffH2 + 2 * hwords(1024) * 4;
 
 __device__ __forceinline__ int reflect(int t, int n)
 {
@@ -95,49 +100,61 @@ __device__ __forceinline__ void wave_hist_add(uint32_t* h, uint32_t d, bool take
         atomicAdd(&h[d], 1u);
 }
 
-// Run by the first wave of a workgroup: the digit whose bin holds the
-// rank-th smallest key (0-based) of an nb-bin histogram (nb = 1024 or 2048)
-// and the rank within that bin, both returned to every lane of the wave.
-__device__ void wave_pick(const uint32_t* hist, int nb, uint32_t rank, uint32_t* digit,
-                          uint32_t* rem)
+// Run by one whole wave: the digit whose bin holds the rank-th smallest key
+// (0-based) of an nb-bin histogram (nb = 1024 or 2048) stored as bins then
+// 32-bin sums, and the rank within that bin; both reach every lane.  The
+// sums locate the block of 32 bins, then the bins of that block the digit.
+__device__ void wave_pick(const uint32_t* __restrict__ hist, int nb, uint32_t rank,
+                          uint32_t* digit, uint32_t* rem)
 {
     const int lane = threadIdx.x & 63;
-    const int per = nb / 64;   // 16 or 32 bins per lane
-    uint32_t c[32];
-    uint32_t sum = 0;
-#pragma unroll
-    for (int i = 0; i < 32; ++i) {
-        c[i] = i < per ? hist[lane * per + i] : 0u;
-        sum += c[i];
-    }
-    // inclusive scan over the lanes
-    uint32_t inc = sum;
+    const int nc = nb / 32;
+    const uint32_t cv = lane < nc ? hist[nb + lane] : 0u;
+    uint32_t inc = cv;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
         const uint32_t v = (uint32_t)__shfl_up((int)inc, off);
         if (lane >= off)
             inc += v;
     }
-    const uint32_t before = inc - sum;
-    const bool here = rank >= before && rank < inc;
-    uint32_t dg = 0, rm = 0;
-    if (here) {
-        uint32_t acc = before;
-        bool found = false;
+    const uint32_t before = inc - cv;
+    const unsigned long long who = __ballot(lane < nc && rank >= before && rank < inc);
+    const int blk = who ? __builtin_ctzll(who) : 0;
+    const uint32_t r2 = rank - (uint32_t)__builtin_amdgcn_readlane((int)before, blk);
+    const uint32_t fv = lane < 32 ? hist[blk * 32 + lane] : 0u;
+    uint32_t inc2 = fv;
 #pragma unroll
-        for (int i = 0; i < 32; ++i) {
-            if (!found && i < per && rank < acc + c[i]) {
-                dg = (uint32_t)(lane * per + i);
-                rm = rank - acc;
-                found = true;
-            }
-            acc += c[i];
-        }
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t v = (uint32_t)__shfl_up((int)inc2, off);
+        if (lane >= off)
+            inc2 += v;
     }
-    const unsigned long long who = __ballot(here);
-    const int src = who ? __builtin_ctzll(who) : 0;
-    *digit = (uint32_t)__builtin_amdgcn_readlane((int)dg, src);
-    *rem = (uint32_t)__builtin_amdgcn_readlane((int)rm, src);
+    const uint32_t before2 = inc2 - fv;
+    const unsigned long long who2 = __ballot(lane < 32 && r2 >= before2 && r2 < inc2);
+    const int j = who2 ? __builtin_ctzll(who2) : 0;
+    *digit = (uint32_t)(blk * 32 + j);
+    *rem = r2 - (uint32_t)__builtin_amdgcn_readlane((int)before2, j);
+}
+
+// Adds the workgroup's LDS histograms h (nt targets of nb bins) to the
+// global ones at g (target t at g + t hwords(nb)): the nonzero bins, then
+// the nonzero 32-bin sums.
+__device__ void flush_hist(const uint32_t* h, int nt, int nb, uint32_t* g)
+{
+    const int nc = nb / 32;
+    for (int i = threadIdx.x; i < nt * nb; i += blockDim.x)
+        if (h[i]) {
+            const int t = i / nb;
+            atomicAdd(&g[t * hwords(nb) + (i - t * nb)], h[i]);
+        }
+    for (int i = threadIdx.x; i < nt * nc; i += blockDim.x) {
+        const int t = i / nc, c = i - t * nc;
+        uint32_t sum = 0;
+        for (int q = 0; q < 32; ++q)
+            sum += h[t * nb + c * 32 + q];
+        if (sum)
+            atomicAdd(&g[t * hwords(nb) + nb + c], sum);
+    }
 }
 
 // Smoothing of one 64 x 32 tile (r = 0 with the single weight 1 copies),
@@ -157,7 +174,8 @@ __global__ void __launch_bounds__(256) k_smooth(const float* __restrict__ in, in
         h[i] = 0u;
     // the pass-1 histograms must be zero before the next kernel counts
     const int wg = blockIdx.y * gridDim.x + blockIdx.x;
-    for (int i = wg * blockDim.x + threadIdx.x; i < 2 * kBins; i += gridDim.x * gridDim.y * blockDim.x)
+    for (int i = wg * blockDim.x + threadIdx.x; i < 2 * hwords(kBins);
+         i += gridDim.x * gridDim.y * blockDim.x)
         hist1[i] = 0u;
     // the input tile with its halo, eight loads in flight per thread
     for (int i0 = 0; i0 < TW * TH; i0 += 8 * 256) {
@@ -203,31 +221,35 @@ __global__ void __launch_bounds__(256) k_smooth(const float* __restrict__ in, in
         wave_hist_add(h, key_of(acc) >> 21, valid);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kBins; i += blockDim.x)
-        if (h[i])
-            atomicAdd(&hist0[i], h[i]);
+    flush_hist(h, 1, kBins, hist0);
 }
 
-// Each target's next digit from `hist` (one nb-bin histogram per target,
-// or one shared when `shared`): the workgroup copies the histograms into
-// LDS (`stage`, 2 nb words) with coalesced loads, the first wave picks, and
-// the results reach every thread through LDS.
-__device__ void pick_both(const uint32_t* __restrict__ hist, int nb, bool shared,
-                          const uint32_t rank[2], uint32_t* stage, uint32_t* s_res,
-                          uint32_t digit[2], uint32_t rem[2])
+// Keys of the kBatch values of this thread in the batch starting at base.
+__device__ __forceinline__ void load_keys(const float* __restrict__ s, long long n, long long base,
+                                          uint32_t (&k)[kBatch])
 {
-    const int words = shared ? nb : 2 * nb;
-    for (int i = 4 * threadIdx.x; i < words; i += 4 * blockDim.x)
-        *reinterpret_cast<uint4*>(stage + i) = *reinterpret_cast<const uint4*>(hist + i);
-    __syncthreads();
-    if (threadIdx.x < 64) {
-        for (int tg = 0; tg < 2; ++tg) {
-            uint32_t dg, rm;
-            wave_pick(stage + (shared ? 0 : tg * nb), nb, rank[tg], &dg, &rm);
-            if (threadIdx.x == 0) {
-                s_res[2 * tg] = dg;
-                s_res[2 * tg + 1] = rm;
-            }
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+        const long long i = base + b * blockDim.x + threadIdx.x;
+        k[b] = i < n ? key_of(s[i]) : 0u;
+    }
+}
+
+// Each target's next digit from `hist` (one nb-bin histogram per target at
+// stride hwords(nb), or one shared when `shared`), picked by the first wave;
+// the results reach every thread through LDS.  Needs at least two waves.
+__device__ void pick_both(const uint32_t* __restrict__ hist, int nb, bool shared,
+                          const uint32_t rank[2], uint32_t* s_res, uint32_t digit[2],
+                          uint32_t rem[2])
+{
+    const int wave = threadIdx.x >> 6;
+    if (wave < 2) {   // waves 0 and 1 pick the two targets side by side
+        const int tg = wave;
+        uint32_t dg, rm;
+        wave_pick(hist + (shared ? 0 : tg * hwords(nb)), nb, rank[tg], &dg, &rm);
+        if ((threadIdx.x & 63) == 0) {
+            s_res[2 * tg] = dg;
+            s_res[2 * tg + 1] = rm;
         }
     }
     __syncthreads();
@@ -246,29 +268,27 @@ __global__ void __launch_bounds__(256) k_select_pass1(const float* __restrict__ 
                                                       uint32_t rank_lo, uint32_t rank_hi,
                                                       SelectState* st)
 {
-    __shared__ __align__(16) uint32_t h[2 * kBins];
+    __shared__ uint32_t h[2 * kBins];
     __shared__ uint32_t s_res[4];
     const uint32_t rk0[2] = {rank_lo, rank_hi};
     uint32_t d0[2], rk[2];
-    pick_both(hist0, kBins, true, rk0, h, s_res, d0, rk);
     for (int i = threadIdx.x; i < 2 * kBins; i += blockDim.x)
         h[i] = 0u;
-    __syncthreads();
+    // the first keys are loaded before the pick, so their latency overlaps it
+    const long long step = (long long)gridDim.x * blockDim.x * kBatch;
+    long long base = (long long)blockIdx.x * blockDim.x * kBatch;
+    uint32_t k[kBatch];
+    load_keys(s, n, base, k);
+    pick_both(hist0, kBins, true, rk0, s_res, d0, rk);   // ends with a barrier
     if (blockIdx.x == 0 && threadIdx.x < 2) {
         st->prefix[0][threadIdx.x] = d0[threadIdx.x];
         st->rank[0][threadIdx.x] = rk[threadIdx.x];
     }
     // the pass-2 histograms must be zero before the next kernel counts
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 2 * 1024; i += gridDim.x * blockDim.x)
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 2 * hwords(1024);
+         i += gridDim.x * blockDim.x)
         hist2[i] = 0u;
-    const long long step = (long long)gridDim.x * blockDim.x * kBatch;
-    for (long long base = (long long)blockIdx.x * blockDim.x * kBatch; base < n; base += step) {
-        uint32_t k[kBatch];
-#pragma unroll
-        for (int b = 0; b < kBatch; ++b) {
-            const long long i = base + b * blockDim.x + threadIdx.x;
-            k[b] = i < n ? key_of(s[i]) : 0u;
-        }
+    for (; base < n; base += step) {
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
             const bool valid = base + b * blockDim.x + threadIdx.x < n;
@@ -276,11 +296,11 @@ __global__ void __launch_bounds__(256) k_select_pass1(const float* __restrict__ 
             wave_hist_add(h, d, valid && (k[b] >> 21) == d0[0]);
             wave_hist_add(h + kBins, d, valid && (k[b] >> 21) == d0[1]);
         }
+        if (base + step < n)
+            load_keys(s, n, base + step, k);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < 2 * kBins; i += blockDim.x)
-        if (h[i])
-            atomicAdd(&hist1[i], h[i]);
+    flush_hist(h, 2, kBins, hist1);
 }
 
 // Pass 2: the second digits from hist1, then the histograms of the low 10
@@ -290,30 +310,25 @@ __global__ void __launch_bounds__(256) k_select_pass2(const float* __restrict__ 
                                                       uint32_t* __restrict__ hist2,
                                                       SelectState* st)
 {
-    __shared__ __align__(16) uint32_t stage[2 * kBins];
+    __shared__ uint32_t h[2 * 1024];
     __shared__ uint32_t s_res[4];
-    uint32_t* h = stage;   // the pass-2 histograms reuse the staging area
     const uint32_t d0[2] = {st->prefix[0][0], st->prefix[0][1]};
     const uint32_t rk0[2] = {st->rank[0][0], st->rank[0][1]};
     uint32_t d1[2], rk[2], pre[2];
-    pick_both(hist1, kBins, false, rk0, stage, s_res, d1, rk);
     for (int i = threadIdx.x; i < 2 * 1024; i += blockDim.x)
         h[i] = 0u;
-    __syncthreads();
+    const long long step = (long long)gridDim.x * blockDim.x * kBatch;
+    long long base = (long long)blockIdx.x * blockDim.x * kBatch;
+    uint32_t k[kBatch];
+    load_keys(s, n, base, k);
+    pick_both(hist1, kBins, false, rk0, s_res, d1, rk);   // ends with a barrier
     for (int tg = 0; tg < 2; ++tg)
         pre[tg] = (d0[tg] << 11) | d1[tg];
     if (blockIdx.x == 0 && threadIdx.x < 2) {
         st->prefix[1][threadIdx.x] = pre[threadIdx.x];
         st->rank[1][threadIdx.x] = rk[threadIdx.x];
     }
-    const long long step = (long long)gridDim.x * blockDim.x * kBatch;
-    for (long long base = (long long)blockIdx.x * blockDim.x * kBatch; base < n; base += step) {
-        uint32_t k[kBatch];
-#pragma unroll
-        for (int b = 0; b < kBatch; ++b) {
-            const long long i = base + b * blockDim.x + threadIdx.x;
-            k[b] = i < n ? key_of(s[i]) : 0u;
-        }
+    for (; base < n; base += step) {
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
             const bool valid = base + b * blockDim.x + threadIdx.x < n;
@@ -321,11 +336,11 @@ __global__ void __launch_bounds__(256) k_select_pass2(const float* __restrict__ 
             wave_hist_add(h, d, valid && (k[b] >> 10) == pre[0]);
             wave_hist_add(h + 1024, d, valid && (k[b] >> 10) == pre[1]);
         }
+        if (base + step < n)
+            load_keys(s, n, base + step, k);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < 2 * 1024; i += blockDim.x)
-        if (h[i])
-            atomicAdd(&hist2[i], h[i]);
+    flush_hist(h, 2, 1024, hist2);
 }
 
 // The last digits from hist2 give the limits (workgroup 0 stores them for
@@ -335,12 +350,15 @@ __global__ void __launch_bounds__(256) k_stretch(const float* __restrict__ s, lo
                                                  const uint32_t* __restrict__ hist2,
                                                  SelectState* st, float* __restrict__ out)
 {
-    __shared__ __align__(16) uint32_t stage[2 * 1024];
     __shared__ uint32_t s_res[4];
     const uint32_t pre[2] = {st->prefix[1][0], st->prefix[1][1]};
     const uint32_t rk1[2] = {st->rank[1][0], st->rank[1][1]};
     uint32_t d2[2], rk[2];
-    pick_both(hist2, 1024, false, rk1, stage, s_res, d2, rk);
+    // the first value is loaded before the pick, so its latency overlaps it
+    const long long step = (long long)gridDim.x * blockDim.x;
+    long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    float v = i < n ? s[i] : 0.0f;
+    pick_both(hist2, 1024, false, rk1, s_res, d2, rk);
     const float lo = value_of((pre[0] << 10) | d2[0]);
     const float hi = value_of((pre[1] << 10) | d2[1]);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -348,14 +366,13 @@ __global__ void __launch_bounds__(256) k_stretch(const float* __restrict__ s, lo
         st->limit[1] = hi;
     }
     // leave the pass-0 histogram zero for the next call's smoothing kernel
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kBins; i += gridDim.x * blockDim.x)
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < hwords(kBins); i += gridDim.x * blockDim.x)
         hist0[i] = 0u;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
-        float v = 0.0f;
-        if (hi > lo)
-            v = fminf(fmaxf((s[i] - lo) / (hi - lo), 0.0f), 1.0f);
-        out[i] = v;
+    for (; i < n; i += step) {
+        const float x = v;
+        if (i + step < n)
+            v = s[i + step];
+        out[i] = hi > lo ? fminf(fmaxf((x - lo) / (hi - lo), 0.0f), 1.0f) : 0.0f;
     }
 }
 
