@@ -26,9 +26,9 @@
 
 namespace dogpre {
 
-constexpr int kTX = 64;        // output columns per smoothing tile
-constexpr int kTY = 32;        // output rows per smoothing tile
+constexpr int kSR = 8;         // output rows per smoothing workgroup (256 columns)
 constexpr int kMaxR = 16;      // largest smoothing radius (sigma <= 3.9 at truncate 4)
+constexpr int kRep = 8;        // replicas of the pass-0 histogram
 constexpr int kBins = 2048;    // digit histogram bins (11 bits)
 constexpr int kBatch = 8;      // keys loaded per thread before counting
 
@@ -53,7 +53,7 @@ struct SelectState {
 // few L2 channels holding them).
 constexpr int hwords(int nb) { return nb + nb / 32; }
 constexpr size_t kOffH0 = 256;
-constexpr size_t kOffH1 = kOffH0 + hwords(kBins) * 4;
+constexpr size_t kOffH1 = kOffH0 + (size_t)kRep * hwords(kBins) * 4;
 constexpr size_t kOffH2 = kOffH1 + 2 * hwords(kBins) * 4;
 constexpr size_t kScratch = kOffH2 + 2 * hwords(1024) * 4;
 
@@ -102,14 +102,18 @@ __device__ __forceinline__ void wave_hist_add(uint32_t* h, uint32_t d, bool take
 
 // Run by one whole wave: the digit whose bin holds the rank-th smallest key
 // (0-based) of an nb-bin histogram (nb = 1024 or 2048) stored as bins then
-// 32-bin sums, and the rank within that bin; both reach every lane.  The
+// 32-bin sums, in `reps` replicas to be added, and the rank within that
+// bin; both reach every lane.  The
 // sums locate the block of 32 bins, then the bins of that block the digit.
-__device__ void wave_pick(const uint32_t* __restrict__ hist, int nb, uint32_t rank,
+__device__ void wave_pick(const uint32_t* __restrict__ hist, int nb, int reps, uint32_t rank,
                           uint32_t* digit, uint32_t* rem)
 {
     const int lane = threadIdx.x & 63;
     const int nc = nb / 32;
-    const uint32_t cv = lane < nc ? hist[nb + lane] : 0u;
+    uint32_t cv = 0u;   // summed over the histogram's replicas
+    if (lane < nc)
+        for (int q = 0; q < reps; ++q)
+            cv += hist[q * hwords(nb) + nb + lane];
     uint32_t inc = cv;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -121,7 +125,10 @@ __device__ void wave_pick(const uint32_t* __restrict__ hist, int nb, uint32_t ra
     const unsigned long long who = __ballot(lane < nc && rank >= before && rank < inc);
     const int blk = who ? __builtin_ctzll(who) : 0;
     const uint32_t r2 = rank - (uint32_t)__builtin_amdgcn_readlane((int)before, blk);
-    const uint32_t fv = lane < 32 ? hist[blk * 32 + lane] : 0u;
+    uint32_t fv = 0u;
+    if (lane < 32)
+        for (int q = 0; q < reps; ++q)
+            fv += hist[q * hwords(nb) + blk * 32 + lane];
     uint32_t inc2 = fv;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -157,71 +164,85 @@ __device__ void flush_hist(const uint32_t* h, int nt, int nb, uint32_t* g)
     }
 }
 
-// Smoothing of one 64 x 32 tile (r = 0 with the single weight 1 copies),
-// and the pass-0 digit histogram of the smoothed values.
+// Smoothing of a tile of 256 columns x kSR rows (one column per thread;
+// r = 0 with the single weight 1 copies), and the pass-0 digit histogram of
+// the smoothed values.  The input rows of the tile and its halo go to LDS
+// with coalesced loads; each thread blurs its column of them along x into
+// registers, then along y from those registers.  The histogram goes to one
+// of kRep replicas of hist0 (by workgroup), so the few hot top-digit bins
+// take kRep times fewer atomics per address.
 __global__ void __launch_bounds__(256) k_smooth(const float* __restrict__ in, int H, int W,
                                                 long long stride, const float* __restrict__ w,
                                                 int r, float* __restrict__ out,
                                                 uint32_t* __restrict__ hist0,
                                                 uint32_t* __restrict__ hist1)
 {
-    __shared__ float tile[(kTY + 2 * kMaxR) * (kTX + 2 * kMaxR)];
-    __shared__ float rows[(kTY + 2 * kMaxR) * kTX];
+    constexpr int TWM = 256 + 2 * kMaxR, THM = kSR + 2 * kMaxR;
+    __shared__ float tile[THM * TWM];
     __shared__ uint32_t h[kBins];
-    const int tx0 = blockIdx.x * kTX, ty0 = blockIdx.y * kTY;
-    const int TW = kTX + 2 * r, TH = kTY + 2 * r;
-    for (int i = threadIdx.x; i < kBins; i += blockDim.x)
+    const int t = threadIdx.x;
+    const int x0 = blockIdx.x * 256, y0 = blockIdx.y * kSR;
+    const int TW = 256 + 2 * r, TH = kSR + 2 * r;
+    for (int i = t; i < kBins; i += 256)
         h[i] = 0u;
     // the pass-1 histograms must be zero before the next kernel counts
     const int wg = blockIdx.y * gridDim.x + blockIdx.x;
-    for (int i = wg * blockDim.x + threadIdx.x; i < 2 * hwords(kBins);
-         i += gridDim.x * gridDim.y * blockDim.x)
+    for (int i = wg * 256 + t; i < 2 * hwords(kBins); i += gridDim.x * gridDim.y * 256)
         hist1[i] = 0u;
-    // the input tile with its halo, eight loads in flight per thread
-    for (int i0 = 0; i0 < TW * TH; i0 += 8 * 256) {
-        float v[8];
+    // input rows y0 - r .. y0 + kSR + r - 1, columns x0 - r .. x0 + 256 + r - 1
+    // (all loads are issued before the first LDS store, so their latencies
+    // overlap instead of adding up row by row)
+    const int xa = reflect(x0 - r + t, W);
+    const bool extra = t < 2 * r;
+    const int xb = extra ? reflect(x0 - r + 256 + t, W) : 0;
+    float va[THM], vb[THM];
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const int i = i0 + b * 256 + threadIdx.x;
-            v[b] = 0.0f;
-            if (i < TW * TH) {
-                const int yy = i / TW, xx = i - yy * TW;
-                const int y = reflect(ty0 - r + yy, H), x = reflect(tx0 - r + xx, W);
-                v[b] = in[(long long)y * stride + x];
-            }
+    for (int yy = 0; yy < THM; ++yy) {
+        va[yy] = vb[yy] = 0.0f;
+        if (yy < TH) {
+            const float* rowp = in + (long long)reflect(y0 - r + yy, H) * stride;
+            va[yy] = rowp[xa];
+            if (extra)
+                vb[yy] = rowp[xb];
         }
+    }
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const int i = i0 + b * 256 + threadIdx.x;
-            if (i < TW * TH)
-                tile[i] = v[b];
+    for (int yy = 0; yy < THM; ++yy) {
+        if (yy < TH) {
+            tile[yy * TW + t] = va[yy];
+            if (extra)
+                tile[yy * TW + 256 + t] = vb[yy];
         }
     }
     __syncthreads();
-    // along rows: rows[yy][x] = sum_j w[j] tile[yy][x + j]
-    for (int i = threadIdx.x; i < TH * kTX; i += blockDim.x) {
-        const int yy = i / kTX, x = i - yy * kTX;
-        const float* t = tile + yy * TW + x;
+    // along x, this thread's column of every tile row, into registers
+    float hr[THM];
+#pragma unroll
+    for (int yy = 0; yy < THM; ++yy) {
         float acc = 0.0f;
-        for (int j = 0; j <= 2 * r; ++j)
-            acc = __builtin_fmaf(w[j], t[j], acc);
-        rows[yy * kTX + x] = acc;
+        if (yy < TH) {
+            const float* p = tile + yy * TW + t;
+            for (int j = 0; j <= 2 * r; ++j)
+                acc = __builtin_fmaf(w[j], p[j], acc);
+        }
+        hr[yy] = acc;
     }
-    __syncthreads();
-    // along columns, into the output (kTY * kTX / 256 = 8 uniform rounds)
-    for (int i = threadIdx.x; i < kTY * kTX; i += blockDim.x) {
-        const int y = i / kTX, x = i - y * kTX;
-        const float* t = rows + y * kTX + x;
+    // along y from the registers (taps beyond 2r are skipped: r is uniform)
+    const int x = x0 + t;
+#pragma unroll
+    for (int o = 0; o < kSR; ++o) {
         float acc = 0.0f;
-        for (int j = 0; j <= 2 * r; ++j)
-            acc = __builtin_fmaf(w[j], t[j * kTX], acc);
-        const bool valid = ty0 + y < H && tx0 + x < W;
+#pragma unroll
+        for (int j = 0; j <= 2 * kMaxR; ++j)
+            if (j <= 2 * r)
+                acc = __builtin_fmaf(w[j], hr[o + j], acc);
+        const bool valid = y0 + o < H && x < W;
         if (valid)
-            out[(long long)(ty0 + y) * W + tx0 + x] = acc;
+            out[(long long)(y0 + o) * W + x] = acc;
         wave_hist_add(h, key_of(acc) >> 21, valid);
     }
     __syncthreads();
-    flush_hist(h, 1, kBins, hist0);
+    flush_hist(h, 1, kBins, hist0 + (size_t)(wg % kRep) * hwords(kBins));
 }
 
 // Keys of the kBatch values of this thread in the batch starting at base.
@@ -236,9 +257,9 @@ __device__ __forceinline__ void load_keys(const float* __restrict__ s, long long
 }
 
 // Each target's next digit from `hist` (one nb-bin histogram per target at
-// stride hwords(nb), or one shared when `shared`), picked by the first wave;
+// stride hwords(nb), or one shared, in `reps` replicas, when `shared`);
 // the results reach every thread through LDS.  Needs at least two waves.
-__device__ void pick_both(const uint32_t* __restrict__ hist, int nb, bool shared,
+__device__ void pick_both(const uint32_t* __restrict__ hist, int nb, int reps, bool shared,
                           const uint32_t rank[2], uint32_t* s_res, uint32_t digit[2],
                           uint32_t rem[2])
 {
@@ -246,7 +267,7 @@ __device__ void pick_both(const uint32_t* __restrict__ hist, int nb, bool shared
     if (wave < 2) {   // waves 0 and 1 pick the two targets side by side
         const int tg = wave;
         uint32_t dg, rm;
-        wave_pick(hist + (shared ? 0 : tg * hwords(nb)), nb, rank[tg], &dg, &rm);
+        wave_pick(hist + (shared ? 0 : tg * hwords(nb)), nb, reps, rank[tg], &dg, &rm);
         if ((threadIdx.x & 63) == 0) {
             s_res[2 * tg] = dg;
             s_res[2 * tg + 1] = rm;
@@ -279,7 +300,7 @@ __global__ void __launch_bounds__(256) k_select_pass1(const float* __restrict__ 
     long long base = (long long)blockIdx.x * blockDim.x * kBatch;
     uint32_t k[kBatch];
     load_keys(s, n, base, k);
-    pick_both(hist0, kBins, true, rk0, s_res, d0, rk);   // ends with a barrier
+    pick_both(hist0, kBins, kRep, true, rk0, s_res, d0, rk);   // ends with a barrier
     if (blockIdx.x == 0 && threadIdx.x < 2) {
         st->prefix[0][threadIdx.x] = d0[threadIdx.x];
         st->rank[0][threadIdx.x] = rk[threadIdx.x];
@@ -321,7 +342,7 @@ __global__ void __launch_bounds__(256) k_select_pass2(const float* __restrict__ 
     long long base = (long long)blockIdx.x * blockDim.x * kBatch;
     uint32_t k[kBatch];
     load_keys(s, n, base, k);
-    pick_both(hist1, kBins, false, rk0, s_res, d1, rk);   // ends with a barrier
+    pick_both(hist1, kBins, 1, false, rk0, s_res, d1, rk);   // ends with a barrier
     for (int tg = 0; tg < 2; ++tg)
         pre[tg] = (d0[tg] << 11) | d1[tg];
     if (blockIdx.x == 0 && threadIdx.x < 2) {
@@ -358,7 +379,7 @@ __global__ void __launch_bounds__(256) k_stretch(const float* __restrict__ s, lo
     const long long step = (long long)gridDim.x * blockDim.x;
     long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     float v = i < n ? s[i] : 0.0f;
-    pick_both(hist2, 1024, false, rk1, s_res, d2, rk);
+    pick_both(hist2, 1024, 1, false, rk1, s_res, d2, rk);
     const float lo = value_of((pre[0] << 10) | d2[0]);
     const float hi = value_of((pre[1] << 10) | d2[1]);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -366,7 +387,8 @@ __global__ void __launch_bounds__(256) k_stretch(const float* __restrict__ s, lo
         st->limit[1] = hi;
     }
     // leave the pass-0 histogram zero for the next call's smoothing kernel
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < hwords(kBins); i += gridDim.x * blockDim.x)
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kRep * hwords(kBins);
+         i += gridDim.x * blockDim.x)
         hist0[i] = 0u;
     for (; i < n; i += step) {
         const float x = v;
@@ -404,7 +426,7 @@ hipError_t dogk_preprocess(const float* d_in, int H, int W, long long stride, co
     uint32_t* h0 = reinterpret_cast<uint32_t*>(base + kOffH0);
     uint32_t* h1 = reinterpret_cast<uint32_t*>(base + kOffH1);
     uint32_t* h2 = reinterpret_cast<uint32_t*>(base + kOffH2);
-    const dim3 grid((unsigned)((W + kTX - 1) / kTX), (unsigned)((H + kTY - 1) / kTY));
+    const dim3 grid((unsigned)((W + 255) / 256), (unsigned)((H + kSR - 1) / kSR));
     hipLaunchKernelGGL(k_smooth, grid, dim3(256), 0, stream, d_in, H, W, stride, d_w, r, d_s, h0, h1);
     const long long g = std::max<long long>(1, std::min<long long>((n + 2047) / 2048, 4096));
     hipLaunchKernelGGL(k_select_pass1, dim3((unsigned)g), dim3(256), 0, stream, (const float*)d_s,
