@@ -8,9 +8,9 @@
 //            m = floor(saturated * N / 2)   (exact order statistics)
 //   out = clamp((S - lo) / (hi - lo), 0, 1), or 0 where hi == lo
 //
-// Smoothing: one workgroup per 64 x 32 output tile; the input tile with its
-// halo is staged in LDS, blurred along rows into a second LDS tile, then
-// along columns into the output (taps in ascending order, fp32 FMAs).
+// Smoothing: one workgroup per 256 x 8 output tile; the input tile with its
+// halo is staged in LDS, blurred along rows into registers, then along
+// columns into the output (taps in ascending order, fp32 FMAs).
 // Order statistics: an exact radix select on the order-preserving integer
 // keys of the fp32 values, over digits of 11, 11 and 10 bits.  The smoothing
 // kernel histograms the top digit of its outputs; each later kernel first
@@ -28,7 +28,7 @@ namespace dogpre {
 
 constexpr int kSR = 8;         // output rows per smoothing workgroup (256 columns)
 constexpr int kMaxR = 16;      // largest smoothing radius (sigma <= 3.9 at truncate 4)
-constexpr int kRep = 8;        // replicas of the pass-0 histogram
+constexpr int kRep = 8;        // replicas of every digit histogram
 constexpr int kBins = 2048;    // digit histogram bins (11 bits)
 constexpr int kBatch = 8;      // keys loaded per thread before counting
 
@@ -50,12 +50,15 @@ struct SelectState {
 // Each histogram of nb bins is followed by its nb/32 sums of 32 bins, so a
 // pick reads 32-bin sums and then one block of 32 bins, not the whole
 // histogram (every workgroup picks; whole histograms made them crowd the
-// few L2 channels holding them).
+// few L2 channels holding them).  Every histogram is kept in kRep replicas
+// (a workgroup adds to replica wg % kRep, a pick sums them), so the hot
+// bins and sums take kRep times fewer global atomics per address: the
+// values of a frame crowd into few digits, and every workgroup adds to them.
 constexpr int hwords(int nb) { return nb + nb / 32; }
 constexpr size_t kOffH0 = 256;
 constexpr size_t kOffH1 = kOffH0 + (size_t)kRep * hwords(kBins) * 4;
-constexpr size_t kOffH2 = kOffH1 + 2 * hwords(kBins) * 4;
-constexpr size_t kScratch = kOffH2 + 2 * hwords(1024) * 4;
+constexpr size_t kOffH2 = kOffH1 + 2 * (size_t)kRep * hwords(kBins) * 4;
+constexpr size_t kScratch = kOffH2 + 2 * (size_t)kRep * hwords(1024) * 4;
 
 __device__ __forceinline__ int reflect(int t, int n)
 {
@@ -144,15 +147,15 @@ __device__ void wave_pick(const uint32_t* __restrict__ hist, int nb, int reps, u
 }
 
 // Adds the workgroup's LDS histograms h (nt targets of nb bins) to the
-// global ones at g (target t at g + t hwords(nb)): the nonzero bins, then
+// global ones at g (target t at g + t tstride words): the nonzero bins, then
 // the nonzero 32-bin sums.
-__device__ void flush_hist(const uint32_t* h, int nt, int nb, uint32_t* g)
+__device__ void flush_hist(const uint32_t* h, int nt, int nb, uint32_t* g, int tstride)
 {
     const int nc = nb / 32;
     for (int i = threadIdx.x; i < nt * nb; i += blockDim.x)
         if (h[i]) {
             const int t = i / nb;
-            atomicAdd(&g[t * hwords(nb) + (i - t * nb)], h[i]);
+            atomicAdd(&g[t * tstride + (i - t * nb)], h[i]);
         }
     for (int i = threadIdx.x; i < nt * nc; i += blockDim.x) {
         const int t = i / nc, c = i - t * nc;
@@ -160,7 +163,7 @@ __device__ void flush_hist(const uint32_t* h, int nt, int nb, uint32_t* g)
         for (int q = 0; q < 32; ++q)
             sum += h[t * nb + c * 32 + q];
         if (sum)
-            atomicAdd(&g[t * hwords(nb) + nb + c], sum);
+            atomicAdd(&g[t * tstride + nb + c], sum);
     }
 }
 
@@ -187,7 +190,7 @@ __global__ void __launch_bounds__(256) k_smooth(const float* __restrict__ in, in
         h[i] = 0u;
     // the pass-1 histograms must be zero before the next kernel counts
     const int wg = blockIdx.y * gridDim.x + blockIdx.x;
-    for (int i = wg * 256 + t; i < 2 * hwords(kBins); i += gridDim.x * gridDim.y * 256)
+    for (int i = wg * 256 + t; i < 2 * kRep * hwords(kBins); i += gridDim.x * gridDim.y * 256)
         hist1[i] = 0u;
     // input rows y0 - r .. y0 + kSR + r - 1, columns x0 - r .. x0 + 256 + r - 1
     // (all loads are issued before the first LDS store, so their latencies
@@ -242,7 +245,7 @@ __global__ void __launch_bounds__(256) k_smooth(const float* __restrict__ in, in
         wave_hist_add(h, key_of(acc) >> 21, valid);
     }
     __syncthreads();
-    flush_hist(h, 1, kBins, hist0 + (size_t)(wg % kRep) * hwords(kBins));
+    flush_hist(h, 1, kBins, hist0 + (size_t)(wg % kRep) * hwords(kBins), 0);
 }
 
 // Keys of the kBatch values of this thread in the batch starting at base.
@@ -256,8 +259,9 @@ __device__ __forceinline__ void load_keys(const float* __restrict__ s, long long
     }
 }
 
-// Each target's next digit from `hist` (one nb-bin histogram per target at
-// stride hwords(nb), or one shared, in `reps` replicas, when `shared`);
+// Each target's next digit from `hist` (one nb-bin histogram per target in
+// `reps` replicas, the target's at stride reps hwords(nb), or one shared
+// when `shared`);
 // the results reach every thread through LDS.  Needs at least two waves.
 __device__ void pick_both(const uint32_t* __restrict__ hist, int nb, int reps, bool shared,
                           const uint32_t rank[2], uint32_t* s_res, uint32_t digit[2],
@@ -267,7 +271,7 @@ __device__ void pick_both(const uint32_t* __restrict__ hist, int nb, int reps, b
     if (wave < 2) {   // waves 0 and 1 pick the two targets side by side
         const int tg = wave;
         uint32_t dg, rm;
-        wave_pick(hist + (shared ? 0 : tg * hwords(nb)), nb, reps, rank[tg], &dg, &rm);
+        wave_pick(hist + (shared ? 0 : tg * reps * hwords(nb)), nb, reps, rank[tg], &dg, &rm);
         if ((threadIdx.x & 63) == 0) {
             s_res[2 * tg] = dg;
             s_res[2 * tg + 1] = rm;
@@ -306,7 +310,7 @@ __global__ void __launch_bounds__(256) k_select_pass1(const float* __restrict__ 
         st->rank[0][threadIdx.x] = rk[threadIdx.x];
     }
     // the pass-2 histograms must be zero before the next kernel counts
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 2 * hwords(1024);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 2 * kRep * hwords(1024);
          i += gridDim.x * blockDim.x)
         hist2[i] = 0u;
     for (; base < n; base += step) {
@@ -321,7 +325,8 @@ __global__ void __launch_bounds__(256) k_select_pass1(const float* __restrict__ 
             load_keys(s, n, base + step, k);
     }
     __syncthreads();
-    flush_hist(h, 2, kBins, hist1);
+    flush_hist(h, 2, kBins, hist1 + (size_t)(blockIdx.x % kRep) * hwords(kBins),
+               kRep * hwords(kBins));
 }
 
 // Pass 2: the second digits from hist1, then the histograms of the low 10
@@ -342,7 +347,7 @@ __global__ void __launch_bounds__(256) k_select_pass2(const float* __restrict__ 
     long long base = (long long)blockIdx.x * blockDim.x * kBatch;
     uint32_t k[kBatch];
     load_keys(s, n, base, k);
-    pick_both(hist1, kBins, 1, false, rk0, s_res, d1, rk);   // ends with a barrier
+    pick_both(hist1, kBins, kRep, false, rk0, s_res, d1, rk);   // ends with a barrier
     for (int tg = 0; tg < 2; ++tg)
         pre[tg] = (d0[tg] << 11) | d1[tg];
     if (blockIdx.x == 0 && threadIdx.x < 2) {
@@ -361,7 +366,8 @@ __global__ void __launch_bounds__(256) k_select_pass2(const float* __restrict__ 
             load_keys(s, n, base + step, k);
     }
     __syncthreads();
-    flush_hist(h, 2, 1024, hist2);
+    flush_hist(h, 2, 1024, hist2 + (size_t)(blockIdx.x % kRep) * hwords(1024),
+               kRep * hwords(1024));
 }
 
 // The last digits from hist2 give the limits (workgroup 0 stores them for
@@ -379,7 +385,7 @@ __global__ void __launch_bounds__(256) k_stretch(const float* __restrict__ s, lo
     const long long step = (long long)gridDim.x * blockDim.x;
     long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     float v = i < n ? s[i] : 0.0f;
-    pick_both(hist2, 1024, 1, false, rk1, s_res, d2, rk);
+    pick_both(hist2, 1024, kRep, false, rk1, s_res, d2, rk);
     const float lo = value_of((pre[0] << 10) | d2[0]);
     const float hi = value_of((pre[1] << 10) | d2[1]);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
