@@ -8,10 +8,11 @@
 // with the smaller sigma is removed (b on a tie) and, if a was removed, a's
 // scan stops.  Pairs whose disks cannot touch (centre distance >= sum of
 // radii) are skipped without evaluation, using the row order to stop each
-// scan early; skipping them does not change the outcome because their
-// overlap is 0 and overlap >= 0.  In coalescing mode (Sec. 4.1: coalescing
-// by averaging the radius) the same visits take place, and the survivor of
-// each removal takes the mean of the pair's sigmas.
+// scan early and column buckets to skip distant columns; skipping them does
+// not change the outcome because their overlap is 0 and overlap >= 0.  In
+// coalescing mode (Sec. 4.1: coalescing by averaging the radius) the same
+// visits take place, and the survivor of each removal takes the mean of the
+// pair's sigmas.
 #include <algorithm>
 #include <cmath>
 
@@ -47,9 +48,44 @@ double overlap_fraction(int y1, int x1, double s1, int y2, int x2, double s2)
     return disk_intersection(dist, ra, rb) / (M_PI * small * small);
 }
 
+// Sorts by (y, x, scale), equal triples in their incoming order.  When the
+// three ranges and the list index fit in 64 bits (always for a frame's
+// candidates), each blob becomes one integer key (y, x, scale, index in
+// mixed radix) and the keys are sorted: several times faster than a
+// three-field comparison on these short lists.
 void sort_blobs(std::vector<dog_blob>& v)
 {
-    std::sort(v.begin(), v.end(), [](const dog_blob& a, const dog_blob& b) {
+    const size_t n = v.size();
+    if (n < 2)
+        return;
+    int64_t lo[3] = {v[0].y, v[0].x, v[0].scale}, hi[3] = {lo[0], lo[1], lo[2]};
+    for (const dog_blob& b : v) {
+        const int64_t f[3] = {b.y, b.x, b.scale};
+        for (int j = 0; j < 3; ++j) {
+            lo[j] = std::min(lo[j], f[j]);
+            hi[j] = std::max(hi[j], f[j]);
+        }
+    }
+    // key = ((y' * RX + x') * RS + s') * n + index, with y' = y - ymin etc.
+    const double span = (double)(hi[0] - lo[0] + 1) * (double)(hi[1] - lo[1] + 1) *
+                        (double)(hi[2] - lo[2] + 1) * (double)n;
+    if (span < 9.0e18) {
+        const uint64_t rx = (uint64_t)(hi[1] - lo[1] + 1), rs = (uint64_t)(hi[2] - lo[2] + 1);
+        std::vector<uint64_t> key(n);
+        for (size_t i = 0; i < n; ++i) {
+            const uint64_t y = (uint64_t)((int64_t)v[i].y - lo[0]);
+            const uint64_t x = (uint64_t)((int64_t)v[i].x - lo[1]);
+            const uint64_t s = (uint64_t)((int64_t)v[i].scale - lo[2]);
+            key[i] = ((y * rx + x) * rs + s) * (uint64_t)n + i;
+        }
+        std::sort(key.begin(), key.end());
+        std::vector<dog_blob> out(n);
+        for (size_t i = 0; i < n; ++i)
+            out[i] = v[key[i] % n];
+        v.swap(out);
+        return;
+    }
+    std::stable_sort(v.begin(), v.end(), [](const dog_blob& a, const dog_blob& b) {
         if (a.y != b.y)
             return a.y < b.y;
         if (a.x != b.x)
@@ -73,19 +109,66 @@ void prune_blobs(std::vector<dog_blob>& v, const std::vector<double>& sigma64, d
         return;
     std::vector<double> sg(n);
     double smax = 0.0;
+    int64_t xmin = v[0].x, xmax = v[0].x;
     for (size_t i = 0; i < n; ++i) {
         sg[i] = sigma64[v[i].scale];
         smax = std::max(smax, sg[i]);
+        xmin = std::min<int64_t>(xmin, v[i].x);
+        xmax = std::max<int64_t>(xmax, v[i].x);
     }
     const double rmax = std::sqrt(2.0) * smax;
+    // Column buckets at least as wide as the largest touching distance
+    // 2 rmax: a blob can only touch blobs of its own bucket and the two next
+    // to it.  Each bucket lists its blobs in list order (so by row), and a
+    // blob's scan merges the three lists by index: it visits every blob it
+    // could touch in the same order as a scan over the whole list, so the
+    // outcome is the same.  A very sparse spread of columns uses one bucket.
+    const int64_t bw = std::max<int64_t>(1, (int64_t)std::ceil(2.0 * rmax));
+    int64_t nbk = (xmax - xmin) / bw + 1;
+    if (nbk > 4 * (int64_t)n + 16)
+        nbk = 1;
+    auto bucket_of = [&](size_t i) -> int64_t { return nbk == 1 ? 0 : ((int64_t)v[i].x - xmin) / bw; };
+    std::vector<size_t> start((size_t)nbk + 1, 0), members(n);
+    for (size_t i = 0; i < n; ++i)
+        ++start[(size_t)bucket_of(i) + 1];
+    for (int64_t c = 0; c < nbk; ++c)
+        start[(size_t)c + 1] += start[(size_t)c];
+    {
+        std::vector<size_t> fill(start.begin(), start.end() - 1);
+        for (size_t i = 0; i < n; ++i)
+            members[fill[(size_t)bucket_of(i)]++] = i;
+    }
+    // cur[c]: the first member of bucket c after the blob being scanned
+    // (blobs are scanned in list order, so these only move forward)
+    std::vector<size_t> cur(start.begin(), start.end() - 1);
     std::vector<char> alive(n, 1);
     for (size_t a = 0; a < n; ++a) {
+        const int64_t ca = bucket_of(a);
+        ++cur[(size_t)ca];   // a itself is the next member of its bucket
         if (!alive[a])
             continue;
         const double reach = std::sqrt(2.0) * sg[a] + rmax;  // no later blob beyond this row distance can touch a
-        for (size_t b = a + 1; b < n; ++b) {
-            if ((double)(v[b].y - v[a].y) >= reach)
+        size_t pos[3], end[3];
+        int nl = 0;
+        for (int64_t c = std::max<int64_t>(0, ca - 1); c <= std::min<int64_t>(nbk - 1, ca + 1); ++c) {
+            pos[nl] = cur[(size_t)c];
+            end[nl] = start[(size_t)c + 1];
+            ++nl;
+        }
+        for (;;) {
+            // the next blob by list index among the three buckets
+            int best = -1;
+            for (int l = 0; l < nl; ++l)
+                if (pos[l] < end[l] && (best < 0 || members[pos[l]] < members[pos[best]]))
+                    best = l;
+            if (best < 0)
                 break;
+            const size_t b = members[pos[best]];
+            if ((double)(v[b].y - v[a].y) >= reach) {
+                end[best] = pos[best];   // this bucket has nothing closer left
+                continue;
+            }
+            ++pos[best];
             if (!alive[b])
                 continue;
             const double sa = sg[a], sb = sg[b];

@@ -160,3 +160,30 @@ def test_radius_histogram_matches_oracle(seed, ladder):
     exp = oracle.radius_histogram(sig[:k], b["sigma"].astype(np.float64))
     assert got.tolist() == exp.tolist() and got.sum() == 500
     assert dog.radius_histogram(prm, b[:0]).tolist() == [0] * k
+
+
+@pytest.mark.parametrize("coalesce", [False, True])
+@pytest.mark.parametrize("spread", [(64, 4000), (700, 700), (3000, 40)])
+def test_prune_wide_frames_match_oracle(coalesce, spread):
+    # frames much wider than the largest touching distance: the host scan
+    # skips distant columns, which must not change which blobs survive
+    H, W = spread
+    rng = np.random.default_rng(H + W + coalesce)
+    n = 2500
+    prm = dog.Params(1, 30, 1.6, 0.05, 0.5, 4.0, "geometric", 0, coalesce)
+    sig = dog.plan_info(prm)["sigmas"]
+    b = np.zeros(n, dog.BLOB_DTYPE)
+    b["y"] = rng.integers(0, H, n)
+    b["x"] = rng.integers(0, W, n) - W // 3     # columns on both sides of 0
+    b["scale"] = rng.integers(0, 8, n)
+    _, u = np.unique(b[["y", "x", "scale"]], return_index=True)
+    b = b[np.sort(u)]
+    rng.shuffle(b)
+    got = dog.prune(prm, b)
+    s = b[np.lexsort((b["scale"], b["x"], b["y"]))]
+    keep, s_out = oracle.prune(s["y"], s["x"], sig[s["scale"]], 0.5, coalesce=True) if coalesce else \
+        (oracle.prune(s["y"], s["x"], sig[s["scale"]], 0.5), sig[s["scale"]])
+    exp = s[keep]
+    assert 0 < len(exp) < len(s)
+    assert got[["y", "x", "scale"]].tolist() == exp[["y", "x", "scale"]].tolist()
+    assert np.array_equal(got["sigma"], s_out[keep].astype(np.float32))
