@@ -8,9 +8,10 @@
 //            m = floor(saturated * N / 2)   (exact order statistics)
 //   out = clamp((S - lo) / (hi - lo), 0, 1), or 0 where hi == lo
 //
-// Smoothing: one workgroup per 256 x 8 output tile; the input tile with its
-// halo is staged in LDS, blurred along rows into registers, then along
-// columns into the output (taps in ascending order, fp32 FMAs).
+// Smoothing: one workgroup per 256 x 8 output tile; each thread blurs its
+// input column along y in registers, the results go to LDS, then each
+// thread blurs its rows along x into the output (taps in ascending order,
+// fp32 FMAs).
 // Order statistics: an exact radix select on the order-preserving integer
 // keys of the fp32 values, over digits of 11, 11 and 10 bits.  The smoothing
 // kernel histograms the top digit of its outputs; each later kernel first
@@ -167,78 +168,79 @@ __device__ void flush_hist(const uint32_t* h, int nt, int nb, uint32_t* g, int t
     }
 }
 
-// Smoothing of a tile of 256 columns x kSR rows (one column per thread;
-// r = 0 with the single weight 1 copies), and the pass-0 digit histogram of
-// the smoothed values.  The input rows of the tile and its halo go to LDS
-// with coalesced loads; each thread blurs its column of them along x into
-// registers, then along y from those registers.  The histogram goes to one
-// of kRep replicas of hist0 (by workgroup), so the few hot top-digit bins
-// take kRep times fewer atomics per address.
+// Smoothing of a tile of 256 columns x kSR rows at radius R (one column per
+// thread; R = 0 with the single weight 1 copies), and the pass-0 digit
+// histogram of the smoothed values.  Each thread loads its input column over
+// the tile's rows and halo (coalesced along the wave, all loads issued
+// before the first use), blurs it along y in registers, and puts the kSR
+// results in LDS; threads t < 2R do the same for the right halo columns.
+// Then each thread blurs its kSR rows along x from LDS.  R is a template
+// argument so that every tap loop unrolls: the LDS reads of a row are issued
+// back to back and the weights sit in scalar registers.  The histogram goes
+// to one of kRep replicas of hist0 (by workgroup).
+template <int R>
 __global__ void __launch_bounds__(256) k_smooth(const float* __restrict__ in, int H, int W,
                                                 long long stride, const float* __restrict__ w,
-                                                int r, float* __restrict__ out,
+                                                float* __restrict__ out,
                                                 uint32_t* __restrict__ hist0,
                                                 uint32_t* __restrict__ hist1)
 {
-    constexpr int TWM = 256 + 2 * kMaxR, THM = kSR + 2 * kMaxR;
-    __shared__ float tile[THM * TWM];
+    constexpr int TW = 256 + 2 * R, TH = kSR + 2 * R, NT = 2 * R + 1;
+    __shared__ float tile[kSR * TW];
     __shared__ uint32_t h[kBins];
     const int t = threadIdx.x;
     const int x0 = blockIdx.x * 256, y0 = blockIdx.y * kSR;
-    const int TW = 256 + 2 * r, TH = kSR + 2 * r;
     for (int i = t; i < kBins; i += 256)
         h[i] = 0u;
     // the pass-1 histograms must be zero before the next kernel counts
     const int wg = blockIdx.y * gridDim.x + blockIdx.x;
     for (int i = wg * 256 + t; i < 2 * kRep * hwords(kBins); i += gridDim.x * gridDim.y * 256)
         hist1[i] = 0u;
-    // input rows y0 - r .. y0 + kSR + r - 1, columns x0 - r .. x0 + 256 + r - 1
-    // (all loads are issued before the first LDS store, so their latencies
-    // overlap instead of adding up row by row)
-    const int xa = reflect(x0 - r + t, W);
-    const bool extra = t < 2 * r;
-    const int xb = extra ? reflect(x0 - r + 256 + t, W) : 0;
-    float va[THM], vb[THM];
+    float wr[NT];
 #pragma unroll
-    for (int yy = 0; yy < THM; ++yy) {
-        va[yy] = vb[yy] = 0.0f;
-        if (yy < TH) {
-            const float* rowp = in + (long long)reflect(y0 - r + yy, H) * stride;
-            va[yy] = rowp[xa];
-            if (extra)
-                vb[yy] = rowp[xb];
-        }
-    }
+    for (int j = 0; j < NT; ++j)
+        wr[j] = w[j];
+    // input rows y0 - R .. y0 + kSR + R - 1 of columns x0 - R + t and, for
+    // t < 2R, x0 + 256 - R + t
+    const int xa = reflect(x0 - R + t, W);
+    const bool extra = t < 2 * R;
+    const int xb = extra ? reflect(x0 - R + 256 + t, W) : 0;
+    float va[TH], vb[TH];
 #pragma unroll
-    for (int yy = 0; yy < THM; ++yy) {
-        if (yy < TH) {
-            tile[yy * TW + t] = va[yy];
-            if (extra)
-                tile[yy * TW + 256 + t] = vb[yy];
-        }
+    for (int yy = 0; yy < TH; ++yy) {
+        const float* rowp = in + (long long)reflect(y0 - R + yy, H) * stride;
+        va[yy] = rowp[xa];
+        vb[yy] = extra ? rowp[xb] : 0.0f;
     }
-    __syncthreads();
-    // along x, this thread's column of every tile row, into registers
-    float hr[THM];
-#pragma unroll
-    for (int yy = 0; yy < THM; ++yy) {
-        float acc = 0.0f;
-        if (yy < TH) {
-            const float* p = tile + yy * TW + t;
-            for (int j = 0; j <= 2 * r; ++j)
-                acc = __builtin_fmaf(w[j], p[j], acc);
-        }
-        hr[yy] = acc;
-    }
-    // along y from the registers (taps beyond 2r are skipped: r is uniform)
-    const int x = x0 + t;
+    // along y, in registers
 #pragma unroll
     for (int o = 0; o < kSR; ++o) {
         float acc = 0.0f;
 #pragma unroll
-        for (int j = 0; j <= 2 * kMaxR; ++j)
-            if (j <= 2 * r)
-                acc = __builtin_fmaf(w[j], hr[o + j], acc);
+        for (int j = 0; j < NT; ++j)
+            acc = __builtin_fmaf(wr[j], va[o + j], acc);
+        tile[o * TW + t] = acc;
+    }
+    if (extra) {
+#pragma unroll
+        for (int o = 0; o < kSR; ++o) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+                acc = __builtin_fmaf(wr[j], vb[o + j], acc);
+            tile[o * TW + 256 + t] = acc;
+        }
+    }
+    __syncthreads();
+    // along x, from LDS
+    const int x = x0 + t;
+#pragma unroll
+    for (int o = 0; o < kSR; ++o) {
+        const float* p = tile + o * TW + t;
+        float acc = 0.0f;
+#pragma unroll
+        for (int j = 0; j < NT; ++j)
+            acc = __builtin_fmaf(wr[j], p[j], acc);
         const bool valid = y0 + o < H && x < W;
         if (valid)
             out[(long long)(y0 + o) * W + x] = acc;
@@ -247,6 +249,14 @@ __global__ void __launch_bounds__(256) k_smooth(const float* __restrict__ in, in
     __syncthreads();
     flush_hist(h, 1, kBins, hist0 + (size_t)(wg % kRep) * hwords(kBins), 0);
 }
+
+using SmoothFn = void (*)(const float*, int, int, long long, const float*, float*, uint32_t*,
+                          uint32_t*);
+
+template <int... Rs>
+struct SmoothTable {
+    static constexpr SmoothFn fn[sizeof...(Rs)] = {&k_smooth<Rs>...};
+};
 
 // Keys of the kBatch values of this thread in the batch starting at base.
 __device__ __forceinline__ void load_keys(const float* __restrict__ s, long long n, long long base,
@@ -432,8 +442,13 @@ hipError_t dogk_preprocess(const float* d_in, int H, int W, long long stride, co
     uint32_t* h0 = reinterpret_cast<uint32_t*>(base + kOffH0);
     uint32_t* h1 = reinterpret_cast<uint32_t*>(base + kOffH1);
     uint32_t* h2 = reinterpret_cast<uint32_t*>(base + kOffH2);
+    if (r < 0 || r > kMaxR)
+        return hipErrorInvalidValue;
+    using Table = SmoothTable<0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16>;
+    static_assert(sizeof(Table::fn) / sizeof(Table::fn[0]) == kMaxR + 1, "one kernel per radius");
     const dim3 grid((unsigned)((W + 255) / 256), (unsigned)((H + kSR - 1) / kSR));
-    hipLaunchKernelGGL(k_smooth, grid, dim3(256), 0, stream, d_in, H, W, stride, d_w, r, d_s, h0, h1);
+    hipLaunchKernelGGL(Table::fn[r], grid, dim3(256), 0, stream, d_in, H, W, stride, d_w, d_s, h0,
+                       h1);
     const long long g = std::max<long long>(1, std::min<long long>((n + 2047) / 2048, 4096));
     hipLaunchKernelGGL(k_select_pass1, dim3((unsigned)g), dim3(256), 0, stream, (const float*)d_s,
                        n, (const uint32_t*)h0, h1, h2, rank_lo, rank_hi, st);
