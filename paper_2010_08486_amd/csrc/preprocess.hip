@@ -381,7 +381,10 @@ __global__ void __launch_bounds__(256) k_select_pass2(const float* __restrict__ 
 }
 
 // The last digits from hist2 give the limits (workgroup 0 stores them for
-// the host), then the stretch.
+// the host), then the stretch.  Each thread takes chunks of 4 consecutive
+// values (one 16-byte load and store when both buffers are 16-byte
+// aligned); its first chunk is loaded before the pick, so that load's
+// latency overlaps it.
 __global__ void __launch_bounds__(256) k_stretch(const float* __restrict__ s, long long n,
                                                  uint32_t* __restrict__ hist0,
                                                  const uint32_t* __restrict__ hist2,
@@ -391,10 +394,29 @@ __global__ void __launch_bounds__(256) k_stretch(const float* __restrict__ s, lo
     const uint32_t pre[2] = {st->prefix[1][0], st->prefix[1][1]};
     const uint32_t rk1[2] = {st->rank[1][0], st->rank[1][1]};
     uint32_t d2[2], rk[2];
-    // the first value is loaded before the pick, so its latency overlaps it
+    const bool vec = ((reinterpret_cast<uintptr_t>(s) | reinterpret_cast<uintptr_t>(out)) & 15u) == 0;
+    const long long nch = (n + 3) / 4;
     const long long step = (long long)gridDim.x * blockDim.x;
-    long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    float v = i < n ? s[i] : 0.0f;
+    long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    auto load = [&](long long ch) {
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        const long long i = 4 * ch;
+        if (ch < nch) {
+            if (vec && i + 4 <= n) {
+                v = *reinterpret_cast<const float4*>(s + i);
+            } else {
+                v.x = s[i];
+                if (i + 1 < n)
+                    v.y = s[i + 1];
+                if (i + 2 < n)
+                    v.z = s[i + 2];
+                if (i + 3 < n)
+                    v.w = s[i + 3];
+            }
+        }
+        return v;
+    };
+    float4 v = load(c);
     pick_both(hist2, 1024, kRep, false, rk1, s_res, d2, rk);
     const float lo = value_of((pre[0] << 10) | d2[0]);
     const float hi = value_of((pre[1] << 10) | d2[1]);
@@ -406,11 +428,26 @@ __global__ void __launch_bounds__(256) k_stretch(const float* __restrict__ s, lo
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kRep * hwords(kBins);
          i += gridDim.x * blockDim.x)
         hist0[i] = 0u;
-    for (; i < n; i += step) {
-        const float x = v;
-        if (i + step < n)
-            v = s[i + step];
-        out[i] = hi > lo ? fminf(fmaxf((x - lo) / (hi - lo), 0.0f), 1.0f) : 0.0f;
+    auto stretch = [&](float x) {
+        return hi > lo ? fminf(fmaxf((x - lo) / (hi - lo), 0.0f), 1.0f) : 0.0f;
+    };
+    for (; c < nch; c += step) {
+        const float4 x = v;
+        if (c + step < nch)
+            v = load(c + step);
+        const float4 y = make_float4(stretch(x.x), stretch(x.y), stretch(x.z), stretch(x.w));
+        const long long i = 4 * c;
+        if (vec && i + 4 <= n) {
+            *reinterpret_cast<float4*>(out + i) = y;
+        } else {
+            out[i] = y.x;
+            if (i + 1 < n)
+                out[i + 1] = y.y;
+            if (i + 2 < n)
+                out[i + 2] = y.z;
+            if (i + 3 < n)
+                out[i + 3] = y.w;
+        }
     }
 }
 
@@ -454,7 +491,7 @@ hipError_t dogk_preprocess(const float* d_in, int H, int W, long long stride, co
                        n, (const uint32_t*)h0, h1, h2, rank_lo, rank_hi, st);
     hipLaunchKernelGGL(k_select_pass2, dim3((unsigned)g), dim3(256), 0, stream, (const float*)d_s,
                        n, (const uint32_t*)h1, h2, st);
-    const long long gs = std::max<long long>(1, std::min<long long>((n + 1023) / 1024, 4096));
+    const long long gs = std::max<long long>(1, std::min<long long>((n + 1023) / 1024, 4096));   // 4 values per thread
     hipLaunchKernelGGL(k_stretch, dim3((unsigned)gs), dim3(256), 0, stream, (const float*)d_s, n, h0,
                        (const uint32_t*)h2, st, d_out);
     return hipGetLastError();

@@ -2,8 +2,9 @@
 oracle: the smoothed image within the plane tolerance, the stretch limits
 exactly the order statistics of the GPU's own fp32 smoothed image (and close
 to the oracle's), the stretched image equal to its definition; no smoothing,
-no saturation and a constant image as special cases; successive calls on two
-streams; and the detector run on the preprocessed frame."""
+no saturation and a constant image as special cases; strided input and
+unaligned output buffers; successive calls on two streams; and the detector
+run on the preprocessed frame."""
 import numpy as np
 import pytest
 
@@ -88,6 +89,28 @@ def test_preprocess_strided_view(dog, torch_mod):
     assert view.stride(0) == 200 and torch.equal(a, b) and lim_a == lim_b
     o_out, _, o_lo, o_hi = oracle.preprocess(np.ascontiguousarray(img[:, 13:170]), 1.0, 0.0035)
     assert np.max(np.abs(a.cpu().numpy() - o_out)) <= 1e-4
+
+
+def test_preprocess_unaligned_buffers(dog, torch_mod):
+    # output and smoothed buffers 4 bytes off 16-byte alignment (the stretch
+    # then moves single values, not 16-byte chunks) and a pixel count that is
+    # not a multiple of 4: the same result as aligned buffers
+    torch = torch_mod
+    img = _counts(90, 123, 77, 15)
+    t = torch.from_numpy(img).cuda()
+    H, W = img.shape
+    buf = torch.empty(H * W + 2, dtype=torch.float32, device="cuda")
+    sbuf = torch.empty(H * W + 2, dtype=torch.float32, device="cuda")
+    out_u = buf[1:1 + H * W].view(H, W)
+    sm_u = sbuf[1:1 + H * W].view(H, W)
+    assert out_u.data_ptr() % 16 != 0 and sm_u.data_ptr() % 16 != 0 and (H * W) % 4 != 0
+    with dog.Context(0) as c:
+        a, lim_a = c.preprocess(t, 1.0, 0.0035, limits=True)
+        b, lim_b = c.preprocess(t, 1.0, 0.0035, out=out_u, smoothed=sm_u, limits=True)
+        torch.cuda.synchronize()
+    assert lim_a == lim_b and torch.equal(a, b)
+    o_out, _, _, _ = oracle.preprocess(img, 1.0, 0.0035)
+    assert np.max(np.abs(b.cpu().numpy() - o_out)) <= 1e-4
 
 
 def test_preprocess_constant_image(dog, torch_mod):
