@@ -76,6 +76,18 @@ def test_preprocess_matches_oracle(dog, torch_mod, shape, sigma, sat):
     assert O.min() >= 0.0 and O.max() <= 1.0
 
 
+@pytest.mark.parametrize("shape", [(4096, 4096), (3001, 4999)])
+def test_preprocess_large_frames(dog, torch_mod, shape):
+    # frames large enough that every select-pass thread counts several
+    # batches of keys and the stretch sweeps the frame several times (the
+    # launch grids are capped at 4096 workgroups); a ragged pixel count
+    H, W = shape
+    print("preprocess %d x %d" % (H, W), flush=True)
+    img = _counts(50 + H, H, W, 400)
+    O, lo, hi = _check(dog, torch_mod, img, 1.0, 0.0035)
+    assert O.min() >= 0.0 and O.max() <= 1.0 and lo < hi
+
+
 def test_preprocess_strided_view(dog, torch_mod):
     # a crop of a wider frame: rows of the view are row_stride floats apart
     torch = torch_mod
