@@ -115,3 +115,20 @@ def test_three_in_flight_full_size(dog, torch_mod):
     finally:
         for c in ctxs:
             c.close()
+
+
+@pytest.mark.parametrize("H,W,n_blobs", [(4096, 4096, 2000), (8, 32768, 60), (32768, 8, 60)])
+def test_large_and_extreme_frames(dog, torch_mod, H, W, n_blobs):
+    # a frame 16x the benchmark's, and the longest side the library accepts
+    # on a frame 8 pixels across (in both orientations), against the oracle
+    torch = torch_mod
+    prm = dog.Params(**CAMERA)
+    print("frame %d x %d" % (H, W), flush=True)
+    img = synth.camera_frame(seed=H + W, H=H, W=W, n_blobs=n_blobs)
+    t = torch.from_numpy(img).cuda()
+    with dog.Context(0) as c:
+        blobs = c.detect_device(t, prm)
+        raw, D_o, sig, exempt = _oracle_check(c, t, img, prm)
+    check_pruned(blobs, raw, D_o, prm.threshold, sig, prm.overlap, exempt)
+    print("frame %d x %d: raw %d pruned %d exempt %d" % (H, W, len(raw), len(blobs), exempt), flush=True)
+    assert len(blobs) > 0
