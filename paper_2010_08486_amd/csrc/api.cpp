@@ -439,7 +439,7 @@ int dog_preprocess(dog_context* ctx, const float* d_image, int64_t height, int64
     if (ctx->prep.p != had) {
         // fresh scratch: the kernels expect zero histograms (each call
         // leaves them zero for the next)
-        DOG_HIP(hipMemset(ctx->prep.p, 0, scratch));
+        ctx->prep_dirty = true;
         ctx->prep_sigma = -1.0;
     }
     float* d_w = reinterpret_cast<float*>(static_cast<char*>(ctx->prep.p) + scratch);
@@ -450,6 +450,12 @@ int dog_preprocess(dog_context* ctx, const float* d_image, int64_t height, int64
         DOG_HIP(hipEventCreateWithFlags(&ctx->ev_prep, hipEventDisableTiming));
     else
         DOG_HIP(hipStreamWaitEvent(st, ctx->ev_prep, 0));
+    if (ctx->prep_dirty) {
+        // ordered on this stream after the previous call (the first call of
+        // a context, or the one after a failed launch)
+        DOG_HIP(hipMemsetAsync(ctx->prep.p, 0, scratch, st));
+        ctx->prep_dirty = false;
+    }
     if (ctx->prep_sigma != smooth_sigma) {
         // the detector's kernel rule: exp(-j^2 / (2 s^2)) in FP64, normalised
         // over the truncated support, rounded once to fp32 (no smoothing:
@@ -469,8 +475,16 @@ int dog_preprocess(dog_context* ctx, const float* d_image, int64_t height, int64
     long long m = (long long)std::floor(saturated * (double)N / 2.0);
     m = std::min(m, (N - 1) / 2);
     float* d_s = d_smoothed ? d_smoothed : d_out;
-    DOG_HIP(dogk_preprocess(d_image, (int)height, (int)width, (long long)row_stride, d_w, r, d_s,
-                            d_out, ctx->prep.p, (uint32_t)m, (uint32_t)(N - 1 - m), st));
+    const hipError_t le = dogk_preprocess(d_image, (int)height, (int)width, (long long)row_stride,
+                                          d_w, r, d_s, d_out, ctx->prep.p, (uint32_t)m,
+                                          (uint32_t)(N - 1 - m), st);
+    if (le != hipSuccess) {
+        // some kernels may have run and left counts behind: the next call
+        // clears the scratch first, after what was queued here
+        ctx->prep_dirty = true;
+        (void)hipEventRecord(ctx->ev_prep, st);
+        DOG_HIP(le);
+    }
     DOG_HIP(hipEventRecord(ctx->ev_prep, st));
     if (limits_out) {
         DOG_HIP(hipMemcpyAsync(limits_out, static_cast<char*>(ctx->prep.p) + 16, 2 * sizeof(float),

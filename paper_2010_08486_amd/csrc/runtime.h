@@ -129,6 +129,7 @@ struct dog_context {
     dog::PinBuf h_input;           // staging of host frames
     dog::DevBuf prep;              // preprocessing: select state, histograms, weights
     double prep_sigma = -1.0;      // smoothing sigma whose weights `prep` holds
+    bool prep_dirty = false;       // `prep` histograms not known to be zero
     hipEvent_t ev_prep = nullptr;  // recorded after the last preprocessing launch
 
     // optional per-kernel timing: start and end events of each kernel's
