@@ -28,7 +28,7 @@
 namespace dogpre {
 
 constexpr int kSR = 8;         // output rows per smoothing workgroup (256 columns)
-constexpr int kMaxR = 16;      // largest smoothing radius (sigma <= 3.9 at truncate 4)
+constexpr int kMaxR = 16;      // largest smoothing radius (sigma < 4.125 at truncate 4)
 constexpr int kRep = 8;        // replicas of every digit histogram
 constexpr int kBins = 2048;    // digit histogram bins (11 bits)
 constexpr int kBatch = 8;      // keys loaded per thread before counting
@@ -271,8 +271,8 @@ __device__ __forceinline__ void load_keys(const float* __restrict__ s, long long
 
 // Each target's next digit from `hist` (one nb-bin histogram per target in
 // `reps` replicas, the target's at stride reps hwords(nb), or one shared
-// when `shared`);
-// the results reach every thread through LDS.  Needs at least two waves.
+// when `shared`); the results reach every thread through LDS.  Needs at
+// least two waves.
 __device__ void pick_both(const uint32_t* __restrict__ hist, int nb, int reps, bool shared,
                           const uint32_t rank[2], uint32_t* s_res, uint32_t digit[2],
                           uint32_t rem[2])
