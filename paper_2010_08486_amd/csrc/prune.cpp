@@ -164,7 +164,7 @@ void prune_blobs(std::vector<dog_blob>& v, const std::vector<double>& sigma64, d
             if (best < 0)
                 break;
             const size_t b = members[pos[best]];
-            if ((double)(v[b].y - v[a].y) >= reach) {
+            if ((double)v[b].y - (double)v[a].y >= reach) {
                 end[best] = pos[best];   // this bucket has nothing closer left
                 continue;
             }
@@ -175,7 +175,8 @@ void prune_blobs(std::vector<dog_blob>& v, const std::vector<double>& sigma64, d
             // disks that clearly cannot touch have overlap 0 <= `overlap`:
             // skip them without the square root (the margin keeps every pair
             // the exact test could see as touching)
-            const double dy = (double)(v[b].y - v[a].y), dx = (double)(v[b].x - v[a].x);
+            // differences in double: coordinates far apart would overflow int32
+            const double dy = (double)v[b].y - (double)v[a].y, dx = (double)v[b].x - (double)v[a].x;
             const double rs = std::sqrt(2.0) * (sa + sb);
             if (dy * dy + dx * dx > rs * rs * (1.0 + 1e-9))
                 continue;

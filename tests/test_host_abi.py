@@ -187,3 +187,35 @@ def test_prune_wide_frames_match_oracle(coalesce, spread):
     assert 0 < len(exp) < len(s)
     assert got[["y", "x", "scale"]].tolist() == exp[["y", "x", "scale"]].tolist()
     assert np.array_equal(got["sigma"], s_out[keep].astype(np.float32))
+
+
+@pytest.mark.parametrize("coalesce", [False, True])
+def test_prune_extreme_coordinates(coalesce):
+    # clusters spread over the whole int32 range: the packed sort key does
+    # not fit in 64 bits (the three-field sort runs), coordinate differences
+    # exceed int32, and blobs in a cluster still overlap
+    rng = np.random.default_rng(11 + coalesce)
+    n = 400
+    prm = dog.Params(1, 30, 1.6, 0.05, 0.5, 4.0, "geometric", 0, coalesce)
+    sig = dog.plan_info(prm)["sigmas"]
+    centres = rng.integers(-2**31 + 100, 2**31 - 100, (25, 2))
+    # two clusters at the two ends of the row range: their int32 row
+    # difference would wrap to a few pixels
+    centres[0] = (-2**31 + 8, 0)
+    centres[1] = (2**31 - 9, 0)
+    pick = rng.integers(0, 25, n)
+    b = np.zeros(n, dog.BLOB_DTYPE)
+    b["y"] = centres[pick, 0] + rng.integers(-8, 9, n)
+    b["x"] = centres[pick, 1] + rng.integers(-8, 9, n)
+    b["scale"] = rng.integers(0, 8, n)
+    _, u = np.unique(b[["y", "x", "scale"]], return_index=True)
+    b = b[np.sort(u)]
+    rng.shuffle(b)
+    got = dog.prune(prm, b)
+    s = b[np.lexsort((b["scale"], b["x"], b["y"]))]
+    keep, s_out = oracle.prune(s["y"], s["x"], sig[s["scale"]], 0.5, coalesce=True) if coalesce else \
+        (oracle.prune(s["y"], s["x"], sig[s["scale"]], 0.5), sig[s["scale"]])
+    exp = s[keep]
+    assert 0 < len(exp) < len(s)
+    assert got[["y", "x", "scale"]].tolist() == exp[["y", "x", "scale"]].tolist()
+    assert np.array_equal(got["sigma"], s_out[keep].astype(np.float32))
