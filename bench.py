@@ -374,9 +374,9 @@ def main() -> int:
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the detector's frames are independent and this "
-              "build runs on a single MI355X (multi-GPU sharding is described in the design "
-              "notes, not run). Use --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: frames are independent, so several GPUs would take "
+              "whole frames each with no collective, and only the one-GPU measurement is "
+              "implemented. Use --gpus 1.", file=sys.stderr)
         return 2
 
     import numpy as np

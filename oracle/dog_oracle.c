@@ -20,7 +20,7 @@
  *   - blob radius sqrt(2)*sigma and overlap pruning             (Sec. 3, Sec. 4.1)
  *
  * Readings of points where the paper is silent or differs from the target
- * configuration (each is listed in the design notes of the repository):
+ * configuration:
  *   R1 ladder: geometric, k = floor(ln(smax/smin)/ln(ratio)) + 1 DoG planes,
  *      sigma_i = smin * ratio^i for i = 0..k (k+1 Gaussian planes).  The
  *      paper's Eq. 1 is arithmetic; the arithmetic form is also provided.
