@@ -34,8 +34,10 @@
  *     library and released with dog_blobs_free().
  *   - Streams are hipStream_t values passed as void*; the sequence is
  *     issued on that stream, after the work already queued there (NULL = the
- *     null stream).  Device entry points are synchronous with respect to the
- *     host: they return after the results have been copied back.
+ *     null stream).  Entry points that return results (blob lists, limits,
+ *     planes) return after those results are complete; the two that only
+ *     queue work return at once and say so below: dog_detect_device_async,
+ *     and dog_preprocess when limits_out is NULL.
  */
 #ifndef DOG_H
 #define DOG_H
@@ -354,11 +356,24 @@ typedef struct {
     double mean_batch_frames;
     double p50_ms, p99_ms, mean_ms, max_ms;   /* submit -> blob list ready          */
     double frames_per_s;                      /* completed / (last done - first submit) */
+    /* Admission: a slot that runs a batch commits the device bytes its
+     * workspace may reach for that batch (each buffer at least what it holds,
+     * grown to the batch's planes and staged inputs, plus launch tables and
+     * candidates), an idle slot what its workspace holds.  reserved = the
+     * sum over the slots now; it never exceeds the budget, and each slot's
+     * allocations are capped at its commit.  held = the bytes the slots'
+     * workspaces actually hold after their last batches; peak over batch
+     * completions. */
     uint64_t reserved_bytes, peak_reserved_bytes;
+    uint64_t held_bytes, peak_held_bytes;
 } dog_stats;
 
-/* Create a server on GPU `device` for fixed detector parameters.  Frame
- * footprint for admission: 2 (k+1) W ceil64(H) + H W floats + 4 KiB. */
+/* Create a server on GPU `device` for fixed detector parameters.  A request
+ * is rejected at submit (DOG_ENOMEM) when its frame alone would need more
+ * than the budget: dog_footprint of that frame (its planes, the staged input
+ * of a host frame, launch tables and candidates).  Idle slots keep their
+ * workspaces between batches and release them when the oldest waiting
+ * request would not fit otherwise. */
 int dog_server_create(int device, const dog_params* params, const dog_server_opts* opts,
                       dog_server** out);
 /* Queue a host frame (copied; the caller may reuse its buffer at once).

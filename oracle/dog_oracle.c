@@ -472,7 +472,8 @@ void orc_radius_histogram(int k, const double *ladder, int64_t n, const double *
 /* Whole detector on one fp32 image: ladder, planes, DoG, local maxima,
  * threshold, then pruning.  Writes up to cap blobs (y, x, i) with sigma and
  * response, sorted by (y, x, i).  *n_raw receives the count before pruning.
- * Returns the count after pruning, or -1 on bad input. */
+ * Returns the count after pruning, or -1 on bad input or when memory for the
+ * DoG cube or the candidate lists cannot be allocated. */
 int64_t orc_detect(const float *image, int64_t H, int64_t W, int64_t stride,
                    double smin, double smax, double ratio, double threshold,
                    double overlap, double truncate, int32_t *yxi,
@@ -487,20 +488,33 @@ int64_t orc_detect(const float *image, int64_t H, int64_t W, int64_t stride,
     orc_sigmas_geometric(smin, ratio, k, s);
     size_t px = (size_t)H * (size_t)W;
     double *D = (double *)malloc(sizeof(double) * px * (size_t)k);
+    if (!D)
+        return -1;
     if (orc_planes_sigmas(image, H, W, stride, k + 1, s, truncate, NULL, D) != 0) {
         free(D);
         return -1;
     }
     int64_t n = orc_nms(D, k, H, W, threshold, NULL, NULL, 0);
-    int32_t *c = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)(n > 0 ? n : 1));
-    double *v = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    int32_t *c = (int32_t *)malloc(sizeof(int32_t) * 3 * nn);
+    double *v = (double *)malloc(sizeof(double) * nn);
+    int32_t *ys = (int32_t *)malloc(sizeof(int32_t) * nn);
+    int32_t *xs = (int32_t *)malloc(sizeof(int32_t) * nn);
+    double *ss = (double *)malloc(sizeof(double) * nn);
+    uint8_t *keep = (uint8_t *)malloc(nn);
+    if (!c || !v || !ys || !xs || !ss || !keep) {
+        free(D);
+        free(c);
+        free(v);
+        free(ys);
+        free(xs);
+        free(ss);
+        free(keep);
+        return -1;
+    }
     orc_nms(D, k, H, W, threshold, c, v, n);
     free(D);
 
-    int32_t *ys = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
-    int32_t *xs = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
-    double *ss = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
-    uint8_t *keep = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
     for (int64_t a = 0; a < n; ++a) {
         ys[a] = c[3 * a];
         xs[a] = c[3 * a + 1];

@@ -73,7 +73,8 @@ class dog_stats(ctypes.Structure):
                                                "queued", "running", "batches")] + \
                [(n, ctypes.c_double) for n in ("mean_batch_frames", "p50_ms", "p99_ms", "mean_ms",
                                                 "max_ms", "frames_per_s")] + \
-               [("reserved_bytes", ctypes.c_uint64), ("peak_reserved_bytes", ctypes.c_uint64)]
+               [("reserved_bytes", ctypes.c_uint64), ("peak_reserved_bytes", ctypes.c_uint64),
+                ("held_bytes", ctypes.c_uint64), ("peak_held_bytes", ctypes.c_uint64)]
 
 
 @dataclass

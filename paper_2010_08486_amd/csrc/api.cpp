@@ -321,14 +321,18 @@ int dog_footprint(const dog_params* params, int32_t n_frames, const int64_t* hei
         set_error(err);
         return rc;
     }
-    uint64_t b = 0;
+    uint64_t planes = 0, input = 0;
     for (int32_t f = 0; f < n_frames; ++f) {
-        const uint64_t pitch = ((uint64_t)heights[f] + 63) / 64 * 64;
-        b += 2ull * P.n_g * (uint64_t)widths[f] * pitch * sizeof(float);
-        b += (uint64_t)heights[f] * (uint64_t)widths[f] * sizeof(float);  // staged input
+        if (heights[f] < 1 || widths[f] < 1) {
+            set_error("frame shapes must be positive");
+            return DOG_EINVAL;
+        }
+        planes += frame_plane_bytes(P, heights[f], widths[f]);
+        input += frame_input_bytes(heights[f], widths[f]);  // staged host frame
     }
-    b += 4096ull * (3 * (uint64_t)n_frames * P.n_g + 64) / 64;  // tables (rough, generous)
-    *bytes_out = b;
+    auto page = [](uint64_t x) { return (x + 4095) & ~(uint64_t)4095; };
+    *bytes_out = page(planes) + page(input) +
+                 (n_frames ? overhead_bound(P, n_frames, heights, widths) : 0);
     return DOG_OK;
 }
 

@@ -97,10 +97,13 @@ static int run_grouped(dog_context* ctx, const Plan& P, const std::vector<FrameI
 
     const int K = std::min<int>(ctx->lane_count, (int)groups);
     while ((int)ctx->lanes.size() < K) {
+        // lanes allocate out of this context's budget (ctx_alloc counts the
+        // parent and every lane together)
         dog_context* l = nullptr;
-        int rc = dog_context_create(ctx->device, std::max<uint64_t>(ctx->budget / 4, 1ull << 28), &l);
+        int rc = dog_context_create(ctx->device, ctx->budget, &l);
         if (rc != DOG_OK)
             return rc;
+        l->parent = ctx;
         ctx->lanes.push_back(l);
     }
     if (!ctx->ev_fork)
@@ -191,16 +194,26 @@ int detect_frames(dog_context* ctx, const dog_params* params, int32_t n_frames,
             }
             continue;
         }
-        const uint64_t pitch = ((uint64_t)fr.height + 63) / 64 * 64;
-        uint64_t b = 2ull * P->n_g * (uint64_t)fr.width * pitch * sizeof(float) + 256;
+        uint64_t b = frame_plane_bytes(*P, fr.height, fr.width);
         if (fr.on_device != 1)
-            b += (uint64_t)fr.height * (uint64_t)fr.width * sizeof(float) + 256;
+            b += frame_input_bytes(fr.height, fr.width);
         idx.push_back(f);
         need.push_back(b);
     }
-    // consecutive chunks that fit in what the budget leaves for planes and inputs
-    const uint64_t fixed = ctx->used - ctx->planes.bytes - ctx->input.bytes;
-    const uint64_t room = ctx->budget > fixed + (64u << 20) ? ctx->budget - fixed - (64u << 20) : 0;
+    // consecutive chunks that fit in what the budget leaves for planes and
+    // inputs; the lanes' workspaces count against the same budget and are
+    // released first when the next frame would not fit beside them
+    auto room_now = [&]() -> uint64_t {
+        const uint64_t fixed = ctx_total_used(ctx) - ctx->planes.bytes - ctx->input.bytes;
+        return ctx->budget > fixed + ctx->room_margin ? ctx->budget - fixed - ctx->room_margin : 0;
+    };
+    uint64_t room = room_now();
+    if (!idx.empty() && need[0] > room && !ctx->lanes.empty()) {
+        for (dog_context* l : ctx->lanes)
+            if ((rc = ctx_trim(l)) != DOG_OK)
+                return rc;
+        room = room_now();
+    }
     size_t i = 0;
     while (i < idx.size()) {
         size_t j = i;

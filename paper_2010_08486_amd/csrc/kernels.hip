@@ -580,6 +580,8 @@ struct CandSink {
     CandHeader* cand;
     CandRec* recs;
     uint32_t cap;
+    CandRec* host_recs;   // pinned host copy of records [0, lim_h)
+    uint32_t lim_h;       // min(cap, n_host)
 };
 
 // Append the voxels of one band row whose flag is set (wave ballot, prefix
@@ -604,9 +606,14 @@ __device__ __forceinline__ void emit_row(const CandSink& snk, const FrameDesc& f
             if (idx < DOG_LDS_RECS) {
                 snk.s_rec[idx] = rec;
             } else {
+                // LDS buffer full: straight to the global list, and to the
+                // pinned host copy like every record below lim_h, since the
+                // host reads records [0, n_host) from there only
                 const unsigned g = atomicAdd(&snk.cand->count, 1u);
                 if (g < snk.cap)
                     snk.recs[g] = rec;
+                if (g < snk.lim_h)
+                    snk.host_recs[g] = rec;
             }
         }
     }
@@ -655,13 +662,12 @@ __device__ __forceinline__ void flush_sink(const CandSink& snk, uint32_t* s_base
         *s_base = n ? atomicAdd(&snk.cand->count, n) : 0u;
     __syncthreads();
     const uint32_t gbase = *s_base;
-    const uint32_t lim_h = snk.cap < a.n_host ? snk.cap : a.n_host;
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
         const uint32_t g = gbase + i;
         if (g < snk.cap)
             snk.recs[g] = snk.s_rec[i];
-        if (g < lim_h)
-            a.host_recs[g] = snk.s_rec[i];
+        if (g < snk.lim_h)
+            snk.host_recs[g] = snk.s_rec[i];
     }
     if (threadIdx.x == 0)
         a.host_ends[blockIdx.x] = gbase + n;
@@ -684,7 +690,8 @@ __global__ void __launch_bounds__(64 * NW) k_nms(LaunchArgs a)
     if (threadIdx.x == 0)
         s_n = 0u;
     __syncthreads();
-    const CandSink snk{&s_n, s_rec, a.cand, reinterpret_cast<CandRec*>(a.cand + 1), a.cap};
+    const CandSink snk{&s_n, s_rec, a.cand, reinterpret_cast<CandRec*>(a.cand + 1), a.cap,
+                       a.host_recs, a.cap < a.n_host ? a.cap : a.n_host};
     const Tile tl = my_tile(a.tiles3);
     const FrameDesc f = frame_of(a, tl.frame);
     const DOG_CONSTANT_AS LadderDesc* ld = cst(a.ladders) + f.ladder;

@@ -23,21 +23,32 @@ int hip_fail(hipError_t e, const char* what)
     return (e == hipErrorOutOfMemory) ? DOG_ENOMEM : DOG_EDEVICE;
 }
 
+uint64_t ctx_total_used(const dog_context* c)
+{
+    uint64_t u = c->used;
+    for (const dog_context* l : c->lanes)
+        u += l->used;
+    return u;
+}
+
 int ctx_alloc(dog_context* c, DevBuf* b, size_t bytes, const char* what)
 {
     if (b->bytes >= bytes)
         return DOG_OK;
+    // a lane allocates out of its parent's budget
+    const dog_context* root = c->parent ? c->parent : c;
+    const uint64_t held = ctx_total_used(root);
     // grow geometrically so a sequence of slightly larger requests does not
-    // reallocate every time
-    size_t want = std::max(bytes, b->bytes + b->bytes / 4);
+    // reallocate every time (unless exact allocation is asked for)
+    size_t want = c->exact_alloc ? bytes : std::max(bytes, b->bytes + b->bytes / 4);
     want = (want + 4095) & ~(size_t)4095;
-    const uint64_t after = c->used - b->bytes + want;
-    if (after > c->budget) {
+    const uint64_t after = held - b->bytes + want;
+    if (after > root->budget) {
         want = (bytes + 4095) & ~(size_t)4095;
-        if (c->used - b->bytes + want > c->budget) {
+        if (held - b->bytes + want > root->budget) {
             set_error(std::string("HBM budget exceeded allocating ") + what + ": need " +
-                      std::to_string(c->used - b->bytes + want) + " bytes, budget " +
-                      std::to_string(c->budget));
+                      std::to_string(held - b->bytes + want) + " bytes, budget " +
+                      std::to_string(root->budget));
             return DOG_ENOMEM;
         }
     }
@@ -62,6 +73,66 @@ int ctx_alloc(dog_context* c, DevBuf* b, size_t bytes, const char* what)
     return DOG_OK;
 }
 
+int ctx_trim(dog_context* c)
+{
+    if (c->stream)
+        DOG_HIP(hipStreamSynchronize(c->stream));
+    drop_graph(c);
+    for (DevBuf* b : {&c->planes, &c->input, &c->tables, &c->cand}) {
+        if (b->p) {
+            DOG_HIP(hipFree(b->p));
+            c->used -= b->bytes;
+        }
+        b->p = nullptr;
+        b->bytes = 0;
+    }
+    c->cap = 0;
+    c->seen_key.clear();
+    return DOG_OK;
+}
+
+static constexpr uint64_t kInitialCap = 65536;   // candidate records of a new context
+
+uint64_t frame_plane_bytes(const Plan& P, int64_t H, int64_t W)
+{
+    const uint64_t pitch = ((uint64_t)H + 63) / 64 * 64;
+    return 2ull * (uint64_t)P.n_g * (uint64_t)W * pitch * sizeof(float) + 256;
+}
+
+uint64_t frame_input_bytes(int64_t H, int64_t W)
+{
+    return (uint64_t)H * (uint64_t)W * sizeof(float) + 256;
+}
+
+uint64_t overhead_bound(const Plan& P, int n, const int64_t* heights, const int64_t* widths)
+{
+    // smallest bands of any variant: blur tiles are 64 columns by at least
+    // min_band rows, local-maximum tiles 62 columns by at least min_nms rows
+    int min_band = 1 << 30, min_nms = 1 << 30, max_pad_rows = 0;
+    for (int v = 0; v < dogk_num_variants(); ++v) {
+        int S, NW, BI, BN, NWN;
+        dogk_variant_geometry(v, &S, &NW, &BI, &BN, &NWN);
+        min_band = std::min(min_band, S * NW * BI);
+        min_nms = std::min(min_nms, BN * NWN);
+        max_pad_rows = std::max(max_pad_rows, (dogk_variant_ring(v) + 1) * S);
+    }
+    const int rmax = *std::max_element(P.r.begin(), P.r.end());
+    const uint64_t pad = (uint64_t)rmax + (uint64_t)max_pad_rows;
+    uint64_t tiles = 0, rows = 0;
+    for (int f = 0; f < n; ++f) {
+        const uint64_t H = (uint64_t)heights[f], W = (uint64_t)widths[f];
+        tiles += (uint64_t)P.n_g * ((W + 63) / 64) * ((H + min_band - 1) / min_band);
+        tiles += (uint64_t)P.n_g * ((H + 63) / 64) * ((W + min_band - 1) / min_band);
+        tiles += ((H + DOG_NMS_COLS - 1) / DOG_NMS_COLS) * ((W + min_nms - 1) / min_nms);
+        rows += (H + 2 * pad + 64) + (W + 2 * pad + 64);
+    }
+    const uint64_t tables = sizeof(FrameDesc) * (uint64_t)n + sizeof(LadderDesc) +
+                            sizeof(float) * P.weights.size() + sizeof(Tile) * tiles +
+                            sizeof(int) * rows + 8 * 256;
+    const uint64_t cand = sizeof(CandHeader) + sizeof(CandRec) * kInitialCap;
+    return ((tables + 4095) & ~(uint64_t)4095) + ((cand + 4095) & ~(uint64_t)4095);
+}
+
 int ctx_pin(PinBuf* b, size_t bytes)
 {
     if (b->bytes >= bytes)
@@ -84,7 +155,12 @@ int ctx_plan(dog_context* c, const dog_params* prm, const Plan** out)
         set_error("params is NULL");
         return DOG_EINVAL;
     }
-    if (!c->have_plan || !same_params(c->plan.prm, *prm) || prm->truncate == 0.0) {
+    // the plan stores truncate 0 as the 4 it selects: compare in that form,
+    // so callers that leave it 0 keep their plan (and captured graph)
+    dog_params want = *prm;
+    if (want.truncate == 0.0)
+        want.truncate = 4.0;
+    if (!c->have_plan || !same_params(c->plan.prm, want)) {
         Plan P;
         std::string err;
         const int rc = build_plan(*prm, &P, &err);
@@ -282,10 +358,10 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
     if (rc != DOG_OK)
         return rc;
     if (c->cap == 0) {
-        if ((rc = ctx_alloc(c, &c->cand, sizeof(CandHeader) + kRecBytes * 65536, "candidates")) !=
-            DOG_OK)
+        if ((rc = ctx_alloc(c, &c->cand, sizeof(CandHeader) + kRecBytes * kInitialCap,
+                            "candidates")) != DOG_OK)
             return rc;
-        c->cap = 65536;
+        c->cap = (uint32_t)kInitialCap;
     }
     if ((rc = ctx_pin(&c->h_cand, sizeof(CandHeader) + kRecBytes * (size_t)c->cap)) != DOG_OK)
         return rc;

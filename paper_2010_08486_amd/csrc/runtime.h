@@ -117,6 +117,16 @@ struct dog_context {
     std::map<std::string, int> tuned;  // "HxW|radii" -> autotuned variant
     int occ[3] = {0, 0, 0};        // workgroups per CU of each kernel (active variant)
 
+    // device memory accounting: allocations are checked against `budget`
+    // together with the lanes' (child contexts of grouped batches, which
+    // share their parent's budget).  exact_alloc: allocate what is asked
+    // (server slots, whose every byte is committed by admission) instead of
+    // growing buffers by a quarter; room_margin: bytes kept free for tables
+    // and candidates when a batch is cut into chunks that fit the budget.
+    dog_context* parent = nullptr;
+    bool exact_alloc = false;
+    uint64_t room_margin = 64ull << 20;
+
     dog::DevBuf planes;            // T, L (and debug D) planes of all frames
     dog::DevBuf input;             // device copies of host frames
     dog::DevBuf tables;            // frames, ladder, weights, units
@@ -182,6 +192,19 @@ struct dog_context {
 namespace dog {
 
 int ctx_alloc(dog_context* c, DevBuf* b, size_t bytes, const char* what);
+// Device bytes held by a context and its lanes.
+uint64_t ctx_total_used(const dog_context* c);
+// Free the workspace buffers of an idle context (planes, inputs, tables,
+// candidates); they are allocated again on the next launch.
+int ctx_trim(dog_context* c);
+// Bytes of a launch sequence over frames of these shapes beyond the planes
+// and staged inputs: an upper bound of its launch tables (any variant) and
+// the initial candidate buffer.
+uint64_t overhead_bound(const Plan& P, int n, const int64_t* heights, const int64_t* widths);
+// Bytes the planes (and, for host frames, the staged input) of one frame
+// take in a launch sequence, as detect_frames sizes its chunks.
+uint64_t frame_plane_bytes(const Plan& P, int64_t H, int64_t W);
+uint64_t frame_input_bytes(int64_t H, int64_t W);
 int ctx_pin(PinBuf* b, size_t bytes);
 int ctx_plan(dog_context* c, const dog_params* prm, const Plan** out);
 int ctx_set_variant(dog_context* c, int v);

@@ -113,6 +113,12 @@ struct Slot {
     std::thread th;
     std::vector<Request> batch;
     bool has_work = false;
+    // device buffers the slot's context holds (as of its last batch) and the
+    // bytes admission counts for it: what it holds while idle, the bound of
+    // its batch while running (its context's budget is capped at that bound)
+    uint64_t planes_b = 0, input_b = 0, other_b = 0;
+    uint64_t commit = 0;
+    uint64_t held() const { return planes_b + input_b + other_b; }
 };
 
 }  // namespace
@@ -120,6 +126,7 @@ struct Slot {
 struct dog_server {
     dog_params prm{};
     dog_server_opts opts{};
+    dog::Plan plan;
     int n_g = 0;
     uint64_t budget = 0;
 
@@ -133,8 +140,9 @@ struct dog_server {
     std::unordered_map<uint64_t, dog_result> done;
     std::unordered_set<uint64_t> pending;  // queued or running
     uint64_t next_ticket = 1;
-    uint64_t reserved = 0;                 // footprint of batches in flight
+    uint64_t reserved = 0;                 // sum of the slots' commits
     uint64_t peak_reserved = 0;
+    uint64_t peak_held = 0;                // largest sum of the slots' held bytes
     bool stop = false;
     std::thread dispatcher;
 
@@ -147,11 +155,43 @@ struct dog_server {
 
 namespace {
 
-uint64_t frame_footprint(int n_g, int64_t H, int64_t W, bool on_device)
+uint64_t page(uint64_t x) { return (x + 4095) & ~(uint64_t)4095; }
+
+// Device bytes slot sl may hold while it runs `reqs` (plus `extra` when not
+// NULL): each workspace buffer grows to the batch's need if that is larger
+// than what the slot holds (exact allocation, so no growth slack), and the
+// launch tables and candidate buffer add at most overhead_bound to what it
+// already holds.  The slot's context budget is set to this figure, so its
+// allocations cannot exceed it.
+uint64_t slot_commit(const dog_server* sv, const Slot* sl, const std::vector<Request>& reqs,
+                     const Request* extra)
 {
-    const uint64_t pitch = ((uint64_t)H + 63) / 64 * 64;
-    return 2ull * (uint64_t)n_g * (uint64_t)W * pitch * sizeof(float) +
-           (on_device ? 0 : (uint64_t)H * (uint64_t)W * sizeof(float)) + 4096;
+    uint64_t planes = 0, input = 0;
+    std::vector<int64_t> hs, ws;
+    auto add = [&](const Request& r) {
+        planes += dog::frame_plane_bytes(sv->plan, r.H, r.W);
+        if (!r.on_device)
+            input += dog::frame_input_bytes(r.H, r.W);
+        hs.push_back(r.H);
+        ws.push_back(r.W);
+    };
+    for (const Request& r : reqs)
+        add(r);
+    if (extra)
+        add(*extra);
+    if (hs.empty())
+        return sl->held();
+    return std::max(sl->planes_b, page(planes)) + std::max(sl->input_b, page(input)) + sl->other_b +
+           dog::overhead_bound(sv->plan, (int)hs.size(), hs.data(), ws.data());
+}
+
+uint64_t sum_commits(const dog_server* sv, const Slot* except)
+{
+    uint64_t t = 0;
+    for (const auto& s : sv->slots)
+        if (s.get() != except)
+            t += s->commit;
+    return t;
 }
 
 void release_request(dog_server* sv, Request& r)
@@ -171,6 +211,8 @@ void run_slot(dog_server* sv, Slot* sl)
             if (!sl->has_work)
                 return;
             batch.swap(sl->batch);
+            if (sl->ctx)
+                sl->ctx->budget = sl->commit;  // allocations stay within the commit
         }
         const int n = (int)batch.size();
         std::vector<dog_result> res(n);
@@ -198,7 +240,6 @@ void run_slot(dog_server* sv, Slot* sl)
         for (Request& r : batch)  // uploads have completed: results were read back
             release_request(sv, r);
         const int64_t t_done = now_ns();
-        uint64_t freed = 0;
         {
             std::lock_guard<std::mutex> lk(sv->mu);
             for (int i = 0; i < n; ++i) {
@@ -215,9 +256,18 @@ void run_slot(dog_server* sv, Slot* sl)
                 }
                 sv->pending.erase(batch[i].ticket);
                 sv->done[batch[i].ticket] = r;
-                freed += batch[i].footprint;
             }
-            sv->reserved -= freed;
+            if (sl->ctx) {
+                sl->planes_b = sl->ctx->planes.bytes;
+                sl->input_b = sl->ctx->input.bytes;
+                sl->other_b = sl->ctx->used - sl->planes_b - sl->input_b;
+            }
+            sl->commit = sl->held();
+            sv->reserved = sum_commits(sv, nullptr);
+            uint64_t held = 0;
+            for (const auto& o : sv->slots)
+                held += o->held();
+            sv->peak_held = std::max(sv->peak_held, held);
             sv->running -= n;
             sv->t_last = std::max(sv->t_last, t_done);
             sl->has_work = false;
@@ -246,11 +296,11 @@ void run_dispatcher(dog_server* sv)
         });
         if (sv->stop)
             return;
+        // the idle slot holding the most device memory: a batch that fits in
+        // its buffers adds nothing to what the slots hold
         for (auto& s : sv->slots)
-            if (!s->has_work) {
+            if (!s->has_work && (!idle || s->held() > idle->held()))
                 idle = s.get();
-                break;
-            }
         // batching window: give a short batch a chance to grow
         if (sv->opts.max_wait_ms > 0.0 && (int)sv->queue.size() < sv->opts.max_batch_frames) {
             const int64_t deadline =
@@ -261,28 +311,57 @@ void run_dispatcher(dog_server* sv)
                 continue;
             }
         }
+        // admission: the other slots' commits (what idle slots hold, the
+        // bounds of running batches) plus this slot's bound for the batch
+        // must stay within the budget
+        const uint64_t others = sum_commits(sv, idle);
         std::vector<Request> batch;
-        uint64_t fp = 0;
+        uint64_t commit = idle->held();
         int64_t px = 0;
         while (!sv->queue.empty() && (int)batch.size() < sv->opts.max_batch_frames) {
             const Request& r = sv->queue.front();
-            if (sv->reserved + fp + r.footprint > sv->budget)
-                break;  // admission: wait until running batches free memory
+            const uint64_t c = slot_commit(sv, idle, batch, &r);
+            if (others + c > sv->budget)
+                break;  // wait until memory is released
             const int64_t rpx = (int64_t)r.H * (int64_t)r.W;
             if (!batch.empty() && sv->opts.max_batch_pixels > 0 &&
                 px + rpx > sv->opts.max_batch_pixels)
                 break;  // the batch's planes would outgrow the cache
             px += rpx;
-            fp += r.footprint;
+            commit = c;
             batch.push_back(std::move(sv->queue.front()));
             sv->queue.pop_front();
         }
         if (batch.empty()) {
-            // the oldest request does not fit while other batches run
-            sv->cv_done.wait(lk);
+            // the oldest request does not fit.  Idle slots keep their
+            // workspaces between batches: release them, other slots first,
+            // then this one; otherwise wait for a running batch to finish
+            const Request& r = sv->queue.front();
+            std::vector<Slot*> idle_held;
+            for (auto& s : sv->slots)
+                if (!s->has_work && s.get() != idle && s->held() > 0)
+                    idle_held.push_back(s.get());
+            std::sort(idle_held.begin(), idle_held.end(),
+                      [](const Slot* a, const Slot* b) { return a->held() > b->held(); });
+            if (idle->held() > 0)
+                idle_held.push_back(idle);
+            bool trimmed = false;
+            for (Slot* s : idle_held) {
+                if (sum_commits(sv, idle) + slot_commit(sv, idle, {}, &r) <= sv->budget)
+                    break;
+                if (s->ctx)
+                    (void)dog::ctx_trim(s->ctx);
+                s->planes_b = s->input_b = s->other_b = 0;
+                s->commit = 0;
+                trimmed = true;
+            }
+            sv->reserved = sum_commits(sv, nullptr);
+            if (!trimmed)
+                sv->cv_done.wait(lk);
             continue;
         }
-        sv->reserved += fp;
+        idle->commit = commit;
+        sv->reserved = sum_commits(sv, nullptr);
         sv->peak_reserved = std::max(sv->peak_reserved, sv->reserved);
         sv->running += (int64_t)batch.size();
         sv->batches += 1;
@@ -361,15 +440,20 @@ int dog_server_create(int device, const dog_params* params, const dog_server_opt
         return DOG_EINVAL;
     }
     sv->n_g = P.n_g;
+    sv->plan = P;
     sv->budget = sv->opts.hbm_budget_bytes;
     if (!sv->opts.dry_run) {
         for (int i = 0; i < sv->opts.slots; ++i) {
             auto sl = std::make_unique<Slot>();
             rc = dog_context_create(device, sv->budget, &sl->ctx);
             // slots already run batches side by side: each batch is one
-            // launch sequence, not split again over lanes of its own
-            if (rc == DOG_OK)
+            // launch sequence, not split again over lanes of its own; every
+            // byte a slot allocates is committed by admission
+            if (rc == DOG_OK) {
                 sl->ctx->group_pixels = 0;
+                sl->ctx->exact_alloc = true;
+                sl->ctx->room_margin = 0;
+            }
             if (rc == DOG_OK && sv->opts.tune_cache) {
                 rc = dog_autotune_load(sl->ctx, sv->opts.tune_cache);
                 if (rc != DOG_OK)
@@ -384,6 +468,8 @@ int dog_server_create(int device, const dog_params* params, const dog_server_opt
         }
         if (sv->budget == 0)
             sv->budget = sv->slots[0]->ctx->budget;
+        for (auto& s : sv->slots)
+            s->ctx->budget = 0;  // nothing is allocated before admission
     } else {
         for (int i = 0; i < sv->opts.slots; ++i)
             sv->slots.push_back(std::make_unique<Slot>());
@@ -419,7 +505,10 @@ int dog_server_submit(dog_server* sv, const dog_frame* frame, uint64_t* ticket)
     r.H = frame->height;
     r.W = frame->width;
     r.on_device = frame->on_device == 1;
-    r.footprint = frame_footprint(sv->n_g, r.H, r.W, r.on_device);
+    {
+        Slot empty;
+        r.footprint = slot_commit(sv, &empty, {}, &r);  // the frame alone on a fresh slot
+    }
     if (r.footprint > sv->budget) {
         std::lock_guard<std::mutex> lk(sv->mu);
         sv->rejected += 1;
@@ -540,6 +629,9 @@ int dog_server_stats(dog_server* sv, dog_stats* out)
     out->mean_batch_frames = sv->batches ? (double)sv->batch_frames / (double)sv->batches : 0.0;
     out->reserved_bytes = sv->reserved;
     out->peak_reserved_bytes = sv->peak_reserved;
+    for (const auto& s : sv->slots)
+        out->held_bytes += s->held();
+    out->peak_held_bytes = sv->peak_held;
     if (!sv->lat_ms.empty()) {
         std::vector<double> v = sv->lat_ms;
         std::sort(v.begin(), v.end());

@@ -7,7 +7,14 @@ Planes (relative 1e-5, scaled so the bound holds where the value is near 0):
 Blob lists: identical, except a voxel may appear on one side only when the
 oracle's FP64 cube puts it within delta_i = 2e-5 * sigma_i * max|I| of a tie
 with its largest neighbour or of the threshold (a decision fp32 cannot take
-the same way as FP64 there).
+the same way as FP64 there).  On frames of natural shape such voxels must
+stay rare (MAX_EXEMPT_FRACTION of the candidates).
+
+Margin-free check: on the GPU's own fp32 DoG cube the local-maximum decision
+has a single right answer.  Widening fp32 to FP64 keeps equality and order,
+and the kernel compares with the largest float <= threshold, so the oracle's
+local-maximum search run on that cube must return exactly the GPU's
+candidates, with their responses bit for bit.
 """
 from __future__ import annotations
 
@@ -17,6 +24,27 @@ import oracle
 
 PLANE_RTOL = 1e-5
 MARGIN = 2e-5
+MAX_EXEMPT_FRACTION = 0.01
+
+
+def check_candidates_exact(gpu_raw, D_gpu, thr):
+    """gpu_raw: the GPU's candidates (sorted by y, x, scale); D_gpu: the same
+    kernels' fp32 DoG cube (k, H, W).  No exemptions."""
+    D = np.asarray(D_gpu, np.float32).astype(np.float64)
+    yxi, resp = oracle.nms(D, thr)
+    got = np.stack([np.asarray(gpu_raw["y"]), np.asarray(gpu_raw["x"]),
+                    np.asarray(gpu_raw["scale"])], 1).astype(np.int64)
+    assert got.shape == yxi.shape, "GPU %d candidates, oracle on the GPU cube %d" % (
+        len(got), len(yxi))
+    assert np.array_equal(got, yxi.astype(np.int64)), "candidate sets differ"
+    assert np.array_equal(np.asarray(gpu_raw["response"], np.float64), resp), "responses differ"
+    return len(yxi)
+
+
+def check_exempt_bound(exempt, n_raw):
+    """Near-tie exemptions on a frame of natural shape: at most 1 %."""
+    assert exempt <= MAX_EXEMPT_FRACTION * max(n_raw, 1), "%d of %d candidates exempt" % (
+        exempt, n_raw)
 
 
 def check_planes(L_gpu, D_gpu, L_orc, D_orc, sigmas, max_abs):

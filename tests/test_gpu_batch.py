@@ -71,9 +71,10 @@ def test_server_device_frames_and_tight_budget(dog, torch_mod):
     with dog.Context(0) as c:
         ref = [c.detect_device(torch_mod.from_numpy(f).cuda(), prm) for f in frames]
     dev = [torch_mod.from_numpy(f).cuda() for f in frames]
-    # admission footprint of a 1024x1024 frame with 9 Gaussian planes (host
-    # frames add their upload buffer); the budget admits two at a time
-    fp_host = (2 * 9 * 1024 * 1024 + 1024 * 1024) * 4 + 4096
+    # device footprint of a 1024x1024 host frame with 9 Gaussian planes
+    # (planes, upload buffer, tables, candidates); the budget admits two at a
+    # time, and idle slots give their workspaces back when a third would not fit
+    fp_host = dog.footprint(prm, [(1024, 1024)])
     budget = int(2.5 * fp_host)
     sv = dog.Server(prm, slots=2, max_batch_frames=4, hbm_budget_bytes=budget)
     try:
@@ -85,6 +86,9 @@ def test_server_device_frames_and_tight_budget(dog, torch_mod):
         st = sv.stats()
         assert st["completed"] == len(tickets)
         assert 0 < st["peak_reserved_bytes"] <= budget
+        # what the slots' workspaces really hold stays within the budget too
+        assert 0 < st["peak_held_bytes"] <= budget
+        assert st["held_bytes"] <= budget
     finally:
         sv.close()
 

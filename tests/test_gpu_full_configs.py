@@ -9,7 +9,8 @@ import pytest
 
 import oracle
 import synth
-from parity import check_candidates, check_pruned
+from parity import (check_candidates, check_candidates_exact, check_exempt_bound, check_planes,
+                    check_pruned)
 
 pytestmark = pytest.mark.gpu
 
@@ -29,11 +30,23 @@ def dog():
     return d
 
 
-def _oracle_check(c, t, img, prm):
+def _oracle_check(c, t, img, prm, natural=True, planes=False):
+    """Candidates against the oracle's FP64 cube (near-tie exemptions bounded
+    on frames of natural shape) and, with no margin at all, against the
+    oracle's local-maximum search on the GPU's own fp32 cube; optionally the
+    planes themselves."""
     L_o, D_o, sig = oracle.planes(img, prm.sigma_min, prm.sigma_max, prm.sigma_ratio, 4.0)
     max_abs = float(np.abs(img).max())
+    L_g, D_g = c.debug_planes(t, prm)
+    D_g = D_g.cpu().numpy()
+    if planes:
+        check_planes(L_g.cpu().numpy(), D_g, L_o, D_o, sig, max_abs)
+    del L_g
     raw = c.debug_candidates(t, prm)
+    check_candidates_exact(raw, D_g, prm.threshold)
     exempt = check_candidates(raw, D_o, prm.threshold, sig, max_abs)
+    if natural:
+        check_exempt_bound(exempt, len(raw))
     return raw, D_o, sig, exempt
 
 
@@ -126,9 +139,10 @@ def test_large_and_extreme_frames(dog, torch_mod, H, W, n_blobs):
     print("frame %d x %d" % (H, W), flush=True)
     img = synth.camera_frame(seed=H + W, H=H, W=W, n_blobs=n_blobs)
     t = torch.from_numpy(img).cuda()
+    natural = H == W
     with dog.Context(0) as c:
         blobs = c.detect_device(t, prm)
-        raw, D_o, sig, exempt = _oracle_check(c, t, img, prm)
+        raw, D_o, sig, exempt = _oracle_check(c, t, img, prm, natural=natural, planes=not natural)
     check_pruned(blobs, raw, D_o, prm.threshold, sig, prm.overlap, exempt)
     print("frame %d x %d: raw %d pruned %d exempt %d" % (H, W, len(raw), len(blobs), exempt), flush=True)
     assert len(blobs) > 0

@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import synth
-from parity import check_candidates, check_planes
+from parity import check_candidates, check_candidates_exact, check_exempt_bound, check_planes
 
 pytestmark = pytest.mark.gpu
 
@@ -26,7 +26,7 @@ def dog():
     return d
 
 
-def _parity(dog, torch, img, prm):
+def _parity(dog, torch, img, prm, natural=False):
     t = torch.from_numpy(np.ascontiguousarray(img)).cuda()
     sig = oracle.sigmas_arithmetic(prm.sigma_min, prm.sigma_max, prm.n_bin)
     L_o, D_o = oracle.planes_sigmas(img, sig, prm.truncate)
@@ -34,9 +34,13 @@ def _parity(dog, torch, img, prm):
     with dog.Context(0) as c:
         L_g, D_g = c.debug_planes(t, prm)
         torch.cuda.synchronize()
-        check_planes(L_g.cpu().numpy(), D_g.cpu().numpy(), L_o, D_o, sig, max_abs)
+        D_g = D_g.cpu().numpy()
+        check_planes(L_g.cpu().numpy(), D_g, L_o, D_o, sig, max_abs)
         raw = c.debug_candidates(t, prm)
+        check_candidates_exact(raw, D_g, prm.threshold)
         exempt = check_candidates(raw, D_o, prm.threshold, sig, max_abs)
+        if natural:
+            check_exempt_bound(exempt, len(raw))
         blobs = c.detect_device(t, prm)
     # coalescing of the oracle's own list (or, with voxels in the decision
     # margin, of the GPU's raw list) must give the same blobs and sigmas
@@ -85,3 +89,14 @@ def test_paper_ladder_pruning_mode_and_variants(dog, torch_mod):
             assert L.cpu().numpy().tobytes() == L0.tobytes(), v
     sig = oracle.sigmas_arithmetic(1.0, 30.0, 10)
     assert np.all(ref["sigma"] == sig[ref["scale"]].astype(np.float32))
+
+
+def test_paper_configuration_at_the_benchmark_size(dog, torch_mod):
+    # the configuration the benchmark times: 1024x1024 camera frame, Eq. 1
+    # ladder with n_bin = 10 over 1..30 (11 planes, radius up to 150),
+    # truncate 5, coalescing, threshold 0.05
+    prm = dog.Params.paper(1.0, 30.0, 10, threshold=0.05)
+    img = synth.camera_frame(seed=1)
+    raw, blobs, exempt = _parity(dog, torch_mod, img, prm, natural=True)
+    print("paper configuration 1024^2: raw %d coalesced %d exempt %d" % (len(raw), len(blobs), exempt))
+    assert len(blobs) >= 100

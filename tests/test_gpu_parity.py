@@ -11,7 +11,8 @@ import pytest
 
 import oracle
 import synth
-from parity import check_candidates, check_planes, check_pruned
+from parity import (check_candidates, check_candidates_exact, check_exempt_bound, check_planes,
+                    check_pruned)
 
 pytestmark = pytest.mark.gpu
 
@@ -43,17 +44,21 @@ def _dev(torch, img):
     return torch.from_numpy(np.ascontiguousarray(img)).cuda()
 
 
-def _full_parity(dog, ctx, torch, img, prm_kw, check_plane=True):
+def _full_parity(dog, ctx, torch, img, prm_kw, check_plane=True, natural=False):
     prm = dog.Params(**prm_kw)
     t = _dev(torch, img)
     L_o, D_o, sig = oracle.planes(img, prm.sigma_min, prm.sigma_max, prm.sigma_ratio, 4.0)
     max_abs = float(np.abs(img).max())
+    L_g, D_g = ctx.debug_planes(t, prm)
+    torch.cuda.synchronize()
+    D_g = D_g.cpu().numpy()
     if check_plane:
-        L_g, D_g = ctx.debug_planes(t, prm)
-        torch.cuda.synchronize()
-        check_planes(L_g.cpu().numpy(), D_g.cpu().numpy(), L_o, D_o, sig, max_abs)
+        check_planes(L_g.cpu().numpy(), D_g, L_o, D_o, sig, max_abs)
     raw = ctx.debug_candidates(t, prm)
+    check_candidates_exact(raw, D_g, prm.threshold)
     exempt = check_candidates(raw, D_o, prm.threshold, sig, max_abs)
+    if natural:
+        check_exempt_bound(exempt, len(raw))
     pruned = ctx.detect_device(t, prm)
     check_pruned(pruned, raw, D_o, prm.threshold, sig, prm.overlap, exempt)
     return raw, pruned, exempt
@@ -61,14 +66,14 @@ def _full_parity(dog, ctx, torch, img, prm_kw, check_plane=True):
 
 def test_small_frame_parity(dog, ctx, torch_mod):
     img = synth.small_frame(seed=0)
-    raw, pruned, exempt = _full_parity(dog, ctx, torch_mod, img, SMALL)
+    raw, pruned, exempt = _full_parity(dog, ctx, torch_mod, img, SMALL, natural=True)
     print("small: raw %d pruned %d exempt %d" % (len(raw), len(pruned), exempt))
     assert len(pruned) >= 10
 
 
 def test_camera_frame_parity_full_size(dog, ctx, torch_mod):
     img = synth.camera_frame(seed=1)
-    raw, pruned, exempt = _full_parity(dog, ctx, torch_mod, img, CAMERA)
+    raw, pruned, exempt = _full_parity(dog, ctx, torch_mod, img, CAMERA, natural=True)
     print("camera 1024^2: raw %d pruned %d exempt %d" % (len(raw), len(pruned), exempt))
     assert len(pruned) >= 100
 
@@ -118,6 +123,26 @@ def test_candidate_overflow_all_ties(dog, ctx, torch_mod):
     assert np.all(raw["response"] == 0)
     # and a normal frame right after still matches
     test_small_frame_parity(dog, ctx, torch)
+
+
+def test_overflow_of_one_tile_below_capacity(dog, torch_mod):
+    # a 64x64 zero frame with a negative threshold: 20,480 tied candidates,
+    # below the initial capacity of a new context but far above what one
+    # workgroup's LDS buffer holds, so most records take the direct path to
+    # the global list; every one must reach the host list
+    torch = torch_mod
+    img = np.zeros((64, 64), np.float32)
+    prm = dog.Params(1, 8, 1.6, -1.0, 1.0)
+    with dog.Context(0) as c:
+        for _ in range(2):   # the second call reads back a larger first slice
+            raw = c.debug_candidates(_dev(torch, img), prm)
+            assert len(raw) == 64 * 64 * 5
+            exp, _ = oracle.nms(np.zeros((5, 64, 64)), -1.0)
+            got = np.stack([raw["y"], raw["x"], raw["scale"]], 1)
+            assert np.array_equal(got, exp)
+            assert np.all(raw["response"] == 0)
+            blobs = c.detect_device(_dev(torch, img), prm)   # overlap 1: no pruning
+            assert blobs.tobytes() == raw.tobytes()
 
 
 def test_repeat_runs_bitwise_identical(dog, ctx, torch_mod):

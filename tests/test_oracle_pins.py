@@ -417,3 +417,37 @@ def test_r12_radius_histogram():
     # beyond the ends: the end bins
     assert oracle.radius_histogram(lad, [0.1, 50.0]).tolist() == [1, 0, 1]
     assert oracle.radius_histogram(lad, []).tolist() == [0, 0, 0]
+
+
+# ------------------------------------------------- the one-call C detector
+# orc_detect composes ladder, planes, local maxima, threshold and pruning a
+# second time inside the C oracle (it is what the CPU baseline times).  It
+# must return exactly what the composition of the pinned pieces above
+# returns: same (y, x, scale) triples, same sigma and response bits.
+def _one_call_equals_composition(img, smin, smax, thr, overlap):
+    comp = oracle.detect(img, smin, smax, 1.6, threshold=thr, overlap=overlap)
+    one = oracle.detect_c(img, smin, smax, 1.6, threshold=thr, overlap=overlap)
+    assert len(one) == len(comp)
+    for f in ("y", "x", "scale"):
+        assert np.array_equal(one[f], comp[f]), f
+    assert one["sigma"].tobytes() == comp["sigma"].tobytes()
+    assert one["response"].tobytes() == comp["response"].tobytes()
+    return len(one)
+
+
+@pytest.mark.parametrize("case", ["small", "ragged"])
+def test_one_call_detector_equals_composition_small(case):
+    if case == "small":
+        img = synth.small_frame(seed=0)                      # 256x256, ladder 1..8
+        n = _one_call_equals_composition(img, 1.0, 8.0, 0.1, 0.5)
+    else:
+        img = synth.small_frame(seed=7, H=97, W=131, n_blobs=9)
+        n = _one_call_equals_composition(img, 1.0, 8.0, 0.1, 0.5)
+    assert n > 0
+
+
+@pytest.mark.parametrize("overlap", [0.5, 1.0])
+def test_one_call_detector_equals_composition_camera_frame(overlap):
+    img = synth.camera_frame(seed=1)                         # 1024x1024, ladder 1..30
+    n = _one_call_equals_composition(img, 1.0, 30.0, 0.05, overlap)
+    assert n > 100
