@@ -29,7 +29,12 @@ Also printed in the same JSON line:
     truncate 5, coalescing) on the same frame;
   * preprocessing (smoothing + 0.35 % contrast stretch) of the frame's raw
     counts alone and in front of the detector;
-  * the FP64 CPU oracle timed on this host on a bounded sample.
+  * overlap pruning and the radius histogram of the frame's candidates on
+    the device against the host step;
+  * the server fed by the same stream under an admission budget of 2.5
+    footprints of the largest frame, so admission binds;
+  * the FP64 CPU oracle timed on this host on a bounded sample, on one
+    thread and on every core.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-batch] [--no-mixed]
                     [--no-serve] [--no-paper] [--serve-seconds S] [--no-cpu] [--variant V]
@@ -116,22 +121,84 @@ def generate_inputs(want_batch: bool, want_mixed: bool, workers: int):
     return frames[:nb], frames[nb:]
 
 
-def cpu_baseline(img, prm, k, budget_s=12.0):
+def cpu_model() -> str:
+    """Model name of the host CPU (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(img, prm, k, budget_s=10.0):
+    """The FP64 C oracle on the same frame: once on one thread, then repeated
+    on every core this process may use (OpenMP over rows), for about
+    budget_s seconds."""
     import oracle
     oracle.build()
-    n_threads = oracle.get_threads()
-    reps, t_total = 0, 0.0
-    while t_total < budget_s and reps < 50:
+    cores = len(os.sched_getaffinity(0))
+    H, W = img.shape
+
+    def run():
         t0 = time.perf_counter()
         oracle.detect_c(img, prm.sigma_min, prm.sigma_max, prm.sigma_ratio, prm.threshold,
                         prm.overlap, 4.0)
-        t_total += time.perf_counter() - t0
+        return time.perf_counter() - t0
+
+    oracle.set_threads(1)
+    t_one = run()
+    oracle.set_threads(cores)
+    n_threads = oracle.get_threads()
+    reps, t_total = 0, 0.0
+    while t_total < budget_s and reps < 50:
+        t_total += run()
         reps += 1
-    H, W = img.shape
-    return {"value": round(H * W * k * reps / t_total / 1e6, 3), "unit": "Mpixel-scales/s",
-            "cores": n_threads, "kind": "oracle",
-            "sample": "%d full run(s) of the FP64 C oracle (OpenMP over rows) on the same "
-                      "1024x1024 frame, %.1f s total" % (reps, t_total)}
+    per = t_total / reps
+    return {"value": round(H * W * k / per / 1e6, 3), "unit": "Mpixel-scales/s",
+            "cores": n_threads, "kind": "oracle", "cpu_model": cpu_model(),
+            "all_cores_s_per_frame": round(per, 3),
+            "single_thread_s_per_frame": round(t_one, 3),
+            "single_thread_mpx_scales_per_s": round(H * W * k / t_one / 1e6, 3),
+            "sample": "the FP64 C oracle (ladder, planes, local maxima, pruning) on the same "
+                      "1024x1024 frame: 1 run on one thread (%.1f s), then %d runs on %d threads "
+                      "(%.1f s)" % (t_one, reps, n_threads, t_total)}
+
+
+def bench_prune(dog, torch, ctx, t_img, prm, reps=50):
+    """Overlap pruning and the radius histogram of the frame's candidates: on
+    the device (dog_prune_device, the list already in HBM) against the host
+    step (dog_prune, the list in host memory), same result."""
+    raw = ctx.debug_candidates(t_img, prm)
+    d = torch.from_numpy(raw.view("u1").reshape(-1).copy()).cuda()
+    out = {"candidates": int(len(raw))}
+    import dataclasses
+    for name, par in (("prune", prm), ("coalesce", dataclasses.replace(prm, coalesce=True))):
+        ref = dog.prune(par, raw)
+        got, _ = ctx.prune_device(d, par)
+        assert got.tobytes() == ref.tobytes()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.prune_device(d, par)
+        t_dev = (time.perf_counter() - t0) / reps
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            dog.prune(par, raw)
+            dog.radius_histogram(par, ref)
+        t_host = (time.perf_counter() - t0) / reps
+        out[name] = {"kept": int(len(ref)), "device_call_us": round(t_dev * 1e6, 1),
+                     "host_call_us": round(t_host * 1e6, 1)}
+    return out
 
 
 def bench_mixed(dog, torch, ctx, prm, k, frames, steps):
@@ -312,12 +379,13 @@ def bench_preprocess(dog, torch, img, prm, k, steps, nf):
             c.close()
 
 
-def bench_serving(dog, prm, k, pool, rate, seconds):
+def bench_serving(dog, prm, k, pool, rate, seconds, budget=0):
     """The server fed by a Poisson stream: frames drawn in turn from the pool
-    of uneven frames, submitted at their arrival times."""
+    of uneven frames, submitted at their arrival times.  budget: the
+    admission budget in bytes (0: the server's default)."""
     import synth
     arrivals = synth.poisson_arrivals(rate=rate, duration=seconds)
-    sv = dog.Server(prm, max_batch_frames=16)
+    sv = dog.Server(prm, max_batch_frames=16, hbm_budget_bytes=budget)
     try:
         for f in pool[:8]:
             sv.wait(sv.submit(f))
@@ -346,7 +414,11 @@ def bench_serving(dog, prm, k, pool, rate, seconds):
             "sustained_fps": round(len(arrivals) / wall, 1),
             "mpx_scales_per_s": round(mpx / wall, 1),
             "batches": st["batches"] - base["batches"],
-            "peak_reserved_gib": round(st["peak_reserved_bytes"] / 2**30, 3)}
+            "mean_batch_frames": round(len(arrivals) / max(1, st["batches"] - base["batches"]), 2),
+            "budget_gib": round(budget / 2**30, 3) if budget else "default (90% of free HBM)",
+            "peak_reserved_gib": round(st["peak_reserved_bytes"] / 2**30, 3),
+            "peak_held_gib": round(st["peak_held_bytes"] / 2**30, 3),
+            "admission_waits": st["admission_waits"] - base["admission_waits"]}
 
 
 def main() -> int:
@@ -362,7 +434,9 @@ def main() -> int:
     ap.add_argument("--only", choices=("paper", "preprocess"), default=None,
                     help="run only the paper-configuration or the preprocessing section "
                          "(for a profile of its kernels) and print its JSON")
-    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--tight-serve-seconds", type=float, default=10.0,
+                    help="length of the serving leg whose admission budget binds")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--variant", type=int, default=-1)
@@ -552,6 +626,7 @@ def main() -> int:
            "blobs": int(len(blobs)),
            "autotune": tune}
 
+    out["prune"] = bench_prune(dog, torch, ctx, t_img, prm)
     if not args.no_paper:
         out["paper_config"] = bench_paper_config(dog, torch, t_img, args.steps, nf)
         out["preprocess"] = bench_preprocess(dog, torch, img, prm, k, args.steps, nf)
@@ -606,6 +681,12 @@ def main() -> int:
     if not args.no_serve:
         out["serving"] = bench_serving(dog, prm, k, mixed_frames, args.serve_rate,
                                        args.serve_seconds)
+        # the same stream under a budget of 2.5 footprints of the largest
+        # frame of the pool, so admission by HBM footprint binds
+        big = max(mixed_frames, key=lambda f: f.size)
+        budget = int(2.5 * dog.footprint(prm, [big.shape]))
+        out["serving_tight_budget"] = bench_serving(dog, prm, k, mixed_frames, args.serve_rate,
+                                                    args.tight_serve_seconds, budget)
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(img, prm, k)

@@ -143,6 +143,28 @@ void dog_blobs_free(dog_blob* blobs);
  * count. */
 int dog_prune(const dog_params* params, dog_blob* blobs, int64_t n, int64_t* n_out);
 
+/* The overlap step and the radius histogram on the GPU (Sec. 4.1: pruning
+ * or coalescing overlapping blobs and histogramming their radii, steps the
+ * paper notes could move to the GPU).  d_blobs: n blobs in DEVICE memory on
+ * the context's GPU, in any order (their sigma field is ignored; each blob
+ * takes the FP64 ladder sigma of its scale index under `params`).  One
+ * workgroup sorts them by (y, x, scale) and prunes exactly as dog_prune
+ * does (the same visits in the same order, coalescing when
+ * params->coalesce is 1), then histograms the survivors as
+ * dog_radius_histogram does.  *blobs_out receives the survivors (malloc'd,
+ * sorted, sigma = ladder sigma or coalesced mean), *count_out their number,
+ * hist_out (host, k int64, may be NULL) the histogram.  Work is queued on
+ * `stream` after what is already there; the call returns when the results
+ * are on the host.  A list of more blobs (or touching pairs) than one
+ * workgroup holds (4096 blobs and 8192 pairs where a workgroup may use
+ * 128 KB of LDS) is pruned by the same steps on the host, with the same
+ * result.  Errors: DOG_EINVAL (NULL pointers, bad parameters, a blob with
+ * y or x outside [0, 32768) or a scale outside the ladder), DOG_EBUSY,
+ * device errors. */
+int dog_prune_device(dog_context* ctx, const dog_params* params, const dog_blob* d_blobs,
+                     int64_t n, void* stream, dog_blob** blobs_out, int64_t* count_out,
+                     int64_t* hist_out);
+
 /* Radius histogram (Sec. 4.1: blobs are histogrammed with bin centres at
  * the detectable radii sqrt(2) sigma_i of the ladder's k DoG scales):
  * counts_out[0..k) receives, for each scale, the number of blobs[0..n)
@@ -318,6 +340,22 @@ int dog_set_graph_mode(dog_context* ctx, int32_t on);
  * timed), with the same kernels and arguments. */
 int dog_set_profiling(dog_context* ctx, int32_t on);
 int dog_kernel_times(dog_context* ctx, double* ms_out, int64_t* launches_out);
+/* The same for every kernel of a sequence (cap >= 7): pass 1, pass 2, local
+ * maxima, then the transform-domain blur's forward 1, forward 2, inverse 1
+ * and inverse 2 (0 where the sequences had no such work). */
+int dog_kernel_times_all(dog_context* ctx, double* ms_out, int32_t cap, int64_t* launches_out);
+
+/* Transform-domain blur (Sec. 4.1, the convolution taken through a fast
+ * Fourier transform, whose cost does not grow with sigma): on frames whose
+ * sides are powers of two in [64, 2048], ladder planes whose kernels have
+ * at least min_taps taps (2 r + 1) are blurred as a product in the type-II
+ * cosine transform domain, which is exact for the half-sample symmetric
+ * border: the frame's 2-D transform is taken once, each such plane costs one
+ * inverse transform (fp32 FFTs of the lines in LDS, FP64 transfer functions
+ * of the kernels rounded once to fp32).  The planes agree with the direct
+ * blur within the detector's plane tolerance, not bit for bit.  min_taps 0
+ * (the default) blurs every plane directly.  DOG_EINVAL for min_taps < 0. */
+int dog_set_dct(dog_context* ctx, int32_t min_taps);
 
 
 /* ------------------------------------------------------------ serving */
@@ -366,6 +404,7 @@ typedef struct {
      * completions. */
     uint64_t reserved_bytes, peak_reserved_bytes;
     uint64_t held_bytes, peak_held_bytes;
+    int64_t admission_waits;   /* times the oldest waiting request did not fit */
 } dog_stats;
 
 /* Create a server on GPU `device` for fixed detector parameters.  A request

@@ -74,7 +74,8 @@ class dog_stats(ctypes.Structure):
                [(n, ctypes.c_double) for n in ("mean_batch_frames", "p50_ms", "p99_ms", "mean_ms",
                                                 "max_ms", "frames_per_s")] + \
                [("reserved_bytes", ctypes.c_uint64), ("peak_reserved_bytes", ctypes.c_uint64),
-                ("held_bytes", ctypes.c_uint64), ("peak_held_bytes", ctypes.c_uint64)]
+                ("held_bytes", ctypes.c_uint64), ("peak_held_bytes", ctypes.c_uint64),
+                ("admission_waits", ctypes.c_int64)]
 
 
 @dataclass
@@ -152,6 +153,7 @@ def lib() -> ctypes.CDLL:
                                 ctypes.POINTER(dbl), ctypes.POINTER(i32), i32]),
         "dog_prune": (i32, [ctypes.POINTER(dog_params), vp, i64, pi64]),
         "dog_radius_histogram": (i32, [ctypes.POINTER(dog_params), vp, i64, pi64]),
+        "dog_prune_device": (i32, [vp, ctypes.POINTER(dog_params), vp, i64, vp, pblob, pi64, pi64]),
         "dog_server_create": (i32, [ctypes.c_int, ctypes.POINTER(dog_params),
                                     ctypes.POINTER(dog_server_opts), ctypes.POINTER(vp)]),
         "dog_server_submit": (i32, [vp, ctypes.POINTER(dog_frame), ctypes.POINTER(u64)]),
@@ -167,6 +169,8 @@ def lib() -> ctypes.CDLL:
         "dog_set_graph_mode": (ctypes.c_int, [vp, i32]),
         "dog_set_batch_grouping": (ctypes.c_int, [vp, i64, i32]),
         "dog_kernel_times": (ctypes.c_int, [vp, ctypes.POINTER(dbl), pi64]),
+        "dog_kernel_times_all": (ctypes.c_int, [vp, ctypes.POINTER(dbl), i32, pi64]),
+        "dog_set_dct": (ctypes.c_int, [vp, i32]),
         "dog_autotune": (i32, [vp, ctypes.POINTER(dog_params), vp, i64, i64, i64, i32,
                                ctypes.POINTER(i32), ctypes.POINTER(dbl)]),
         "dog_autotune_save": (i32, [vp, ctypes.c_char_p]),
@@ -331,6 +335,20 @@ class Context:
         _check(lib().dog_kernel_times(self._h, ms, ctypes.byref(n)))
         return list(ms), n.value
 
+    KERNEL_NAMES = ("pass1", "pass2", "nms", "dct_fwd1", "dct_fwd2", "dct_inv1", "dct_inv2")
+
+    def kernel_times_all(self):
+        """(ms per kernel summed, in KERNEL_NAMES order, number of launch sequences)."""
+        ms = (ctypes.c_double * 7)()
+        n = ctypes.c_int64(0)
+        _check(lib().dog_kernel_times_all(self._h, ms, 7, ctypes.byref(n)))
+        return list(ms), n.value
+
+    def set_dct(self, min_taps: int) -> None:
+        """dog_set_dct: planes whose kernels have at least min_taps taps are
+        blurred in the cosine-transform domain (power-of-two frames); 0 = never."""
+        _check(lib().dog_set_dct(self._h, int(min_taps)))
+
     def detect_device(self, image, params: Params, stream=None) -> np.ndarray:
         ptr, H, W, st = _tensor_image(image)
         p = ctypes.POINTER(dog_blob)()
@@ -387,6 +405,30 @@ class Context:
         _check(lib().dog_debug_candidates(self._h, ptr, H, W, st, ctypes.byref(prm),
                                           ctypes.byref(p), ctypes.byref(n)))
         return _blobs(p, n.value)
+
+    def prune_device(self, blobs, params: Params, stream=None):
+        """dog_prune_device: sort, overlap-prune and histogram a blob list on
+        the GPU.  blobs: a BLOB_DTYPE array (copied to the device first) or a
+        CUDA uint8 tensor holding such records.  Returns (survivors,
+        histogram of k int64)."""
+        import torch
+        if isinstance(blobs, torch.Tensor):
+            d = blobs
+            n = d.numel() // BLOB_DTYPE.itemsize
+        else:
+            b = np.ascontiguousarray(np.array(blobs, dtype=BLOB_DTYPE))
+            n = len(b)
+            d = torch.from_numpy(b.view(np.uint8).reshape(-1)).cuda()
+        k = plan_info(params)["k"]
+        hist = np.zeros(k, np.int64)
+        p = ctypes.POINTER(dog_blob)()
+        cnt = ctypes.c_int64(0)
+        prm = params.c()
+        st = stream.cuda_stream if stream is not None else torch.cuda.current_stream().cuda_stream
+        _check(lib().dog_prune_device(self._h, ctypes.byref(prm), d.data_ptr() if n else None, n,
+                                      st, ctypes.byref(p), ctypes.byref(cnt),
+                                      hist.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return _blobs(p, cnt.value), hist
 
     def debug_planes(self, image, params: Params):
         """(L, D) as CUDA tensors: (k+1, H, W) and (k, H, W) fp32."""

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdog.so")
 
-SOURCES = ["kernels.hip", "preprocess.hip", "plan.cpp", "prune.cpp", "runtime.cpp", "batch.cpp",
+SOURCES = ["kernels.hip", "preprocess.hip", "prune_device.hip", "dct.hip", "plan.cpp", "prune.cpp", "runtime.cpp", "batch.cpp",
            "api.cpp", "server.cpp", "autotune.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -34,7 +34,7 @@ def kernel_hash() -> str:
     """First 16 hex digits of the SHA-256 of the kernel source and its shared
     header; names the kernel build in autotuner caches."""
     h = hashlib.sha256()
-    for name in ("kernels.hip", "dog_internal.h"):
+    for name in ("kernels.hip", "dct.hip", "dct.h", "dog_internal.h"):
         with open(os.path.join(CSRC, name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -8,6 +8,7 @@
 #include <string>
 #include <vector>
 
+#include "prune_device.h"
 #include "runtime.h"
 
 using namespace dog;
@@ -58,10 +59,10 @@ void free_context(dog_context* c)
     (void)hipSetDevice(c->device);
     if (c->stream)
         (void)hipStreamSynchronize(c->stream);
-    for (DevBuf* b : {&c->planes, &c->input, &c->tables, &c->cand, &c->prep})
+    for (DevBuf* b : {&c->planes, &c->input, &c->tables, &c->cand, &c->prep, &c->prn})
         if (b->p)
             (void)hipFree(b->p);
-    for (PinBuf* b : {&c->h_tables, &c->h_cand, &c->h_ends, &c->h_input})
+    for (PinBuf* b : {&c->h_tables, &c->h_cand, &c->h_ends, &c->h_input, &c->h_prn})
         if (b->p)
             (void)hipHostFree(b->p);
     drop_graph(c);
@@ -189,6 +190,33 @@ int dog_set_profiling(dog_context* ctx, int32_t on)
     return DOG_OK;
 }
 
+int dog_set_dct(dog_context* ctx, int32_t min_taps)
+{
+    if (!ctx || min_taps < 0) {
+        set_error("invalid argument");
+        return DOG_EINVAL;
+    }
+    if (ctx->pending)
+        return ctx_idle(ctx);
+    if (ctx->dct_min_taps != min_taps)
+        drop_graph(ctx);
+    ctx->dct_min_taps = min_taps;
+    return DOG_OK;
+}
+
+int dog_kernel_times_all(dog_context* ctx, double* ms_out, int32_t cap, int64_t* launches_out)
+{
+    if (!ctx || !ms_out || cap < DOG_NKERNELS) {
+        set_error("invalid argument (ms_out needs room for 7 kernels)");
+        return DOG_EINVAL;
+    }
+    for (int i = 0; i < DOG_NKERNELS; ++i)
+        ms_out[i] = ctx->kernel_ms[i];
+    if (launches_out)
+        *launches_out = ctx->kernel_launches;
+    return DOG_OK;
+}
+
 int dog_set_batch_grouping(dog_context* ctx, int64_t max_group_pixels, int32_t lanes)
 {
     if (!ctx || max_group_pixels < 0 || lanes < 1 || lanes > 16) {
@@ -256,6 +284,113 @@ int dog_prune(const dog_params* params, dog_blob* blobs, int64_t n, int64_t* n_o
     std::copy(v.begin(), v.end(), blobs);
     *n_out = (int64_t)v.size();
     return DOG_OK;
+}
+
+int dog_prune_device(dog_context* ctx, const dog_params* params, const dog_blob* d_blobs,
+                     int64_t n, void* stream, dog_blob** blobs_out, int64_t* count_out,
+                     int64_t* hist_out)
+{
+    if (!ctx || !params || !blobs_out || !count_out || n < 0 || (n > 0 && !d_blobs)) {
+        set_error("invalid argument");
+        return DOG_EINVAL;
+    }
+    *blobs_out = nullptr;
+    *count_out = 0;
+    int rc = ctx_idle(ctx);
+    if (rc != DOG_OK)
+        return rc;
+    if ((rc = use_device(ctx)) != DOG_OK)
+        return rc;
+    const Plan* P = nullptr;
+    if ((rc = ctx_plan(ctx, params, &P)) != DOG_OK)
+        return rc;
+    const hipStream_t st = pick_stream(ctx, stream);
+    if (ctx->prn_blobs == 0) {
+        // the workgroup's capacity follows the LDS one workgroup may use
+        int lds = 0;
+        DOG_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                                      ctx->device));
+        ctx->prn_blobs = 4096;
+        ctx->prn_pairs = 8192;
+        while (ctx->prn_blobs > 256 &&
+               dogk_prune_lds_bytes(ctx->prn_blobs, ctx->prn_pairs) + 4096 > (size_t)lds) {
+            ctx->prn_blobs /= 2;
+            ctx->prn_pairs /= 2;
+        }
+    }
+    const size_t sig_bytes = sizeof(double) * (size_t)P->n_g;
+    const size_t out_bytes = sizeof(PruneHead) + sizeof(dog_blob) * (size_t)ctx->prn_blobs;
+    if ((rc = ctx_alloc(ctx, &ctx->prn, sig_bytes, "pruning ladder")) != DOG_OK)
+        return rc;
+    // pinned: the ladder's staging, then the kernel's output (written by the
+    // kernel straight into host memory)
+    const size_t head_off = (sig_bytes + 255) & ~(size_t)255;
+    if ((rc = ctx_pin(&ctx->h_prn, head_off + out_bytes)) != DOG_OK)
+        return rc;
+    char* h = static_cast<char*>(ctx->h_prn.p);
+    PruneHead* head = reinterpret_cast<PruneHead*>(h + head_off);
+    std::vector<dog_blob> v;
+    std::vector<int64_t> hist(P->k, 0);
+    bool on_host = n > (int64_t)ctx->prn_blobs;
+    if (!on_host) {
+        DOG_HIP(hipStreamSynchronize(st));   // the staging area is reused
+        std::memcpy(h, P->sigma.data(), sig_bytes);
+        head->status = 0;
+        DOG_HIP(hipMemcpyAsync(ctx->prn.p, h, sig_bytes, hipMemcpyHostToDevice, st));
+        PruneArgs a{};
+        a.cand = nullptr;
+        a.recs = d_blobs;
+        a.cap = (uint32_t)n;
+        a.n_direct = (uint32_t)n;
+        a.sig64 = static_cast<const double*>(ctx->prn.p);
+        a.sig_max = P->sigma[P->k - 1];
+        a.overlap = P->prm.overlap;
+        a.k = P->k;
+        a.coalesce = P->prm.coalesce;
+        a.blob_in = 1;
+        a.max_blobs = ctx->prn_blobs;
+        a.max_pairs = ctx->prn_pairs;
+        a.out = reinterpret_cast<char*>(head);
+        a.out_stride = out_bytes;
+        DOG_HIP(dogk_prune(&a, 1, st));
+        DOG_HIP(hipStreamSynchronize(st));
+        if (head->status == kPruneBadRecord) {
+            set_error("blob outside 0 <= y, x < 32768 or scale outside the ladder");
+            return DOG_EINVAL;
+        }
+        if (head->status == kPruneDone) {
+            const dog_blob* ob = reinterpret_cast<const dog_blob*>(head + 1);
+            v.assign(ob, ob + head->n_out);
+            for (int i = 0; i < P->k; ++i)
+                hist[i] = head->hist[i];
+        } else if (head->status == kPruneTooManyPairs) {
+            on_host = true;
+        } else {
+            set_error("device pruning did not complete");
+            return DOG_EDEVICE;
+        }
+    }
+    if (on_host) {
+        // more than one workgroup holds: the same steps on the host
+        v.resize((size_t)n);
+        DOG_HIP(hipMemcpyAsync(v.data(), d_blobs, sizeof(dog_blob) * (size_t)n,
+                               hipMemcpyDeviceToHost, st));
+        DOG_HIP(hipStreamSynchronize(st));
+        for (dog_blob& b : v) {
+            if (b.scale < 0 || b.scale >= P->k || b.y < 0 || b.y > 32767 || b.x < 0 ||
+                b.x > 32767) {
+                set_error("blob outside 0 <= y, x < 32768 or scale outside the ladder");
+                return DOG_EINVAL;
+            }
+            b.sigma = (float)P->sigma[b.scale];
+        }
+        sort_blobs(v);
+        prune_blobs(v, P->sigma, P->prm.overlap, P->prm.coalesce != 0);
+        radius_histogram(P->sigma, P->k, v.data(), (int64_t)v.size(), hist.data());
+    }
+    if (hist_out)
+        std::copy(hist.begin(), hist.end(), hist_out);
+    return export_blobs(v, blobs_out, count_out);
 }
 
 int dog_radius_histogram(const dog_params* params, const dog_blob* blobs, int64_t n,

@@ -133,8 +133,10 @@ int dog_autotune(dog_context* ctx, const dog_params* params, const float* d_imag
             rc = run_frames(ctx, plan, fr, ctx->stream, &out, false, nullptr, nullptr, nullptr);
         if (rc != DOG_OK)
             break;
-        const double us = (ctx->kernel_ms[0] + ctx->kernel_ms[1] + ctx->kernel_ms[2]) * 1e3 /
-                          (double)std::max<int64_t>(1, ctx->kernel_launches);
+        double ms = 0.0;
+        for (double m : ctx->kernel_ms)
+            ms += m;
+        const double us = ms * 1e3 / (double)std::max<int64_t>(1, ctx->kernel_launches);
         times[v] = us;
         if (us_out)
             us_out[v] = us;

@@ -113,6 +113,7 @@ static int run_grouped(dog_context* ctx, const Plan& P, const std::vector<FrameI
         dog_context* l = ctx->lanes[k];
         l->tuned = ctx->tuned;
         l->use_graphs = ctx->use_graphs;
+        l->dct_min_taps = ctx->dct_min_taps;
         if (ctx->variant_forced) {
             int rc = ctx_set_variant(l, ctx->variant);
             if (rc != DOG_OK)

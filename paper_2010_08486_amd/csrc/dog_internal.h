@@ -101,4 +101,12 @@ struct LaunchArgs {
     FrameDesc f0;               // the frame of a one-frame launch (frames == NULL)
 };
 
+// The transform-domain blur's four launches of a sequence: job tables
+// (device) and counts, and the dynamic LDS the largest job of each needs.
+struct DctLaunch {
+    const void* jobs[4];        // forward 1, forward 2, inverse 1, inverse 2
+    int n[4];
+    size_t lds[4];
+};
+
 }  // namespace dog

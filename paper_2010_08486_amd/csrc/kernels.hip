@@ -850,33 +850,50 @@ void dogk_variant_geometry(int v, int* S, int* NW, int* BI, int* BN, int* NWN)
 
 int dogk_variant_ring(int v) { return dog::kSets[v].R; }
 
-// Launch pass 1, pass 2 and the local-maximum kernel on `stream`, one
-// workgroup per tile of each table.  wide1: every frame's rows are 16-byte
-// aligned and its width is a multiple of 64, so pass 1 may use 16-byte loads.
-// If ev is non-NULL, ev[2i] and ev[2i+1] take the start and end of kernel i's
-// execution (the dispatch's own timestamps, so the launch gap before a kernel
-// is not counted).  Returns the first launch error.
-hipError_t dogk_launch_sequence(int variant, const dog::LaunchArgs* args, int grid1, int grid2,
-                                int grid3, int max_gauss, int debug, int wide1, hipStream_t stream,
-                                hipEvent_t* ev)
+// Launch pass 1 and pass 2 on `stream`, one workgroup per tile of each
+// table (a pass with no tiles is not launched; pass 1 also clears the
+// candidate count, so without pass-1 tiles a fill kernel does).  wide1: every
+// frame's rows are 16-byte aligned and its width is a multiple of 64, so
+// pass 1 may use 16-byte loads.  If ev is non-NULL, ev[2i] and ev[2i+1] take
+// the start and end of pass i+1's execution (the dispatch's own timestamps,
+// so the launch gap before a kernel is not counted).
+hipError_t dogk_launch_passes(int variant, const dog::LaunchArgs* args, int grid1, int grid2,
+                              int wide1, hipStream_t stream, hipEvent_t* ev)
 {
     const dog::KernelSet& k = dog::kSets[variant];
     const void* pass1 = wide1 && k.pass1w ? k.pass1w : k.pass1;
-    const void* nms = k.nms[debug ? 1 : 0];
-    (void)max_gauss;
     void* params[] = {const_cast<dog::LaunchArgs*>(args)};
-    const void* fn[3] = {pass1, k.pass2, nms};
-    const int grid[3] = {grid1, grid2, grid3};
-    const int block[3] = {64 * k.NW, 64 * k.NW, 64 * k.NWN};
-    for (int i = 0; i < 3; ++i) {
+    const void* fn[2] = {pass1, k.pass2};
+    const int grid[2] = {grid1, grid2};
+    if (grid1 <= 0) {
+        hipLaunchKernelGGL(dog::k_fill_u32, dim3(1), dim3(64), 0, stream, &args->cand->count, 1, 0u);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    for (int i = 0; i < 2; ++i) {
+        if (grid[i] <= 0)
+            continue;
         const hipError_t e =
-            ev ? hipExtLaunchKernel(fn[i], dim3(grid[i]), dim3(block[i]), params, 0, stream,
+            ev ? hipExtLaunchKernel(fn[i], dim3(grid[i]), dim3(64 * k.NW), params, 0, stream,
                                     ev[2 * i], ev[2 * i + 1], 0)
-               : hipLaunchKernel(fn[i], dim3(grid[i]), dim3(block[i]), params, 0, stream);
+               : hipLaunchKernel(fn[i], dim3(grid[i]), dim3(64 * k.NW), params, 0, stream);
         if (e != hipSuccess)
             return e;
     }
     return hipSuccess;
+}
+
+// The local-maximum kernel (timed by ev[0], ev[1] when ev is non-NULL).
+hipError_t dogk_launch_nms_ev(int variant, const dog::LaunchArgs* args, int grid3, int debug,
+                              hipStream_t stream, hipEvent_t* ev)
+{
+    const dog::KernelSet& k = dog::kSets[variant];
+    void* params[] = {const_cast<dog::LaunchArgs*>(args)};
+    const void* fn = k.nms[debug ? 1 : 0];
+    return ev ? hipExtLaunchKernel(fn, dim3(grid3), dim3(64 * k.NWN), params, 0, stream, ev[0],
+                                   ev[1], 0)
+              : hipLaunchKernel(fn, dim3(grid3), dim3(64 * k.NWN), params, 0, stream);
 }
 
 hipError_t dogk_launch_nms(int variant, const dog::LaunchArgs* args, int grid3, int max_gauss,

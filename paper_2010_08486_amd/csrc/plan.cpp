@@ -71,6 +71,7 @@ int build_plan(const dog_params& prm, Plan* plan, std::string* err)
     P.sigma.assign(P.n_g, 0.0);
     P.r.assign(P.n_g, 0);
     P.weights.clear();
+    P.half64.assign(P.n_g, {});
     std::memset(&P.desc, 0, sizeof(P.desc));
     P.desc.n_g = P.n_g;
     for (int i = 0; i < P.n_g; ++i) {
@@ -101,6 +102,9 @@ int build_plan(const dog_params& prm, Plan* plan, std::string* err)
         P.weights.resize(off + padded, 0.0f);
         for (int j = -r; j <= r; ++j)
             P.weights[off + (j + r)] = (float)(g[j < 0 ? -j : j] / total);
+        P.half64[i].resize(r + 1);
+        for (int j = 0; j <= r; ++j)
+            P.half64[i][j] = g[j] / total;
         P.desc.r[i] = r;
         P.desc.woff[i] = off;
         P.desc.sigma[i] = (float)s;

@@ -6,6 +6,7 @@
 #include "runtime.h"
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 
@@ -214,6 +215,51 @@ static long long reflect_index(long long t, long long n)
     return u < n ? u : p - 1 - u;
 }
 
+// ---- transform-domain blur: shapes, job sizes, kernel transfer functions
+
+// Frames whose sides are powers of two in [64, 2048] take the transform path.
+static bool dct_shape_ok(int H, int W)
+{
+    auto p2 = [](int v) { return v >= 64 && v <= 2048 && (v & (v - 1)) == 0; };
+    return p2(H) && p2(W);
+}
+
+static int ilog2(int v)
+{
+    int l = 0;
+    while ((1 << l) < v)
+        ++l;
+    return l;
+}
+
+// Lines per workgroup: 4096 / N (at least 4, at most 16), so a workgroup
+// holds at most 2048 complex values per line pair count (at most 40 KB of LDS
+// with the twiddles) and small transforms still fill their workgroups.
+static int dct_lines_per_job(int N)
+{
+    return std::min(16, std::max(4, 4096 / N));
+}
+
+// H[k] = w_0 + 2 sum_{j=1..r} w_j cos(pi k j / N), k = 0..N-1, from the FP64
+// half kernel (cosines by the three-term recurrence in j).
+static std::vector<double> dct_transfer(const std::vector<double>& half, int N)
+{
+    std::vector<double> H((size_t)N);
+    const int r = (int)half.size() - 1;
+    for (int k = 0; k < N; ++k) {
+        const double c1 = std::cos(M_PI * (double)k / (double)N);
+        double cm = 1.0, cj = c1, sum = 0.0;
+        for (int j = 1; j <= r; ++j) {
+            sum += half[j] * cj;
+            const double cn = 2.0 * c1 * cj - cm;
+            cm = cj;
+            cj = cn;
+        }
+        H[k] = half[0] + 2.0 * sum;
+    }
+    return H;
+}
+
 static constexpr size_t kRecBytes = sizeof(CandRec);
 static constexpr uint32_t kUnpublished = 0xffffffffu;  // host-side count before a launch
 
@@ -273,10 +319,17 @@ static hipError_t enqueue_sequence(dog_context* c, hipStream_t st, const FrameDe
         e = hipMemcpyAsync(const_cast<FrameDesc*>(a.frames), c->h_tables.p, c->frames_bytes,
                            hipMemcpyHostToDevice, st);
     }
+    hipEvent_t* ev = c->profiling ? c->ev : nullptr;
     if (e == hipSuccess)
-        e = dogk_launch_sequence(c->variant, &a, a.n1, a.n2, a.n3, c->n_gauss,
-                                 c->debug_planes ? 1 : 0, c->wide1 ? 1 : 0, st,
-                                 c->profiling ? c->ev : nullptr);
+        e = dogk_launch_passes(c->variant, &a, a.n1, a.n2, c->wide1 ? 1 : 0, st, ev);
+    // the transform-domain planes: forward 1, forward 2, inverse 1, inverse 2
+    for (int i = 0; i < 4 && e == hipSuccess; ++i)
+        if (c->dct.n[i] > 0)
+            e = dogk_dct(&a, static_cast<const DctJob*>(c->dct.jobs[i]), c->dct.n[i],
+                         c->dct.lds[i], i >= 2 ? 1 : 0, st, ev ? ev + 6 + 2 * i : nullptr);
+    if (e == hipSuccess)
+        e = dogk_launch_nms_ev(c->variant, &a, a.n3, c->debug_planes ? 1 : 0, st,
+                               ev ? ev + 4 : nullptr);
     return e;
 }
 
@@ -308,6 +361,7 @@ static std::vector<long long> launch_key(const dog_context* c, const std::vector
     k.push_back((long long)c->plan_gen);
     k.push_back(dbg_D ? 1 : 0);
     k.push_back(c->profiling ? 1 : 0);
+    k.push_back(c->dct_min_taps);
     k.push_back((long long)(uintptr_t)c->planes.p);
     k.push_back((long long)(uintptr_t)c->tables.p);
     k.push_back((long long)(uintptr_t)c->cand.p);
@@ -344,14 +398,29 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
     const Variant V = variant_geometry(c->variant);
     const int n_g = P.n_g;
 
-    // ---- workspace: T and L planes (transposed, pitch = H rounded to 64)
+    // ---- planes blurred in the transform domain: those whose kernels have
+    // at least dct_min_taps taps, on frames whose sides are powers of two
+    std::vector<std::vector<int>> dctp(n);
+    bool any_dct = false;
+    for (int f = 0; f < n; ++f) {
+        if (!dct_shape_ok(frames[f].H, frames[f].W) || c->dct_min_taps <= 0)
+            continue;
+        for (int p = 0; p < n_g; ++p)
+            if (2 * P.r[p] + 1 >= c->dct_min_taps)
+                dctp[f].push_back(p);
+        any_dct = any_dct || !dctp[f].empty();
+    }
+
+    // ---- workspace: T and L planes (transposed, pitch = H rounded to 64),
+    // and the transform of the frame where planes are taken that way
     std::vector<long long> pitch(n), off(n);
     size_t total = 0;
     for (int f = 0; f < n; ++f) {
         pitch[f] = ((long long)frames[f].H + 63) / 64 * 64;
         const size_t plane = (size_t)frames[f].W * (size_t)pitch[f];
         off[f] = (long long)total;
-        total += 2 * (size_t)n_g * plane + ((dbg_D && f == 0) ? (size_t)P.k * plane : 0);
+        total += 2 * (size_t)n_g * plane + ((dbg_D && f == 0) ? (size_t)P.k * plane : 0) +
+                 (dctp[f].empty() ? 0 : plane);
         total = align_up(total, 64);
     }
     int rc = ctx_alloc(c, &c->planes, total * sizeof(float), "scale-space planes");
@@ -422,6 +491,8 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
         for (int f = 0; f < n; ++f) {
             const int H = frames[f].H, W = frames[f].W;
             for (int p = 0; p < n_g; ++p) {
+                if (std::find(dctp[f].begin(), dctp[f].end(), p) != dctp[f].end())
+                    continue;   // blurred in the transform domain
                 r1.push_back({f, p, (W + 63) / 64, (H + band - 1) / band, P.r[p]});
                 r2.push_back({f, p, (H + 63) / 64, (W + band - 1) / band, P.r[p]});
             }
@@ -504,6 +575,112 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
                 rows2_off[f] = table_for(frames[f].W, pitch[f] * 4);
             }
         }
+        // transform-domain tables: per transform length the twiddles, per
+        // (length, plane) the scaled kernel transfer function, and the jobs
+        // of the four launches (float offsets into one host array first)
+        std::vector<float> dtab;                       // twiddles and H vectors
+        std::vector<DctJob> djobs[4];
+        struct TabRef {
+            int N, p;
+            size_t at;
+        };
+        std::vector<TabRef> tw_at, h_at;
+        auto twiddles = [&](int N) {
+            for (const TabRef& t : tw_at)
+                if (t.N == N)
+                    return t.at;
+            const size_t at = dtab.size();
+            for (int t = 0; t < N / 2; ++t) {
+                const double a = -2.0 * M_PI * (double)t / (double)N;
+                dtab.push_back((float)std::cos(a));
+                dtab.push_back((float)std::sin(a));
+            }
+            for (int k = 0; k < N; ++k) {
+                const double a = -M_PI * (double)k / (2.0 * (double)N);
+                dtab.push_back((float)std::cos(a));
+                dtab.push_back((float)std::sin(a));
+            }
+            while (dtab.size() % 64)
+                dtab.push_back(0.0f);
+            tw_at.push_back({N, 0, at});
+            return at;
+        };
+        auto transfer = [&](int N, int p) {
+            for (const TabRef& t : h_at)
+                if (t.N == N && t.p == p)
+                    return t.at;
+            const size_t at = dtab.size();
+            const std::vector<double> h = dct_transfer(P.half64[p], N);
+            for (int k = 0; k < N; ++k)
+                dtab.push_back((float)(h[k] / (double)N));
+            while (dtab.size() % 64)
+                dtab.push_back(0.0f);
+            h_at.push_back({N, p, at});
+            return at;
+        };
+        // pointers into the device table are fixed up once its offset is known
+        struct Fix {
+            int kind;
+            size_t job;
+            size_t tw, post, hl, hp;
+            bool scaled;
+        };
+        std::vector<Fix> fixes;
+        auto add_jobs = [&](int kind, const float* in, int in_pitch, float* out, int out_pitch,
+                            int N, int nlines, int cols, int frame, int p_scaled) {
+            const int L = dct_lines_per_job(N);
+            const size_t tw = twiddles(N);
+            size_t hl = 0, hp = 0;
+            if (p_scaled >= 0) {
+                const int Hn = frames[frame].H, Wn = frames[frame].W;
+                hl = transfer(Hn, p_scaled);   // lines are rows ky: H_y
+                hp = transfer(Wn, p_scaled);   // positions kx: H_x
+            }
+            for (int l0 = 0; l0 < nlines; l0 += L) {
+                DctJob j{};
+                j.in = in;
+                j.out = out;
+                j.in_pitch = in_pitch;
+                j.out_pitch = out_pitch;
+                j.N = N;
+                j.logn = ilog2(N);
+                j.line0 = l0;
+                j.lines = L;
+                j.logp = ilog2(L / 2);
+                j.cols = cols;
+                j.frame = frame;
+                fixes.push_back({kind, djobs[kind].size(), tw, tw + (size_t)N, hl, hp,
+                                 p_scaled >= 0});
+                djobs[kind].push_back(j);
+            }
+        };
+        for (int f = 0; f < n; ++f) {
+            if (dctp[f].empty())
+                continue;
+            const int H = frames[f].H, W = frames[f].W;
+            const long long pt = pitch[f];
+            const size_t plane = (size_t)W * (size_t)pt;
+            float* T0 = planes + off[f];
+            float* L0 = T0 + (size_t)n_g * plane;
+            float* Ft = L0 + (size_t)n_g * plane + ((dbg_D && f == 0) ? (size_t)P.k * plane : 0);
+            float* F1 = T0 + (size_t)dctp[f][0] * plane;   // the first such plane's T storage
+            // forward: along y over the frame's columns, then along x
+            add_jobs(0, nullptr, 0, F1, (int)pt, H, W, 1, f, -1);
+            add_jobs(1, F1, (int)pt, Ft, W, W, H, 1, f, -1);
+            for (int p : dctp[f]) {
+                float* G = T0 + (size_t)p * plane;
+                add_jobs(2, Ft, W, G, W, W, H, 0, f, p);
+                add_jobs(3, G, W, L0 + (size_t)p * plane, (int)pt, H, W, 1, f, -1);
+            }
+        }
+        DctLaunch dl{};
+        for (int i = 0; i < 4; ++i) {
+            dl.n[i] = (int)djobs[i].size();
+            for (const DctJob& j : djobs[i])
+                dl.lds[i] = std::max(dl.lds[i], dogk_dct_lds_bytes(j.N, j.lines));
+        }
+        (void)any_dct;
+
         const long long t1 = (long long)tb1.size(), t2 = (long long)tb2.size(),
                         t3 = (long long)tb3.size();
         if (t1 > INT32_MAX / 2 || t2 > INT32_MAX / 2 || t3 > INT32_MAX / 2 || n > 65535) {
@@ -518,7 +695,14 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
         const size_t o_t2 = align_up(o_t1 + sizeof(Tile) * tb1.size(), 256);
         const size_t o_t3 = align_up(o_t2 + sizeof(Tile) * tb2.size(), 256);
         const size_t o_rows = align_up(o_t3 + sizeof(Tile) * tb3.size(), 256);
-        const size_t tbytes = align_up(o_rows + sizeof(int) * rowtab.size(), 256);
+        const size_t o_dtab = align_up(o_rows + sizeof(int) * rowtab.size(), 256);
+        size_t o_djobs[4];
+        size_t o_end = align_up(o_dtab + sizeof(float) * dtab.size(), 256);
+        for (int i = 0; i < 4; ++i) {
+            o_djobs[i] = o_end;
+            o_end = align_up(o_end + sizeof(DctJob) * djobs[i].size(), 256);
+        }
+        const size_t tbytes = o_end;
         if ((rc = ctx_alloc(c, &c->tables, tbytes, "launch tables")) != DOG_OK)
             return rc;
         if ((rc = ctx_pin(&c->h_tables, tbytes)) != DOG_OK)
@@ -546,6 +730,22 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
         std::memcpy(h + o_t2, tb2.data(), sizeof(Tile) * tb2.size());
         std::memcpy(h + o_t3, tb3.data(), sizeof(Tile) * tb3.size());
         std::memcpy(h + o_rows, rowtab.data(), sizeof(int) * rowtab.size());
+        std::memcpy(h + o_dtab, dtab.data(), sizeof(float) * dtab.size());
+        {
+            const float* dt_f = reinterpret_cast<const float*>(dt + o_dtab);
+            for (const Fix& fx : fixes) {
+                DctJob& j = djobs[fx.kind][fx.job];
+                j.tw = reinterpret_cast<const float2*>(dt_f + fx.tw);
+                j.post = reinterpret_cast<const float2*>(dt_f + fx.post);
+                j.hline = fx.scaled ? dt_f + fx.hl : nullptr;
+                j.hpos = fx.scaled ? dt_f + fx.hp : nullptr;
+            }
+            for (int i = 0; i < 4; ++i) {
+                std::memcpy(h + o_djobs[i], djobs[i].data(), sizeof(DctJob) * djobs[i].size());
+                dl.jobs[i] = dt + o_djobs[i];
+            }
+        }
+        c->dct = dl;
         DOG_HIP(hipMemcpyAsync(c->tables.p, h, tbytes, hipMemcpyHostToDevice, c->stream));
         DOG_HIP(hipStreamSynchronize(c->stream));
 
@@ -571,7 +771,7 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
             c->cap, std::max<uint32_t>(2048, c->last_count + c->last_count / 2 + 256));
 
         if (c->profiling) {
-            for (int i = 0; i < 6; ++i)
+            for (int i = 0; i < 2 * DOG_NKERNELS; ++i)
                 if (!c->ev[i])
                     DOG_HIP(hipEventCreate(&c->ev[i]));
         }
@@ -655,7 +855,13 @@ int collect_frames(dog_context* c, const Plan& P, std::vector<std::vector<dog_bl
         count = std::max(count, ends[i]);
     }
     if (c->profiling) {
-        for (int i = 0; i < 3; ++i) {
+        // kernels that were launched: pass 1 and 2 when they had tiles, the
+        // local maxima, the transform-domain launches that had jobs
+        const bool ran[DOG_NKERNELS] = {c->args.n1 > 0, c->args.n2 > 0, true, c->dct.n[0] > 0,
+                                        c->dct.n[1] > 0, c->dct.n[2] > 0, c->dct.n[3] > 0};
+        for (int i = 0; i < DOG_NKERNELS; ++i) {
+            if (!ran[i])
+                continue;
             float ms = 0.0f;
             DOG_HIP(hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]));
             c->kernel_ms[i] += ms;

@@ -8,8 +8,11 @@
 #include <string>
 #include <vector>
 
+#include "dct.h"
 #include "dog.h"
 #include "dog_internal.h"
+
+#define DOG_NKERNELS 7
 
 namespace dog {
 
@@ -21,6 +24,7 @@ struct Plan {
     std::vector<double> sigma;
     std::vector<int> r;
     std::vector<float> weights;  // per-plane vectors, zero-padded
+    std::vector<std::vector<double>> half64;  // per plane: FP64 weights w_j, j = 0..r
     LadderDesc desc;
 };
 
@@ -89,9 +93,10 @@ extern "C" {
 int dogk_num_variants();
 void dogk_variant_geometry(int v, int* S, int* NW, int* BI, int* BN, int* NWN);
 int dogk_variant_ring(int v);
-hipError_t dogk_launch_sequence(int variant, const dog::LaunchArgs* args, int grid1, int grid2,
-                                int grid3, int max_gauss, int debug, int wide1, hipStream_t stream,
-                                hipEvent_t* ev);
+hipError_t dogk_launch_passes(int variant, const dog::LaunchArgs* args, int grid1, int grid2,
+                              int wide1, hipStream_t stream, hipEvent_t* ev);
+hipError_t dogk_launch_nms_ev(int variant, const dog::LaunchArgs* args, int grid3, int debug,
+                              hipStream_t stream, hipEvent_t* ev);
 hipError_t dogk_launch_nms(int variant, const dog::LaunchArgs* args, int grid3, int max_gauss,
                            int debug, hipStream_t stream);
 hipError_t dogk_untranspose(const float* src, float* dst, int n_planes, int H, int W,
@@ -138,6 +143,10 @@ struct dog_context {
     dog::PinBuf h_ends;            // per local-maximum workgroup: end of its record range
     dog::PinBuf h_input;           // staging of host frames
     dog::DevBuf prep;              // preprocessing: select state, histograms, weights
+    dog::DevBuf prn;               // device pruning: FP64 ladder sigmas
+    dog::PinBuf h_prn;             // device pruning: sigma staging, then the kernel's output
+    uint32_t prn_blobs = 0;        // blobs one pruning workgroup holds (from the LDS limit)
+    uint32_t prn_pairs = 0;        // touching pairs it holds
     double prep_sigma = -1.0;      // smoothing sigma whose weights `prep` holds
     bool prep_dirty = false;       // `prep` histograms not known to be zero
     hipEvent_t ev_prep = nullptr;  // recorded after the last preprocessing launch
@@ -145,8 +154,10 @@ struct dog_context {
     // optional per-kernel timing: start and end events of each kernel's
     // dispatch, on the stream it is launched on
     bool profiling = false;
-    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    double kernel_ms[3] = {0.0, 0.0, 0.0};
+    // kernels: pass 1, pass 2, local maxima, then the transform-domain
+    // blur's forward 1, forward 2, inverse 1, inverse 2
+    hipEvent_t ev[2 * DOG_NKERNELS] = {};
+    double kernel_ms[DOG_NKERNELS] = {};
     int64_t kernel_launches = 0;
 
     // the captured launch sequence of the last table layout (frame table
@@ -156,6 +167,7 @@ struct dog_context {
     std::vector<long long> graph_key;
     std::vector<long long> seen_key;   // layout of the previous call
     dog::LaunchArgs args;
+    dog::DctLaunch dct{};          // transform-domain launches of the current tables
     int n_gauss = 0;
     bool debug_planes = false;     // the current tables write the DoG planes
     bool wide1 = false;            // every frame of the tables allows 16-byte row loads
@@ -182,6 +194,11 @@ struct dog_context {
     int lane_count = 3;
     std::vector<dog_context*> lanes;
     hipEvent_t ev_fork = nullptr;
+
+    // transform-domain blur: planes whose kernels have at least this many
+    // taps, on frames whose sides are powers of two in [64, 4096]; 0: never
+    int dct_min_taps = 0;
+    bool dct_forced = false;     // set by dog_set_dct (else the tuned choice)
 
     bool have_plan = false;
     uint64_t plan_gen = 0;

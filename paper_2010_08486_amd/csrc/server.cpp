@@ -143,6 +143,7 @@ struct dog_server {
     uint64_t reserved = 0;                 // sum of the slots' commits
     uint64_t peak_reserved = 0;
     uint64_t peak_held = 0;                // largest sum of the slots' held bytes
+    int64_t admission_waits = 0;           // times the oldest request did not fit
     bool stop = false;
     std::thread dispatcher;
 
@@ -337,6 +338,7 @@ void run_dispatcher(dog_server* sv)
             // workspaces between batches: release them, other slots first,
             // then this one; otherwise wait for a running batch to finish
             const Request& r = sv->queue.front();
+            sv->admission_waits += 1;
             std::vector<Slot*> idle_held;
             for (auto& s : sv->slots)
                 if (!s->has_work && s.get() != idle && s->held() > 0)
@@ -632,6 +634,7 @@ int dog_server_stats(dog_server* sv, dog_stats* out)
     for (const auto& s : sv->slots)
         out->held_bytes += s->held();
     out->peak_held_bytes = sv->peak_held;
+    out->admission_waits = sv->admission_waits;
     if (!sv->lat_ms.empty()) {
         std::vector<double> v = sv->lat_ms;
         std::sort(v.begin(), v.end());

@@ -18,6 +18,8 @@ candidates, with their responses bit for bit.
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 import oracle
@@ -42,9 +44,10 @@ def check_candidates_exact(gpu_raw, D_gpu, thr):
 
 
 def check_exempt_bound(exempt, n_raw):
-    """Near-tie exemptions on a frame of natural shape: at most 1 %."""
-    assert exempt <= MAX_EXEMPT_FRACTION * max(n_raw, 1), "%d of %d candidates exempt" % (
-        exempt, n_raw)
+    """Near-tie exemptions on a frame of natural shape: at most 1 % of the
+    candidates, rounded up to a whole voxel."""
+    allowed = math.ceil(MAX_EXEMPT_FRACTION * max(n_raw, 1))
+    assert exempt <= allowed, "%d of %d candidates exempt (at most %d)" % (exempt, n_raw, allowed)
 
 
 def check_planes(L_gpu, D_gpu, L_orc, D_orc, sigmas, max_abs):
