@@ -244,6 +244,26 @@ int dog_preprocess(dog_context* ctx, const float* d_image, int64_t height, int64
                    int64_t row_stride, double smooth_sigma, double saturated, float* d_out,
                    float* d_smoothed, float* limits_out, void* stream);
 
+/* dog_preprocess for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results, with no context.  Its select state,
+ * histograms and weights (about 265 KB) live in a static device array, one
+ * per GPU, held until the process ends; the call allocates nothing
+ * (no hipMalloc, hipFree, pinned or heap memory), uploads nothing and never
+ * waits.  It runs on the calling thread's current device, on `stream` (a
+ * stream of that device; NULL = the null stream): a fill kernel clears the
+ * histograms and stores the weights, then the four preprocessing kernels.
+ * d_image, d_out and d_smoothed as in dog_preprocess.  d_limits (device, 2
+ * floats, may be NULL) receives lo and hi once the stream has passed the
+ * call.  Calls that overlap on one GPU (other streams, other threads) share
+ * the array and race: the caller orders them.  Limits: the image bounds of
+ * every entry point (height * row_stride < 2^29) and a smoothing radius of
+ * at most 16; beyond them DOG_EINVAL with a message.  Errors: DOG_EINVAL,
+ * DOG_EDEVICE. */
+int dog_preprocess_noalloc(const float* d_image, int64_t height, int64_t width,
+                           int64_t row_stride, double smooth_sigma, double saturated,
+                           float* d_out, float* d_smoothed, float* d_limits, void* stream);
+
 /* Whole detector on n_frames frames of any sizes.  The frames are cut into
  * consecutive groups of at most dog_set_batch_grouping's pixel count (by
  * default 2^20, one 1024x1024 frame; a larger frame forms a group alone),

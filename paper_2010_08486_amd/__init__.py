@@ -143,6 +143,7 @@ def lib() -> ctypes.CDLL:
         "dog_detect_device_async": (i32, [vp, vp, i64, i64, i64, ctypes.POINTER(dog_params), vp]),
         "dog_detect_device_finish": (i32, [vp, pblob, pi64]),
         "dog_preprocess": (i32, [vp, vp, i64, i64, i64, dbl, dbl, vp, vp, vp, vp]),
+        "dog_preprocess_noalloc": (i32, [vp, i64, i64, i64, dbl, dbl, vp, vp, vp, vp]),
         "dog_detect_batch": (i32, [vp, i32, ctypes.POINTER(dog_frame), ctypes.POINTER(dog_params), vp,
                                    ctypes.POINTER(dog_result)]),
         "dog_results_free": (None, [ctypes.POINTER(dog_result), i32]),
@@ -487,6 +488,32 @@ class Context:
         lib().dog_results_free(res, n)
         _check(rc)
         return out, raw
+
+
+def preprocess_noalloc(image, out, smoothed=None, limits=None, sigma: float = 1.0,
+                       saturated: float = 0.0035, stream=None) -> None:
+    """dog_preprocess_noalloc: the preprocessing of Context.preprocess into
+    caller-allocated CUDA tensors, with no allocation by the library (its
+    scratch is a static device array of the current GPU).  out (and
+    smoothed, if given): float32 tensors of the image's shape with dense
+    rows; limits: a float32 CUDA tensor of 2 elements receiving (lo, hi).
+    Queued on `stream` (default: the current stream); nothing is waited for."""
+    import torch
+    ptr, H, W, st = _tensor_image(image)
+    for t in (out, smoothed):
+        if t is not None and (not isinstance(t, torch.Tensor) or not t.is_cuda or
+                              t.dtype != torch.float32 or tuple(t.shape) != (H, W) or
+                              not t.is_contiguous()):
+            raise TypeError("out and smoothed must be dense float32 CUDA tensors of the image's shape")
+    if limits is not None and (not isinstance(limits, torch.Tensor) or not limits.is_cuda or
+                               limits.dtype != torch.float32 or limits.numel() < 2 or
+                               not limits.is_contiguous()):
+        raise TypeError("limits must be a float32 CUDA tensor of 2 elements")
+    _check(lib().dog_preprocess_noalloc(ptr, H, W, st, float(sigma), float(saturated),
+                                        out.data_ptr(),
+                                        smoothed.data_ptr() if smoothed is not None else None,
+                                        limits.data_ptr() if limits is not None else None,
+                                        _stream_ptr(stream, image.device.index)))
 
 
 def prune(params: Params, blobs: np.ndarray) -> np.ndarray:

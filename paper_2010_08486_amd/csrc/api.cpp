@@ -545,15 +545,17 @@ int dog_detect_device_finish(dog_context* ctx, dog_blob** blobs_out, int64_t* co
     return export_blobs(res[0], blobs_out, count_out);
 }
 
-int dog_preprocess(dog_context* ctx, const float* d_image, int64_t height, int64_t width,
-                   int64_t row_stride, double smooth_sigma, double saturated, float* d_out,
-                   float* d_smoothed, float* limits_out, void* stream)
+// Arguments of both preprocessing entry points; sets *r to the smoothing
+// radius.
+static int check_preprocess(const float* d_image, int64_t height, int64_t width,
+                            int64_t row_stride, double smooth_sigma, double saturated,
+                            const float* d_out, int* r)
 {
-    if (!ctx || !d_out) {
+    if (!d_out) {
         set_error("invalid argument");
         return DOG_EINVAL;
     }
-    int rc = check_image(d_image, height, width, row_stride);
+    const int rc = check_image(d_image, height, width, row_stride);
     if (rc != DOG_OK)
         return rc;
     if (!std::isfinite(smooth_sigma) || smooth_sigma < 0.0 || !(saturated >= 0.0) ||
@@ -561,11 +563,53 @@ int dog_preprocess(dog_context* ctx, const float* d_image, int64_t height, int64
         set_error("smooth_sigma must be finite and >= 0, saturated in [0, 1)");
         return DOG_EINVAL;
     }
-    const int r = smooth_sigma > 0.0 ? (int)std::floor(4.0 * smooth_sigma + 0.5) : 0;
-    if (r > dogk_preprocess_max_radius()) {
+    *r = smooth_sigma > 0.0 ? (int)std::floor(4.0 * smooth_sigma + 0.5) : 0;
+    if (*r > dogk_preprocess_max_radius()) {
         set_error("smoothing radius above " + std::to_string(dogk_preprocess_max_radius()));
         return DOG_EINVAL;
     }
+    return DOG_OK;
+}
+
+// The detector's kernel rule for the smoothing weights: exp(-j^2 / (2 s^2))
+// in FP64, normalised over the truncated support, rounded once to fp32 (no
+// smoothing: the single weight 1).  wf: 2r+1 floats (r <= 16; no heap use,
+// so the entry point that allocates nothing can call it).
+static void smoothing_weights(double smooth_sigma, int r, float* wf)
+{
+    double g[2 * 16 + 1];
+    double total = r > 0 ? 0.0 : 1.0;
+    g[r] = 1.0;
+    for (int j = -r; r > 0 && j <= r; ++j)
+        total += (g[j + r] = std::exp(-((double)j * j) / (2.0 * smooth_sigma * smooth_sigma)));
+    for (int j = 0; j <= 2 * r; ++j)
+        wf[j] = (float)(g[j] / total);
+}
+
+// Ranks of the two limits: m = floor(saturated N / 2), at most (N-1)/2.
+static void limit_ranks(int64_t height, int64_t width, double saturated, uint32_t* lo,
+                        uint32_t* hi)
+{
+    const long long N = (long long)height * width;
+    long long m = (long long)std::floor(saturated * (double)N / 2.0);
+    m = std::min(m, (N - 1) / 2);
+    *lo = (uint32_t)m;
+    *hi = (uint32_t)(N - 1 - m);
+}
+
+int dog_preprocess(dog_context* ctx, const float* d_image, int64_t height, int64_t width,
+                   int64_t row_stride, double smooth_sigma, double saturated, float* d_out,
+                   float* d_smoothed, float* limits_out, void* stream)
+{
+    if (!ctx) {
+        set_error("invalid argument");
+        return DOG_EINVAL;
+    }
+    int r = 0;
+    int rc = check_preprocess(d_image, height, width, row_stride, smooth_sigma, saturated, d_out,
+                              &r);
+    if (rc != DOG_OK)
+        return rc;
     if ((rc = ctx_idle(ctx)) != DOG_OK)
         return rc;
     if ((rc = use_device(ctx)) != DOG_OK)
@@ -596,27 +640,18 @@ int dog_preprocess(dog_context* ctx, const float* d_image, int64_t height, int64
         ctx->prep_dirty = false;
     }
     if (ctx->prep_sigma != smooth_sigma) {
-        // the detector's kernel rule: exp(-j^2 / (2 s^2)) in FP64, normalised
-        // over the truncated support, rounded once to fp32 (no smoothing:
-        // the single weight 1)
-        std::vector<double> g(2 * r + 1, 1.0);
-        double total = r > 0 ? 0.0 : 1.0;
-        for (int j = -r; r > 0 && j <= r; ++j)
-            total += (g[j + r] = std::exp(-((double)j * j) / (2.0 * smooth_sigma * smooth_sigma)));
-        std::vector<float> wf(2 * r + 1);
-        for (int j = 0; j <= 2 * r; ++j)
-            wf[j] = (float)(g[j] / total);
-        DOG_HIP(hipMemcpyAsync(d_w, wf.data(), wf.size() * sizeof(float), hipMemcpyHostToDevice, st));
+        float wf[2 * 16 + 1];
+        smoothing_weights(smooth_sigma, r, wf);
+        DOG_HIP(hipMemcpyAsync(d_w, wf, (size_t)(2 * r + 1) * sizeof(float), hipMemcpyHostToDevice,
+                               st));
         DOG_HIP(hipStreamSynchronize(st));
         ctx->prep_sigma = smooth_sigma;
     }
-    const long long N = (long long)height * width;
-    long long m = (long long)std::floor(saturated * (double)N / 2.0);
-    m = std::min(m, (N - 1) / 2);
+    uint32_t rank_lo = 0, rank_hi = 0;
+    limit_ranks(height, width, saturated, &rank_lo, &rank_hi);
     float* d_s = d_smoothed ? d_smoothed : d_out;
     const hipError_t le = dogk_preprocess(d_image, (int)height, (int)width, (long long)row_stride,
-                                          d_w, r, d_s, d_out, ctx->prep.p, (uint32_t)m,
-                                          (uint32_t)(N - 1 - m), st);
+                                          d_w, r, d_s, d_out, ctx->prep.p, rank_lo, rank_hi, st);
     if (le != hipSuccess) {
         // some kernels may have run and left counts behind: the next call
         // clears the scratch first, after what was queued here
@@ -630,6 +665,25 @@ int dog_preprocess(dog_context* ctx, const float* d_image, int64_t height, int64
                                hipMemcpyDeviceToHost, st));
         DOG_HIP(hipStreamSynchronize(st));
     }
+    return DOG_OK;
+}
+
+int dog_preprocess_noalloc(const float* d_image, int64_t height, int64_t width,
+                           int64_t row_stride, double smooth_sigma, double saturated,
+                           float* d_out, float* d_smoothed, float* d_limits, void* stream)
+{
+    int r = 0;
+    const int rc = check_preprocess(d_image, height, width, row_stride, smooth_sigma, saturated,
+                                    d_out, &r);
+    if (rc != DOG_OK)
+        return rc;
+    float wf[2 * 16 + 1];
+    smoothing_weights(smooth_sigma, r, wf);
+    uint32_t rank_lo = 0, rank_hi = 0;
+    limit_ranks(height, width, saturated, &rank_lo, &rank_hi);
+    DOG_HIP(dogk_preprocess_noalloc(d_image, (int)height, (int)width, (long long)row_stride,
+                                    wf, r, d_smoothed ? d_smoothed : d_out, d_out,
+                                    d_limits, rank_lo, rank_hi, static_cast<hipStream_t>(stream)));
     return DOG_OK;
 }
 

@@ -24,6 +24,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 
 namespace dogpre {
 
@@ -451,9 +452,116 @@ __global__ void __launch_bounds__(256) k_stretch(const float* __restrict__ s, lo
     }
 }
 
+// Set-up of a call that allocates nothing: clear the select state and the
+// histograms (the four kernels expect zero histograms; a fill kernel rather
+// than a memset, so the call can be captured into a graph), and put the
+// smoothing weights, passed by value, after them.
+struct SmoothWeights {
+    float w[2 * kMaxR + 1];
+};
+
+__global__ void __launch_bounds__(256) k_noalloc_setup(uint32_t* __restrict__ words, int n_words,
+                                                       SmoothWeights sw, float* __restrict__ wdst,
+                                                       int nw)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_words; i += gridDim.x * blockDim.x)
+        words[i] = 0u;
+    if (blockIdx.x == 0 && (int)threadIdx.x < nw)
+        wdst[threadIdx.x] = sw.w[threadIdx.x];
+}
+
+__global__ void k_copy_limits(const float* __restrict__ src, float* __restrict__ dst)
+{
+    if (threadIdx.x < 2)
+        dst[threadIdx.x] = src[threadIdx.x];
+}
+
+// Bytes of the static scratch: select state and histograms, then the weights.
+constexpr size_t kNoAllocWeights = kScratch;
+constexpr size_t kNoAllocBytes = kScratch + 256;
+static_assert((2 * kMaxR + 1) * sizeof(float) <= 256, "weights fit the scratch tail");
+
 }  // namespace dogpre
 
+// Scratch of the preprocessing variant that allocates nothing: one copy per
+// GPU, held until the process ends.  Host code never uses this name as an
+// address (on the host it is only a stand-in for the symbol); it uses the
+// device address that hipGetSymbolAddress returns for the current GPU.
+static __device__ __align__(256) unsigned char scratch[dogpre::kNoAllocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};   // device address of `scratch`, per GPU
+}  // namespace
+
 extern "C" {
+
+hipError_t dogk_preprocess(const float* d_in, int H, int W, long long stride, const float* d_w,
+                           int r, float* d_s, float* d_out, void* d_scratch, uint32_t rank_lo,
+                           uint32_t rank_hi, hipStream_t stream);
+
+size_t dogk_preprocess_noalloc_bytes() { return dogpre::kNoAllocBytes; }
+
+// Device address of the static scratch on the current GPU, looked up once
+// per device (with that device current) and kept.
+hipError_t dogk_noalloc_scratch(void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        if (!p)
+            return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+// dogk_preprocess with its scratch and weights in the static array of the
+// current GPU: set-up kernel, the four preprocessing kernels, and (d_limits
+// non-NULL) a copy of the two limits to d_limits on the device.  w_host: the
+// 2r+1 fp32 weights.  Calls overlapping on one GPU share the array and race.
+hipError_t dogk_preprocess_noalloc(const float* d_in, int H, int W, long long stride,
+                                   const float* w_host, int r, float* d_s, float* d_out,
+                                   float* d_limits, uint32_t rank_lo, uint32_t rank_hi,
+                                   hipStream_t stream)
+{
+    using namespace dogpre;
+    if (r < 0 || r > kMaxR)
+        return hipErrorInvalidValue;
+    void* p = nullptr;
+    hipError_t e = dogk_noalloc_scratch(&p);
+    if (e != hipSuccess)
+        return e;
+    char* base = static_cast<char*>(p);
+    SmoothWeights sw{};
+    for (int j = 0; j <= 2 * r; ++j)
+        sw.w[j] = w_host[j];
+    float* d_w = reinterpret_cast<float*>(base + kNoAllocWeights);
+    hipLaunchKernelGGL(k_noalloc_setup, dim3(64), dim3(256), 0, stream,
+                       reinterpret_cast<uint32_t*>(base), (int)(kScratch / 4), sw, d_w, 2 * r + 1);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    if ((e = dogk_preprocess(d_in, H, W, stride, d_w, r, d_s, d_out, base, rank_lo, rank_hi,
+                             stream)) != hipSuccess)
+        return e;
+    if (d_limits) {
+        hipLaunchKernelGGL(k_copy_limits, dim3(1), dim3(64), 0, stream,
+                           reinterpret_cast<const float*>(base + 16), d_limits);
+        e = hipGetLastError();
+    }
+    return e;
+}
 
 // Scratch the launcher needs in device memory: select state + histograms.
 size_t dogk_preprocess_scratch_bytes() { return dogpre::kScratch; }

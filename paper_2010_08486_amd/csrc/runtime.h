@@ -108,6 +108,11 @@ int dogk_preprocess_max_radius();
 hipError_t dogk_preprocess(const float* d_in, int H, int W, long long stride, const float* d_w,
                            int r, float* d_s, float* d_out, void* d_scratch, uint32_t rank_lo,
                            uint32_t rank_hi, hipStream_t stream);
+size_t dogk_preprocess_noalloc_bytes();
+hipError_t dogk_preprocess_noalloc(const float* d_in, int H, int W, long long stride,
+                                   const float* w_host, int r, float* d_s, float* d_out,
+                                   float* d_limits, uint32_t rank_lo, uint32_t rank_hi,
+                                   hipStream_t stream);
 }
 
 struct dog_context {
