@@ -62,7 +62,7 @@ struct LadderDesc {
 struct Tile {
     uint16_t frame;
     uint8_t plane;
-    uint8_t pad_;
+    uint8_t n_planes;   // staged blur: planes plane, plane-1, ..., in turn (0: one)
     uint16_t cb;
     uint16_t band;
 };

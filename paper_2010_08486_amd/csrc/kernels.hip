@@ -369,149 +369,156 @@ __global__ void __launch_bounds__(64 * NW) k_blur_lds(LaunchArgs a)
         a.cand->count = 0u;  // read by the local-maximum kernel of this sequence
     const Tile tl = my_tile(PASS == 1 ? a.tiles1 : a.tiles2);
     const FrameDesc f = frame_of(a, tl.frame);
-    const int p = tl.plane;
-    const int r = cst(a.ladders)[f.ladder].r[p];
-    const cptr_t w = (cptr_t)(a.weights + cst(a.ladders)[f.ladder].woff[p]);
-    const float* src = PASS == 1 ? f.src : f.T + (long long)p * f.W * f.pitch;
-    const int n = PASS == 1 ? f.H : f.W;                       // rows along the blur
-    const int stride = PASS == 1 ? (int)f.src_stride : (int)f.pitch;
-    const int ncols = PASS == 1 ? f.W : (int)f.pitch;
-    const unsigned bytes = PASS == 1
-                               ? (unsigned)(((long long)(f.H - 1) * f.src_stride + f.W) * 4)
-                               : (unsigned)((long long)f.W * f.pitch * 4);
-    const __amdgpu_buffer_rsrc_t rs = plane_rsrc(src, bytes);
-    const int col0 = tl.cb * 64;
-    (void)ncols;
-    const int y0 = tl.band * (NW * S);
-    const int base = y0 - r;
-    const int nch = (2 * r + S) / S;   // tap chunks
-    const int nload = nch + NW;        // row chunks X_0 .. X_{nch+NW-1}
-    // the plane's taps go to LDS when they fit: each step then reads its S
-    // weights as broadcast vector loads, with no scalar-load latency per step
-    const bool w_lds = nch * S <= kLdsWeights;
-    if (w_lds) {
-        const float4* w4 = reinterpret_cast<const float4*>(a.weights + cst(a.ladders)[f.ladder].woff[p]);
-        for (int q = tid; q < nch * S / 4; q += G::NT)
-            wl4[q] = w4[q];
-    }
-
-    // X_0 .. X_NW into the ring, X_{NW+1} .. X_{NW+P} into registers.  Loads
-    // past the last chunk fetch the last chunk again (never stored), so every
-    // step issues the same loads.
-#pragma unroll
-    for (int j = 0; j <= NW; ++j) {
-        float4 t[G::LPL];
-        stage_load<S, NW, WIDE>(t, rs, tid, base, j, n, stride, col0);
-        stage_store<S, NW>(lds4, j, t, tid);
-    }
-    float4 stg[P][G::LPL];
-#pragma unroll
-    for (int k = 0; k < P; ++k)
-        stage_load<S, NW, WIDE>(stg[k], rs, tid, base, min(NW + 1 + k, nload - 1), n, stride, col0);
-    __syncthreads();
-
-    float acc[S], lo[S], hi[S], wr[S];
-#pragma unroll
-    for (int t = 0; t < S; ++t)
-        acc[t] = 0.0f;
-    lds_rows<S>(lo, lds, wv, lane);
-    // step c: taps c*S .. c*S+S-1 on X_{w+c}, X_{w+c+1}; then publish
-    // X_{NW+1+c} from staging register set c % P and refill that set
-    auto step = [&](int c, float4 (&st)[G::LPL]) {
-        // weights first: LDS returns in order, so the first products (with
-        // `lo` and these weights) need not wait for the rows of `hi`
+    // the tile's planes: tl.plane and the (tl.n_planes - 1) planes below it,
+    // widest first, each over the same columns and band (one plane if 0)
+    const int n_pl = tl.n_planes > 1 ? tl.n_planes : 1;
+    for (int pi = 0; pi < n_pl; ++pi) {
+        if (pi > 0)
+            __syncthreads();   // the previous plane's last LDS reads are done
+        const int p = tl.plane - pi;
+        const int r = cst(a.ladders)[f.ladder].r[p];
+        const cptr_t w = (cptr_t)(a.weights + cst(a.ladders)[f.ladder].woff[p]);
+        const float* src = PASS == 1 ? f.src : f.T + (long long)p * f.W * f.pitch;
+        const int n = PASS == 1 ? f.H : f.W;                       // rows along the blur
+        const int stride = PASS == 1 ? (int)f.src_stride : (int)f.pitch;
+        const int ncols = PASS == 1 ? f.W : (int)f.pitch;
+        const unsigned bytes = PASS == 1
+                                   ? (unsigned)(((long long)(f.H - 1) * f.src_stride + f.W) * 4)
+                                   : (unsigned)((long long)f.W * f.pitch * 4);
+        const __amdgpu_buffer_rsrc_t rs = plane_rsrc(src, bytes);
+        const int col0 = tl.cb * 64;
+        (void)ncols;
+        const int y0 = tl.band * (NW * S);
+        const int base = y0 - r;
+        const int nch = (2 * r + S) / S;   // tap chunks
+        const int nload = nch + NW;        // row chunks X_0 .. X_{nch+NW-1}
+        // the plane's taps go to LDS when they fit: each step then reads its S
+        // weights as broadcast vector loads, with no scalar-load latency per step
+        const bool w_lds = nch * S <= kLdsWeights;
         if (w_lds) {
-#pragma unroll
-            for (int u = 0; u < S; u += 4) {
-                const float4 q = wl4[(c * S + u) / 4];
-                wr[u] = q.x;
-                wr[u + 1] = q.y;
-                wr[u + 2] = q.z;
-                wr[u + 3] = q.w;
-            }
-        } else {
-#pragma unroll
-            for (int u = 0; u < S; ++u)
-                wr[u] = to_vgpr(w[c * S + u]);
+            const float4* w4 = reinterpret_cast<const float4*>(a.weights + cst(a.ladders)[f.ladder].woff[p]);
+            for (int q = tid; q < nch * S / 4; q += G::NT)
+                wl4[q] = w4[q];
         }
-        lds_rows<S>(hi, lds, (wv + c + 1) % G::Q, lane);
-        fma_chunk_v<S>(acc, lo, hi, wr);
+
+        // X_0 .. X_NW into the ring, X_{NW+1} .. X_{NW+P} into registers.  Loads
+        // past the last chunk fetch the last chunk again (never stored), so every
+        // step issues the same loads.
 #pragma unroll
-        for (int t = 0; t < S; ++t) {
-            // the accumulators pass through an empty asm statement, so the
-            // multiply-adds cannot sink past the barrier below (two steps'
-            // operands live at once would cost occupancy)
-            asm volatile("" : "+v"(acc[t]));
-            lo[t] = hi[t];
+        for (int j = 0; j <= NW; ++j) {
+            float4 t[G::LPL];
+            stage_load<S, NW, WIDE>(t, rs, tid, base, j, n, stride, col0);
+            stage_store<S, NW>(lds4, j, t, tid);
         }
-        const int j = NW + 1 + c;
-        if (j < nload)
-            stage_store<S, NW>(lds4, j % G::Q, st, tid);
-        stage_load<S, NW, WIDE>(st, rs, tid, base, min(j + P, nload - 1), n, stride, col0);
-        __syncthreads();
-    };
-    // whole groups of P steps issue the same loads every iteration, so each
-    // wait covers exactly the oldest staged chunk
-    int c = 0;
-    for (; c + P <= nch; c += P) {
+        float4 stg[P][G::LPL];
 #pragma unroll
         for (int k = 0; k < P; ++k)
-            step(c + k, stg[k]);
-    }
-#pragma unroll
-    for (int k = 0; k < P - 1; ++k)
-        if (c + k < nch)
-            step(c + k, stg[k]);
-
-    if (PASS == 1) {
-        // T is stored transposed: output column x is a row of T.  The tile
-        // (64 columns x NW*S outputs) goes through LDS (the ring is free after
-        // the last barrier) so that consecutive threads write consecutive
-        // 16-byte pieces of each T row; a direct store from the accumulators
-        // would scatter every store instruction over 64 rows of T.
-        constexpr int TS = NW * S + 4;   // LDS floats per column (padded)
-        constexpr int Q4 = NW * S / 4;   // 16-byte pieces per column
-        constexpr int NQ = 64 * Q4;
-        static_assert(64 * TS <= G::Q * S * 64, "transpose tile fits the ring");
-        float* tr = reinterpret_cast<float*>(lds4);
-#pragma unroll
-        for (int t = 0; t < S; t += 4)
-            *reinterpret_cast<float4*>(tr + lane * TS + wv * S + t) =
-                make_float4(acc[t], acc[t + 1], acc[t + 2], acc[t + 3]);
+            stage_load<S, NW, WIDE>(stg[k], rs, tid, base, min(NW + 1 + k, nload - 1), n, stride, col0);
         __syncthreads();
+
+        float acc[S], lo[S], hi[S], wr[S];
 #pragma unroll
-        for (int i = 0; i < (NQ + G::NT - 1) / G::NT; ++i) {
-            const int q = tid + i * G::NT;
-            if (NQ % G::NT == 0 || q < NQ) {
-                const int cx = q / Q4, y4 = q - cx * Q4;
-                const int x = col0 + cx, y = y0 + 4 * y4;
-                if (x < f.W && y < f.H) {
-                    const float4 v = *reinterpret_cast<const float4*>(tr + cx * TS + 4 * y4);
-                    float* __restrict__ dst = f.T + ((long long)p * f.W + x) * f.pitch + y;
-                    if (y + 4 <= f.H) {
-                        *reinterpret_cast<float4*>(dst) = v;
-                    } else {
-                        dst[0] = v.x;
-                        if (y + 1 < f.H)
-                            dst[1] = v.y;
-                        if (y + 2 < f.H)
-                            dst[2] = v.z;
+        for (int t = 0; t < S; ++t)
+            acc[t] = 0.0f;
+        lds_rows<S>(lo, lds, wv, lane);
+        // step c: taps c*S .. c*S+S-1 on X_{w+c}, X_{w+c+1}; then publish
+        // X_{NW+1+c} from staging register set c % P and refill that set
+        auto step = [&](int c, float4 (&st)[G::LPL]) {
+            // weights first: LDS returns in order, so the first products (with
+            // `lo` and these weights) need not wait for the rows of `hi`
+            if (w_lds) {
+#pragma unroll
+                for (int u = 0; u < S; u += 4) {
+                    const float4 q = wl4[(c * S + u) / 4];
+                    wr[u] = q.x;
+                    wr[u + 1] = q.y;
+                    wr[u + 2] = q.z;
+                    wr[u + 3] = q.w;
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < S; ++u)
+                    wr[u] = to_vgpr(w[c * S + u]);
+            }
+            lds_rows<S>(hi, lds, (wv + c + 1) % G::Q, lane);
+            fma_chunk_v<S>(acc, lo, hi, wr);
+#pragma unroll
+            for (int t = 0; t < S; ++t) {
+                // the accumulators pass through an empty asm statement, so the
+                // multiply-adds cannot sink past the barrier below (two steps'
+                // operands live at once would cost occupancy)
+                asm volatile("" : "+v"(acc[t]));
+                lo[t] = hi[t];
+            }
+            const int j = NW + 1 + c;
+            if (j < nload)
+                stage_store<S, NW>(lds4, j % G::Q, st, tid);
+            stage_load<S, NW, WIDE>(st, rs, tid, base, min(j + P, nload - 1), n, stride, col0);
+            __syncthreads();
+        };
+        // whole groups of P steps issue the same loads every iteration, so each
+        // wait covers exactly the oldest staged chunk
+        int c = 0;
+        for (; c + P <= nch; c += P) {
+#pragma unroll
+            for (int k = 0; k < P; ++k)
+                step(c + k, stg[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < P - 1; ++k)
+            if (c + k < nch)
+                step(c + k, stg[k]);
+
+        if (PASS == 1) {
+            // T is stored transposed: output column x is a row of T.  The tile
+            // (64 columns x NW*S outputs) goes through LDS (the ring is free after
+            // the last barrier) so that consecutive threads write consecutive
+            // 16-byte pieces of each T row; a direct store from the accumulators
+            // would scatter every store instruction over 64 rows of T.
+            constexpr int TS = NW * S + 4;   // LDS floats per column (padded)
+            constexpr int Q4 = NW * S / 4;   // 16-byte pieces per column
+            constexpr int NQ = 64 * Q4;
+            static_assert(64 * TS <= G::Q * S * 64, "transpose tile fits the ring");
+            float* tr = reinterpret_cast<float*>(lds4);
+#pragma unroll
+            for (int t = 0; t < S; t += 4)
+                *reinterpret_cast<float4*>(tr + lane * TS + wv * S + t) =
+                    make_float4(acc[t], acc[t + 1], acc[t + 2], acc[t + 3]);
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < (NQ + G::NT - 1) / G::NT; ++i) {
+                const int q = tid + i * G::NT;
+                if (NQ % G::NT == 0 || q < NQ) {
+                    const int cx = q / Q4, y4 = q - cx * Q4;
+                    const int x = col0 + cx, y = y0 + 4 * y4;
+                    if (x < f.W && y < f.H) {
+                        const float4 v = *reinterpret_cast<const float4*>(tr + cx * TS + 4 * y4);
+                        float* __restrict__ dst = f.T + ((long long)p * f.W + x) * f.pitch + y;
+                        if (y + 4 <= f.H) {
+                            *reinterpret_cast<float4*>(dst) = v;
+                        } else {
+                            dst[0] = v.x;
+                            if (y + 1 < f.H)
+                                dst[1] = v.y;
+                            if (y + 2 < f.H)
+                                dst[2] = v.z;
+                        }
                     }
                 }
             }
-        }
-    } else {
-        // L rows are contiguous along the lanes: direct coalesced stores
-        const int col = col0 + lane;
-        const int o0 = y0 + wv * S;  // first output of this wave along the blur
-        if (col < f.H) {
-            float* __restrict__ dstp = f.L + (long long)p * f.W * f.pitch;
+        } else {
+            // L rows are contiguous along the lanes: direct coalesced stores
+            const int col = col0 + lane;
+            const int o0 = y0 + wv * S;  // first output of this wave along the blur
+            if (col < f.H) {
+                float* __restrict__ dstp = f.L + (long long)p * f.W * f.pitch;
 #pragma unroll
-            for (int t = 0; t < S; ++t)
-                if (o0 + t < f.W)
-                    dstp[(long long)(o0 + t) * f.pitch + col] = acc[t];
+                for (int t = 0; t < S; ++t)
+                    if (o0 + t < f.W)
+                        dstp[(long long)(o0 + t) * f.pitch + col] = acc[t];
+            }
         }
-    }
+    }   // planes of the tile
 }
 
 // Lanes i-1 and i+1 of a wave.  Lanes 0 and 63 receive 0 from outside the
@@ -774,12 +781,14 @@ struct KernelSet {
     const void* pass2;
     const void* nms[2];     // [debug planes]
     int S, R, NW, BI, BN, NWN;
+    int group;              // staged blur: a tile takes several planes (cost-balanced)
 };
 
-template <int S, int NW, int P, int BN, int NWN>
+template <int S, int NW, int P, int BN, int NWN, int GROUP = 0>
 static KernelSet make_lds_set()
 {
     KernelSet k;
+    k.group = GROUP;
     k.pass1 = reinterpret_cast<const void*>(&k_blur_lds<1, S, NW, P, false>);
     k.pass1w = reinterpret_cast<const void*>(&k_blur_lds<1, S, NW, P, true>);
     k.pass2 = reinterpret_cast<const void*>(&k_blur_lds<2, S, NW, P, true>);
@@ -798,6 +807,7 @@ template <int S, int R, int NW, int BI, int BN, int NWN>
 static KernelSet make_set()
 {
     KernelSet k;
+    k.group = 0;
     k.pass1w = nullptr;
     k.pass1 = reinterpret_cast<const void*>(&k_pass1<S, R, NW, BI>);
     k.pass2 = reinterpret_cast<const void*>(&k_pass2<S, R, NW, BI>);
@@ -814,7 +824,11 @@ static KernelSet make_set()
 
 // Variants available to the autotuner: (S outputs per lane, R ring buffers,
 // waves per workgroup, strips per wave) for the blur passes and (rows per
-// wave, waves) for the local-maximum kernel.
+// wave, waves) for the local-maximum kernel.  The last three run the staged
+// kernels of variants 8, 9 and 13 with cost-balanced tiles: each tile takes
+// a run of consecutive planes whose tap chunks add up to about those of the
+// widest plane (the kernels are the same; only the host's tile tables
+// differ), so every workgroup runs a long chain of steps.
 static const KernelSet kSets[] = {
     make_set<12, 4, 4, 1, 4, 4>(),
     make_set<12, 6, 4, 1, 4, 4>(),
@@ -830,6 +844,9 @@ static const KernelSet kSets[] = {
     make_lds_set<8, 8, 2, 4, 4>(),
     make_lds_set<16, 8, 2, 4, 4>(),
     make_lds_set<16, 2, 2, 4, 4>(),
+    make_lds_set<16, 4, 2, 4, 4, 1>(),
+    make_lds_set<16, 4, 4, 4, 4, 1>(),
+    make_lds_set<16, 2, 2, 4, 4, 1>(),
 };
 
 }  // namespace dog
@@ -849,6 +866,8 @@ void dogk_variant_geometry(int v, int* S, int* NW, int* BI, int* BN, int* NWN)
 }
 
 int dogk_variant_ring(int v) { return dog::kSets[v].R; }
+
+int dogk_variant_group(int v) { return dog::kSets[v].group; }
 
 // Launch pass 1 and pass 2 on `stream`, one workgroup per tile of each
 // table (a pass with no tiles is not launched; pass 1 also clears the

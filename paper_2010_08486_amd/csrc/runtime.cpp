@@ -199,6 +199,7 @@ static Variant variant_geometry(int v)
 {
     Variant g;
     dogk_variant_geometry(v, &g.S, &g.NW, &g.BI, &g.BN, &g.NWN);
+    g.group = dogk_variant_group(v);
     return g;
 }
 
@@ -258,6 +259,70 @@ static std::vector<double> dct_transfer(const std::vector<double>& half, int N)
         H[k] = half[0] + 2.0 * sum;
     }
     return H;
+}
+
+// ---- blur tiles: which planes one workgroup takes
+
+std::vector<PlaneRun> plane_runs(const Plan& P, const std::vector<int>& planes, int S, bool group)
+{
+    // cost of a plane in a tile: its tap chunks, plus one for staging the
+    // band's first rows
+    auto cost = [&](int p) { return (2 * P.r[p] + S) / S + 1; };
+    std::vector<PlaneRun> runs;
+    if (!group) {
+        for (int p : planes)
+            runs.push_back({p, 1, cost(p)});
+        return runs;
+    }
+    // Cut the planes (widest first) into runs of consecutive planes: the
+    // fewest runs whose longest chain stays within 15 % of the widest
+    // plane's, and among those cuts the one with the shortest longest chain.
+    int cmax = 0;
+    for (int p : planes)
+        cmax = std::max(cmax, cost(p));
+    size_t i = 0;
+    while (i < planes.size()) {
+        // a segment of consecutive plane indices
+        size_t j = i + 1;
+        while (j < planes.size() && planes[j] == planes[j - 1] - 1)
+            ++j;
+        const int m = (int)(j - i);
+        std::vector<int> c(m), pre(m + 1, 0);
+        for (int q = 0; q < m; ++q) {
+            c[q] = cost(planes[i + q]);
+            pre[q + 1] = pre[q] + c[q];
+        }
+        // best[g][q]: the smallest longest run over cuts of the first q
+        // planes into g runs; cut[g][q]: where the last run starts
+        const int INF = 1 << 30;
+        std::vector<std::vector<int>> best(m + 1, std::vector<int>(m + 1, INF)),
+            cut(m + 1, std::vector<int>(m + 1, 0));
+        best[0][0] = 0;
+        int g_use = m;
+        for (int g = 1; g <= m; ++g) {
+            for (int q = g; q <= m; ++q)
+                for (int s0 = g - 1; s0 < q; ++s0) {
+                    const int v = std::max(best[g - 1][s0], pre[q] - pre[s0]);
+                    if (v < best[g][q]) {
+                        best[g][q] = v;
+                        cut[g][q] = s0;
+                    }
+                }
+            if (best[g][m] * 100 <= cmax * 115) {
+                g_use = g;
+                break;
+            }
+        }
+        std::vector<PlaneRun> seg;
+        for (int g = g_use, q = m; g > 0; --g) {
+            const int s0 = cut[g][q];
+            seg.push_back({planes[i + s0], q - s0, pre[q] - pre[s0]});
+            q = s0;
+        }
+        runs.insert(runs.end(), seg.rbegin(), seg.rend());
+        i = j;
+    }
+    return runs;
 }
 
 static constexpr size_t kRecBytes = sizeof(CandRec);
@@ -485,23 +550,25 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
         // an exhausted list's slot is filled from the longest remaining list.
         const int band = V.band();
         struct Raw {
-            int frame, plane, n_cb, n_band, radius;
+            int frame, plane, count, n_cb, n_band, cost;
         };
         std::vector<Raw> r1, r2, r3;
         for (int f = 0; f < n; ++f) {
             const int H = frames[f].H, W = frames[f].W;
-            for (int p = 0; p < n_g; ++p) {
-                if (std::find(dctp[f].begin(), dctp[f].end(), p) != dctp[f].end())
-                    continue;   // blurred in the transform domain
-                r1.push_back({f, p, (W + 63) / 64, (H + band - 1) / band, P.r[p]});
-                r2.push_back({f, p, (H + 63) / 64, (W + band - 1) / band, P.r[p]});
+            std::vector<int> direct;   // planes blurred directly, widest first
+            for (int p = n_g - 1; p >= 0; --p)
+                if (std::find(dctp[f].begin(), dctp[f].end(), p) == dctp[f].end())
+                    direct.push_back(p);
+            for (const PlaneRun& u : plane_runs(P, direct, V.S, V.group != 0)) {
+                r1.push_back({f, u.top, u.count, (W + 63) / 64, (H + band - 1) / band, u.cost});
+                r2.push_back({f, u.top, u.count, (H + 63) / 64, (W + band - 1) / band, u.cost});
             }
-            r3.push_back({f, 0, (H + DOG_NMS_COLS - 1) / DOG_NMS_COLS,
+            r3.push_back({f, 0, 1, (H + DOG_NMS_COLS - 1) / DOG_NMS_COLS,
                           (W + V.nms_band() - 1) / V.nms_band(), 0});
         }
         auto by_cost = [](const Raw& a, const Raw& b) {
-            if (a.radius != b.radius)
-                return a.radius > b.radius;
+            if (a.cost != b.cost)
+                return a.cost > b.cost;
             return a.frame < b.frame;
         };
         std::stable_sort(r1.begin(), r1.end(), by_cost);
@@ -518,7 +585,7 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
                             Tile t;
                             t.frame = (uint16_t)r.frame;
                             t.plane = (uint8_t)r.plane;
-                            t.pad_ = 0;
+                            t.n_planes = (uint8_t)r.count;
                             t.cb = (uint16_t)cb;
                             t.band = (uint16_t)bnd;
                             per[x].push_back(t);

@@ -73,9 +73,19 @@ struct FrameIn {
 // Geometry of one tiling variant.
 struct Variant {
     int S, NW, BI, BN, NWN;
+    int group;   // blur tiles take runs of planes (cost-balanced)
     int band() const { return S * NW * BI; }
     int nms_band() const { return BN * NWN; }
 };
+
+// A run of consecutive planes that one blur workgroup takes in turn: top,
+// top-1, ..., top-count+1 (widest first); cost in tap chunks.
+struct PlaneRun {
+    int top, count, cost;
+};
+// The planes (indices, widest first) cut into runs: one plane each, or
+// (group) cost-balanced runs of consecutive planes.
+std::vector<PlaneRun> plane_runs(const Plan& P, const std::vector<int>& planes, int S, bool group);
 
 const char* last_error();
 int check_image(const void* p, int64_t h, int64_t w, int64_t stride);
@@ -93,6 +103,7 @@ extern "C" {
 int dogk_num_variants();
 void dogk_variant_geometry(int v, int* S, int* NW, int* BI, int* BN, int* NWN);
 int dogk_variant_ring(int v);
+int dogk_variant_group(int v);
 hipError_t dogk_launch_passes(int variant, const dog::LaunchArgs* args, int grid1, int grid2,
                               int wide1, hipStream_t stream, hipEvent_t* ev);
 hipError_t dogk_launch_nms_ev(int variant, const dog::LaunchArgs* args, int grid3, int debug,
