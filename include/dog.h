@@ -360,21 +360,24 @@ int dog_set_graph_mode(dog_context* ctx, int32_t on);
  * timed), with the same kernels and arguments. */
 int dog_set_profiling(dog_context* ctx, int32_t on);
 int dog_kernel_times(dog_context* ctx, double* ms_out, int64_t* launches_out);
-/* The same for every kernel of a sequence (cap >= 7): pass 1, pass 2, local
- * maxima, then the transform-domain blur's forward 1, forward 2, inverse 1
- * and inverse 2 (0 where the sequences had no such work). */
+/* The same for every kernel of a sequence (cap >= 5): pass 1, pass 2, local
+ * maxima, then the transform-domain blur's pass 1 and pass 2 (0 where the
+ * sequences had no such work). */
 int dog_kernel_times_all(dog_context* ctx, double* ms_out, int32_t cap, int64_t* launches_out);
 
 /* Transform-domain blur (Sec. 4.1, the convolution taken through a fast
  * Fourier transform, whose cost does not grow with sigma): on frames whose
  * sides are powers of two in [64, 2048], ladder planes whose kernels have
- * at least min_taps taps (2 r + 1) are blurred as a product in the type-II
- * cosine transform domain, which is exact for the half-sample symmetric
- * border: the frame's 2-D transform is taken once, each such plane costs one
- * inverse transform (fp32 FFTs of the lines in LDS, FP64 transfer functions
- * of the kernels rounded once to fp32).  The planes agree with the direct
- * blur within the detector's plane tolerance, not bit for bit.  min_taps 0
- * (the default) blurs every plane directly.  DOG_EINVAL for min_taps < 0. */
+ * at least min_taps taps (2 r + 1) are blurred, in each of the two
+ * separable passes, as a product in the type-II cosine transform domain of
+ * the lines, which is exact for the half-sample symmetric border: one
+ * forward transform of the frame's columns serves every such plane in the
+ * first pass, and each plane then costs one inverse transform per pass and
+ * one forward one in the second (fp32 FFTs of the lines in LDS, FP64
+ * transfer functions of the kernels rounded once to fp32).  The planes agree
+ * with the direct blur within the detector's plane tolerance, not bit for
+ * bit.  min_taps 0 (the default) blurs every plane directly.  DOG_EINVAL for
+ * min_taps < 0. */
 int dog_set_dct(dog_context* ctx, int32_t min_taps);
 
 

@@ -336,13 +336,13 @@ class Context:
         _check(lib().dog_kernel_times(self._h, ms, ctypes.byref(n)))
         return list(ms), n.value
 
-    KERNEL_NAMES = ("pass1", "pass2", "nms", "dct_fwd1", "dct_fwd2", "dct_inv1", "dct_inv2")
+    KERNEL_NAMES = ("pass1", "pass2", "nms", "fft1", "fft2")
 
     def kernel_times_all(self):
         """(ms per kernel summed, in KERNEL_NAMES order, number of launch sequences)."""
-        ms = (ctypes.c_double * 7)()
+        ms = (ctypes.c_double * len(self.KERNEL_NAMES))()
         n = ctypes.c_int64(0)
-        _check(lib().dog_kernel_times_all(self._h, ms, 7, ctypes.byref(n)))
+        _check(lib().dog_kernel_times_all(self._h, ms, len(ms), ctypes.byref(n)))
         return list(ms), n.value
 
     def set_dct(self, min_taps: int) -> None:

@@ -207,7 +207,7 @@ int dog_set_dct(dog_context* ctx, int32_t min_taps)
 int dog_kernel_times_all(dog_context* ctx, double* ms_out, int32_t cap, int64_t* launches_out)
 {
     if (!ctx || !ms_out || cap < DOG_NKERNELS) {
-        set_error("invalid argument (ms_out needs room for 7 kernels)");
+        set_error("invalid argument (ms_out needs room for 5 kernels)");
         return DOG_EINVAL;
     }
     for (int i = 0; i < DOG_NKERNELS; ++i)

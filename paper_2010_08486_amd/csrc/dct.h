@@ -8,35 +8,39 @@
 
 namespace dog {
 
-// `lines` lines (even) starting at line0 of one length-N transform (N a
-// power of two).  cols = 1: line l is column l of `in` (row-major, rows
-// in_pitch floats apart, N rows); 0: line l is row l (N values).  Output
-// line l is the row out + l * out_pitch.  Inverse jobs of the first inverse
-// step scale the input by hline[line] * hpos[position].
-struct DctJob {
+constexpr int kFftLines = 4;        // lines per job (two complex sequences)
+constexpr int kFftMaxN = 2048;      // longest line
+constexpr int kFftMaxPlanes = 16;   // planes one job produces from one forward transform
+
+// Blur of kFftLines consecutive lines of length N (a power of two) by the
+// kernels of n_planes planes.  Lines are columns of the input: element n of
+// line l is in[n * in_pitch + line0 + l].  Output line l of plane q is the
+// row out[q] + (line0 + l) * out_pitch (out_rows) or the column
+// out[q][n * out_pitch + line0 + l].
+struct FftJob {
     const float* in;         // NULL: the pixels of frame `frame` of the launch
-    float* out;
-    const float* hline;      // NULL: no scaling
-    const float* hpos;
     const float2* tw;        // N/2 twiddles exp(-2 pi i t / N)
     const float2* post;      // N twiddles exp(-i pi k / (2N))
     int32_t in_pitch;
-    int32_t out_pitch;
     int32_t N;
     int32_t logn;
     int32_t line0;
-    int32_t lines;           // 2^(logp + 1), (lines / 2) * N <= 4096
-    int32_t logp;
-    int32_t cols;
     int32_t frame;
-    int32_t pad_;
+    int32_t n_planes;
+    int32_t out_rows;
+    int32_t out_pitch;
+    float* out[kFftMaxPlanes];
+    const float* h[kFftMaxPlanes];   // per plane: transfer function H[k] / N, k = 0..N-1
 };
 
 }  // namespace dog
 
 extern "C" {
-size_t dogk_dct_lds_bytes(int N, int lines);
+size_t dogk_fft_lds_bytes(int N);
+// n_jobs jobs whose lines all have 2^logn values (6 <= logn <= 11).  vec:
+// every job's input rows hold its lines at 16-byte aligned addresses (pitch
+// and line0 multiples of 4, base 16-byte aligned); else 4-byte loads.
 // ev (may be NULL): start and end events of the dispatch.
-hipError_t dogk_dct(const dog::LaunchArgs* args, const dog::DctJob* d_jobs, int n_jobs,
-                    size_t lds_bytes, int inverse, hipStream_t stream, hipEvent_t* ev);
+hipError_t dogk_fft_blur(const dog::LaunchArgs* args, const dog::FftJob* d_jobs, int n_jobs,
+                         int logn, int vec, hipStream_t stream, hipEvent_t* ev);
 }

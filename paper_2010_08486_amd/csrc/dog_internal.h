@@ -101,12 +101,21 @@ struct LaunchArgs {
     FrameDesc f0;               // the frame of a one-frame launch (frames == NULL)
 };
 
-// The transform-domain blur's four launches of a sequence: job tables
-// (device) and counts, and the dynamic LDS the largest job of each needs.
-struct DctLaunch {
-    const void* jobs[4];        // forward 1, forward 2, inverse 1, inverse 2
-    int n[4];
-    size_t lds[4];
+// The transform-domain blur's launches of a sequence: for pass 1 (along y)
+// and pass 2 (along x), one launch per line length (log2 N = 6..11) with its
+// job table (device) and count, and whether every job's input allows
+// 16-byte loads.
+struct FftLaunch {
+    const void* jobs[2][6];
+    int n[2][6];
+    int vec[2];
+    int total(int pass) const
+    {
+        int t = 0;
+        for (int i = 0; i < 6; ++i)
+            t += n[pass][i];
+        return t;
+    }
 };
 
 }  // namespace dog

@@ -869,38 +869,30 @@ int dogk_variant_ring(int v) { return dog::kSets[v].R; }
 
 int dogk_variant_group(int v) { return dog::kSets[v].group; }
 
-// Launch pass 1 and pass 2 on `stream`, one workgroup per tile of each
-// table (a pass with no tiles is not launched; pass 1 also clears the
-// candidate count, so without pass-1 tiles a fill kernel does).  wide1: every
+// Launch blur pass `pass` (1 or 2) on `stream`, one workgroup per tile of
+// its table; a pass with no tiles is not launched.  Pass 1 also clears the
+// candidate count, so without pass-1 tiles a fill kernel does.  wide1: every
 // frame's rows are 16-byte aligned and its width is a multiple of 64, so
-// pass 1 may use 16-byte loads.  If ev is non-NULL, ev[2i] and ev[2i+1] take
-// the start and end of pass i+1's execution (the dispatch's own timestamps,
-// so the launch gap before a kernel is not counted).
-hipError_t dogk_launch_passes(int variant, const dog::LaunchArgs* args, int grid1, int grid2,
-                              int wide1, hipStream_t stream, hipEvent_t* ev)
+// pass 1 may use 16-byte loads.  If ev is non-NULL, ev[0] and ev[1] take the
+// start and end of the pass's execution (the dispatch's own timestamps, so
+// the launch gap before a kernel is not counted).
+hipError_t dogk_launch_pass(int variant, const dog::LaunchArgs* args, int pass, int grid,
+                            int wide1, hipStream_t stream, hipEvent_t* ev)
 {
     const dog::KernelSet& k = dog::kSets[variant];
-    const void* pass1 = wide1 && k.pass1w ? k.pass1w : k.pass1;
+    const void* fn = pass == 1 ? (wide1 && k.pass1w ? k.pass1w : k.pass1) : k.pass2;
     void* params[] = {const_cast<dog::LaunchArgs*>(args)};
-    const void* fn[2] = {pass1, k.pass2};
-    const int grid[2] = {grid1, grid2};
-    if (grid1 <= 0) {
+    if (pass == 1 && grid <= 0) {
         hipLaunchKernelGGL(dog::k_fill_u32, dim3(1), dim3(64), 0, stream, &args->cand->count, 1, 0u);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
     }
-    for (int i = 0; i < 2; ++i) {
-        if (grid[i] <= 0)
-            continue;
-        const hipError_t e =
-            ev ? hipExtLaunchKernel(fn[i], dim3(grid[i]), dim3(64 * k.NW), params, 0, stream,
-                                    ev[2 * i], ev[2 * i + 1], 0)
-               : hipLaunchKernel(fn[i], dim3(grid[i]), dim3(64 * k.NW), params, 0, stream);
-        if (e != hipSuccess)
-            return e;
-    }
-    return hipSuccess;
+    if (grid <= 0)
+        return hipSuccess;
+    return ev ? hipExtLaunchKernel(fn, dim3(grid), dim3(64 * k.NW), params, 0, stream, ev[0],
+                                   ev[1], 0)
+              : hipLaunchKernel(fn, dim3(grid), dim3(64 * k.NW), params, 0, stream);
 }
 
 // The local-maximum kernel (timed by ev[0], ev[1] when ev is non-NULL).

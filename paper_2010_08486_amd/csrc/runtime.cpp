@@ -233,14 +233,6 @@ static int ilog2(int v)
     return l;
 }
 
-// Lines per workgroup: 4096 / N (at least 4, at most 16), so a workgroup
-// holds at most 2048 complex values per line pair count (at most 40 KB of LDS
-// with the twiddles) and small transforms still fill their workgroups.
-static int dct_lines_per_job(int N)
-{
-    return std::min(16, std::max(4, 4096 / N));
-}
-
 // H[k] = w_0 + 2 sum_{j=1..r} w_j cos(pi k j / N), k = 0..N-1, from the FP64
 // half kernel (cosines by the three-term recurrence in j).
 static std::vector<double> dct_transfer(const std::vector<double>& half, int N)
@@ -325,6 +317,40 @@ std::vector<PlaneRun> plane_runs(const Plan& P, const std::vector<int>& planes, 
     return runs;
 }
 
+// Workgroup order for jobs whose neighbours share cache lines: the list is
+// cut into DOG_NXCD contiguous slices and slot b (dispatched to XCD b mod
+// DOG_NXCD) takes the next job of slice b mod DOG_NXCD, so neighbouring jobs
+// run on one XCD and its L2 fetches each line once (round-robin order would
+// have every XCD fetch the lines of all its neighbours' jobs).  An exhausted
+// slice's slots take jobs from the longest remaining slice.
+template <class T>
+static std::vector<T> xcd_order(const std::vector<T>& v)
+{
+    const size_t n = v.size();
+    size_t lo[DOG_NXCD], hi[DOG_NXCD];
+    for (int x = 0; x < DOG_NXCD; ++x) {
+        lo[x] = n * x / DOG_NXCD;
+        hi[x] = n * (x + 1) / DOG_NXCD;
+    }
+    std::vector<T> out;
+    out.reserve(n);
+    while (out.size() < n) {
+        for (int x = 0; x < DOG_NXCD && out.size() < n; ++x) {
+            int src = x;
+            if (lo[x] >= hi[x]) {
+                size_t best = 0;
+                for (int y = 0; y < DOG_NXCD; ++y)
+                    if (hi[y] - lo[y] > best) {
+                        best = hi[y] - lo[y];
+                        src = y;
+                    }
+            }
+            out.push_back(v[lo[src]++]);
+        }
+    }
+    return out;
+}
+
 static constexpr size_t kRecBytes = sizeof(CandRec);
 static constexpr uint32_t kUnpublished = 0xffffffffu;  // host-side count before a launch
 
@@ -385,13 +411,18 @@ static hipError_t enqueue_sequence(dog_context* c, hipStream_t st, const FrameDe
                            hipMemcpyHostToDevice, st);
     }
     hipEvent_t* ev = c->profiling ? c->ev : nullptr;
-    if (e == hipSuccess)
-        e = dogk_launch_passes(c->variant, &a, a.n1, a.n2, c->wide1 ? 1 : 0, st, ev);
-    // the transform-domain planes: forward 1, forward 2, inverse 1, inverse 2
-    for (int i = 0; i < 4 && e == hipSuccess; ++i)
-        if (c->dct.n[i] > 0)
-            e = dogk_dct(&a, static_cast<const DctJob*>(c->dct.jobs[i]), c->dct.n[i],
-                         c->dct.lds[i], i >= 2 ? 1 : 0, st, ev ? ev + 6 + 2 * i : nullptr);
+    // each pass: the direct planes' tiles, then the transform-domain planes'
+    // jobs (events: pass 1, pass 2, local maxima, transform 1, transform 2)
+    for (int pass = 1; pass <= 2 && e == hipSuccess; ++pass) {
+        e = dogk_launch_pass(c->variant, &a, pass, pass == 1 ? a.n1 : a.n2, c->wide1 ? 1 : 0, st,
+                             ev ? ev + 2 * (pass - 1) : nullptr);
+        const int i = pass - 1;
+        for (int lg = 0; lg < 6 && e == hipSuccess; ++lg)
+            if (c->fft.n[i][lg] > 0)
+                e = dogk_fft_blur(&a, static_cast<const FftJob*>(c->fft.jobs[i][lg]),
+                                  c->fft.n[i][lg], lg + 6, c->fft.vec[i], st,
+                                  ev ? ev + 6 + 2 * i : nullptr);
+    }
     if (e == hipSuccess)
         e = dogk_launch_nms_ev(c->variant, &a, a.n3, c->debug_planes ? 1 : 0, st,
                                ev ? ev + 4 : nullptr);
@@ -466,26 +497,22 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
     // ---- planes blurred in the transform domain: those whose kernels have
     // at least dct_min_taps taps, on frames whose sides are powers of two
     std::vector<std::vector<int>> dctp(n);
-    bool any_dct = false;
     for (int f = 0; f < n; ++f) {
         if (!dct_shape_ok(frames[f].H, frames[f].W) || c->dct_min_taps <= 0)
             continue;
         for (int p = 0; p < n_g; ++p)
             if (2 * P.r[p] + 1 >= c->dct_min_taps)
                 dctp[f].push_back(p);
-        any_dct = any_dct || !dctp[f].empty();
     }
 
-    // ---- workspace: T and L planes (transposed, pitch = H rounded to 64),
-    // and the transform of the frame where planes are taken that way
+    // ---- workspace: T and L planes (transposed, pitch = H rounded to 64)
     std::vector<long long> pitch(n), off(n);
     size_t total = 0;
     for (int f = 0; f < n; ++f) {
         pitch[f] = ((long long)frames[f].H + 63) / 64 * 64;
         const size_t plane = (size_t)frames[f].W * (size_t)pitch[f];
         off[f] = (long long)total;
-        total += 2 * (size_t)n_g * plane + ((dbg_D && f == 0) ? (size_t)P.k * plane : 0) +
-                 (dctp[f].empty() ? 0 : plane);
+        total += 2 * (size_t)n_g * plane + ((dbg_D && f == 0) ? (size_t)P.k * plane : 0);
         total = align_up(total, 64);
     }
     int rc = ctx_alloc(c, &c->planes, total * sizeof(float), "scale-space planes");
@@ -642,11 +669,11 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
                 rows2_off[f] = table_for(frames[f].W, pitch[f] * 4);
             }
         }
-        // transform-domain tables: per transform length the twiddles, per
-        // (length, plane) the scaled kernel transfer function, and the jobs
-        // of the four launches (float offsets into one host array first)
+        // transform-domain tables: per line length the twiddles, per (length,
+        // plane) the kernel's transfer function over N, and the jobs of the
+        // two launches (float offsets into one host array first)
         std::vector<float> dtab;                       // twiddles and H vectors
-        std::vector<DctJob> djobs[4];
+        std::vector<FftJob> djobs[2][6];               // per pass and log2 N - 6
         struct TabRef {
             int N, p;
             size_t at;
@@ -685,42 +712,18 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
             h_at.push_back({N, p, at});
             return at;
         };
-        // pointers into the device table are fixed up once its offset is known
+        // table pointers are fixed up once the device table's offset is known
         struct Fix {
-            int kind;
-            size_t job;
-            size_t tw, post, hl, hp;
-            bool scaled;
+            int pass, lg;
+            size_t job, tw;
+            int n_h;
+            size_t h[kFftMaxPlanes];
         };
         std::vector<Fix> fixes;
-        auto add_jobs = [&](int kind, const float* in, int in_pitch, float* out, int out_pitch,
-                            int N, int nlines, int cols, int frame, int p_scaled) {
-            const int L = dct_lines_per_job(N);
-            const size_t tw = twiddles(N);
-            size_t hl = 0, hp = 0;
-            if (p_scaled >= 0) {
-                const int Hn = frames[frame].H, Wn = frames[frame].W;
-                hl = transfer(Hn, p_scaled);   // lines are rows ky: H_y
-                hp = transfer(Wn, p_scaled);   // positions kx: H_x
-            }
-            for (int l0 = 0; l0 < nlines; l0 += L) {
-                DctJob j{};
-                j.in = in;
-                j.out = out;
-                j.in_pitch = in_pitch;
-                j.out_pitch = out_pitch;
-                j.N = N;
-                j.logn = ilog2(N);
-                j.line0 = l0;
-                j.lines = L;
-                j.logp = ilog2(L / 2);
-                j.cols = cols;
-                j.frame = frame;
-                fixes.push_back({kind, djobs[kind].size(), tw, tw + (size_t)N, hl, hp,
-                                 p_scaled >= 0});
-                djobs[kind].push_back(j);
-            }
-        };
+        const bool wide_src = key[0] != 0;   // frames' rows allow 16-byte loads
+        FftLaunch fl{};
+        fl.vec[0] = wide_src ? 1 : 0;
+        fl.vec[1] = 1;                       // T planes: pitch a multiple of 64
         for (int f = 0; f < n; ++f) {
             if (dctp[f].empty())
                 continue;
@@ -729,24 +732,57 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
             const size_t plane = (size_t)W * (size_t)pt;
             float* T0 = planes + off[f];
             float* L0 = T0 + (size_t)n_g * plane;
-            float* Ft = L0 + (size_t)n_g * plane + ((dbg_D && f == 0) ? (size_t)P.k * plane : 0);
-            float* F1 = T0 + (size_t)dctp[f][0] * plane;   // the first such plane's T storage
-            // forward: along y over the frame's columns, then along x
-            add_jobs(0, nullptr, 0, F1, (int)pt, H, W, 1, f, -1);
-            add_jobs(1, F1, (int)pt, Ft, W, W, H, 1, f, -1);
+            // pass 1: the frame's columns (lines along y, N = H) -> rows of T_p,
+            // up to kFftMaxPlanes planes per forward transform
+            for (size_t g0 = 0; g0 < dctp[f].size(); g0 += kFftMaxPlanes) {
+                const int ng = (int)std::min<size_t>(kFftMaxPlanes, dctp[f].size() - g0);
+                for (int l0 = 0; l0 < W; l0 += kFftLines) {
+                    FftJob j{};
+                    j.in = nullptr;
+                    j.N = H;
+                    j.logn = ilog2(H);
+                    j.line0 = l0;
+                    j.frame = f;
+                    j.n_planes = ng;
+                    j.out_rows = 1;
+                    j.out_pitch = (int)pt;
+                    const int lg = ilog2(H) - 6;
+                    Fix fx{0, lg, djobs[0][lg].size(), twiddles(H), ng, {}};
+                    for (int q = 0; q < ng; ++q) {
+                        const int p = dctp[f][g0 + q];
+                        j.out[q] = T0 + (size_t)p * plane;
+                        fx.h[q] = transfer(H, p);
+                    }
+                    fixes.push_back(fx);
+                    djobs[0][lg].push_back(j);
+                }
+            }
+            // pass 2: per plane, the columns of T_p (lines along x, N = W) ->
+            // columns of L_p
             for (int p : dctp[f]) {
-                float* G = T0 + (size_t)p * plane;
-                add_jobs(2, Ft, W, G, W, W, H, 0, f, p);
-                add_jobs(3, G, W, L0 + (size_t)p * plane, (int)pt, H, W, 1, f, -1);
+                for (int l0 = 0; l0 < H; l0 += kFftLines) {
+                    FftJob j{};
+                    j.in = T0 + (size_t)p * plane;
+                    j.in_pitch = (int)pt;
+                    j.N = W;
+                    j.logn = ilog2(W);
+                    j.line0 = l0;
+                    j.frame = f;
+                    j.n_planes = 1;
+                    j.out_rows = 0;
+                    j.out_pitch = (int)pt;
+                    j.out[0] = L0 + (size_t)p * plane;
+                    const int lg = ilog2(W) - 6;
+                    Fix fx{1, lg, djobs[1][lg].size(), twiddles(W), 1, {}};
+                    fx.h[0] = transfer(W, p);
+                    fixes.push_back(fx);
+                    djobs[1][lg].push_back(j);
+                }
             }
         }
-        DctLaunch dl{};
-        for (int i = 0; i < 4; ++i) {
-            dl.n[i] = (int)djobs[i].size();
-            for (const DctJob& j : djobs[i])
-                dl.lds[i] = std::max(dl.lds[i], dogk_dct_lds_bytes(j.N, j.lines));
-        }
-        (void)any_dct;
+        for (int i = 0; i < 2; ++i)
+            for (int lg = 0; lg < 6; ++lg)
+                fl.n[i][lg] = (int)djobs[i][lg].size();
 
         const long long t1 = (long long)tb1.size(), t2 = (long long)tb2.size(),
                         t3 = (long long)tb3.size();
@@ -763,12 +799,13 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
         const size_t o_t3 = align_up(o_t2 + sizeof(Tile) * tb2.size(), 256);
         const size_t o_rows = align_up(o_t3 + sizeof(Tile) * tb3.size(), 256);
         const size_t o_dtab = align_up(o_rows + sizeof(int) * rowtab.size(), 256);
-        size_t o_djobs[4];
+        size_t o_djobs[2][6];
         size_t o_end = align_up(o_dtab + sizeof(float) * dtab.size(), 256);
-        for (int i = 0; i < 4; ++i) {
-            o_djobs[i] = o_end;
-            o_end = align_up(o_end + sizeof(DctJob) * djobs[i].size(), 256);
-        }
+        for (int i = 0; i < 2; ++i)
+            for (int lg = 0; lg < 6; ++lg) {
+                o_djobs[i][lg] = o_end;
+                o_end = align_up(o_end + sizeof(FftJob) * djobs[i][lg].size(), 256);
+            }
         const size_t tbytes = o_end;
         if ((rc = ctx_alloc(c, &c->tables, tbytes, "launch tables")) != DOG_OK)
             return rc;
@@ -801,18 +838,21 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
         {
             const float* dt_f = reinterpret_cast<const float*>(dt + o_dtab);
             for (const Fix& fx : fixes) {
-                DctJob& j = djobs[fx.kind][fx.job];
+                FftJob& j = djobs[fx.pass][fx.lg][fx.job];
                 j.tw = reinterpret_cast<const float2*>(dt_f + fx.tw);
-                j.post = reinterpret_cast<const float2*>(dt_f + fx.post);
-                j.hline = fx.scaled ? dt_f + fx.hl : nullptr;
-                j.hpos = fx.scaled ? dt_f + fx.hp : nullptr;
+                j.post = reinterpret_cast<const float2*>(dt_f + fx.tw + (size_t)j.N);
+                for (int q = 0; q < fx.n_h; ++q)
+                    j.h[q] = dt_f + fx.h[q];
             }
-            for (int i = 0; i < 4; ++i) {
-                std::memcpy(h + o_djobs[i], djobs[i].data(), sizeof(DctJob) * djobs[i].size());
-                dl.jobs[i] = dt + o_djobs[i];
-            }
+            for (int i = 0; i < 2; ++i)
+                for (int lg = 0; lg < 6; ++lg) {
+                    djobs[i][lg] = xcd_order(djobs[i][lg]);
+                    std::memcpy(h + o_djobs[i][lg], djobs[i][lg].data(),
+                                sizeof(FftJob) * djobs[i][lg].size());
+                    fl.jobs[i][lg] = dt + o_djobs[i][lg];
+                }
         }
-        c->dct = dl;
+        c->fft = fl;
         DOG_HIP(hipMemcpyAsync(c->tables.p, h, tbytes, hipMemcpyHostToDevice, c->stream));
         DOG_HIP(hipStreamSynchronize(c->stream));
 
@@ -924,8 +964,8 @@ int collect_frames(dog_context* c, const Plan& P, std::vector<std::vector<dog_bl
     if (c->profiling) {
         // kernels that were launched: pass 1 and 2 when they had tiles, the
         // local maxima, the transform-domain launches that had jobs
-        const bool ran[DOG_NKERNELS] = {c->args.n1 > 0, c->args.n2 > 0, true, c->dct.n[0] > 0,
-                                        c->dct.n[1] > 0, c->dct.n[2] > 0, c->dct.n[3] > 0};
+        const bool ran[DOG_NKERNELS] = {c->args.n1 > 0, c->args.n2 > 0, true,
+                                        c->fft.total(0) > 0, c->fft.total(1) > 0};
         for (int i = 0; i < DOG_NKERNELS; ++i) {
             if (!ran[i])
                 continue;

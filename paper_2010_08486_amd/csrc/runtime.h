@@ -12,7 +12,7 @@
 #include "dog.h"
 #include "dog_internal.h"
 
-#define DOG_NKERNELS 7
+#define DOG_NKERNELS 5
 
 namespace dog {
 
@@ -104,8 +104,8 @@ int dogk_num_variants();
 void dogk_variant_geometry(int v, int* S, int* NW, int* BI, int* BN, int* NWN);
 int dogk_variant_ring(int v);
 int dogk_variant_group(int v);
-hipError_t dogk_launch_passes(int variant, const dog::LaunchArgs* args, int grid1, int grid2,
-                              int wide1, hipStream_t stream, hipEvent_t* ev);
+hipError_t dogk_launch_pass(int variant, const dog::LaunchArgs* args, int pass, int grid,
+                            int wide1, hipStream_t stream, hipEvent_t* ev);
 hipError_t dogk_launch_nms_ev(int variant, const dog::LaunchArgs* args, int grid3, int debug,
                               hipStream_t stream, hipEvent_t* ev);
 hipError_t dogk_launch_nms(int variant, const dog::LaunchArgs* args, int grid3, int max_gauss,
@@ -183,7 +183,7 @@ struct dog_context {
     std::vector<long long> graph_key;
     std::vector<long long> seen_key;   // layout of the previous call
     dog::LaunchArgs args;
-    dog::DctLaunch dct{};          // transform-domain launches of the current tables
+    dog::FftLaunch fft{};          // transform-domain launches of the current tables
     int n_gauss = 0;
     bool debug_planes = false;     // the current tables write the DoG planes
     bool wide1 = false;            // every frame of the tables allows 16-byte row loads
