@@ -38,7 +38,7 @@ Also printed in the same JSON line:
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-batch] [--no-mixed]
                     [--no-serve] [--no-paper] [--serve-seconds S] [--no-cpu] [--variant V]
-                    [--inflight N] [--only paper|preprocess]
+                    [--dct MIN_TAPS] [--inflight N] [--only paper|preprocess]
 """
 from __future__ import annotations
 
@@ -75,10 +75,11 @@ def kernel_source_hash() -> str:
     return kernel_hash()
 
 
-def measured_traffic(kernel: str, variant: int):
-    """HBM bytes per launch of `kernel` in kernel variant `variant` from the
-    committed rocprofv3 counter summary, if it was taken on the current kernel
-    build and covers that variant (else None)."""
+def measured_traffic(kernel: str, variant: int, min_taps: int = 0):
+    """HBM bytes per launch of `kernel` in kernel variant `variant` at
+    transform threshold `min_taps` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel build and covers that
+    configuration (else None)."""
     if not os.path.exists(PROFILE_COUNTERS):
         return None
     vals = {}
@@ -89,7 +90,7 @@ def measured_traffic(kernel: str, variant: int):
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    key = "v%d.%s_hbm_bytes_per_launch" % (variant, kernel)
+    key = "v%d.m%d.%s_hbm_bytes_per_launch" % (variant, min_taps, kernel)
     return float(vals[key]) if key in vals else None
 
 
@@ -138,6 +139,37 @@ def cpu_model() -> str:
     except OSError:
         pass
     return "unknown"
+
+
+def blur_flops(radii, H, W, min_taps, merged):
+    """Algorithmic FP32 flops per launch of the blur kernels of one H x W
+    frame: 2 per tap and output pixel for the planes blurred directly; for
+    the planes taken in the cosine-transform domain (kernels of at least
+    min_taps taps) the transforms' flops, counted per job of two lines of N
+    values as 5 N log2 N per complex FFT (one forward per job, one inverse
+    per plane) plus 8 N for the cosine coefficients and 14 N per plane for
+    the inverse sequence.  Pass 1's jobs take the frame's columns (N = H,
+    W / 2 jobs, every transform plane from one forward transform); pass 2's
+    the planes' rows (N = W, H / 2 jobs per plane).  merged: the jobs run in
+    the blur passes' launches (their flops count there), else in fft1 / fft2."""
+    import math
+    taps = [2 * int(r) + 1 for r in radii]
+    tr = [t for t in taps if min_taps > 0 and t >= min_taps]
+    direct = 2.0 * (sum(taps) - sum(tr)) * H * W
+    n_tr = len(tr)
+
+    def job(N, planes):
+        return 5.0 * N * math.log2(N) * (1 + planes) + 8.0 * N + 14.0 * N * planes
+
+    f1 = (W / 2) * job(H, n_tr) if n_tr else 0.0
+    f2 = n_tr * (H / 2) * job(W, 1) if n_tr else 0.0
+    out = {"pass1": direct, "pass2": direct, "nms": 0.0, "fft1": f1, "fft2": f2,
+           "merged": merged}
+    if merged:
+        out["pass1"] += f1
+        out["pass2"] += f2
+        out["fft1"] = out["fft2"] = 0.0
+    return out
 
 
 def cpu_baseline(img, prm, k, budget_s=10.0):
@@ -201,7 +233,7 @@ def bench_prune(dog, torch, ctx, t_img, prm, reps=50):
     return out
 
 
-def bench_mixed(dog, torch, ctx, prm, k, frames, steps):
+def bench_mixed(dog, torch, ctx, prm, k, frames, steps, tune_cache):
     """Uneven batch of 128 frames: one batched launch sequence vs a launch per
     frame (device frames), and the server at saturation vs the plain host
     entry point frame by frame (host frames)."""
@@ -209,10 +241,12 @@ def bench_mixed(dog, torch, ctx, prm, k, frames, steps):
     dfr = [torch.from_numpy(f).to(dev) for f in frames]
     tot = sum(f.shape[0] * f.shape[1] for f in frames) * k / 1e6
     shapes = sorted({f.shape for f in frames}, key=lambda s: s[0] * s[1])
-    choice = {}
-    for shp in shapes:   # the autotuner picks a variant per frame size
+    choice, transform = {}, {}
+    for shp in shapes:   # the autotuner picks a variant and transform threshold per frame size
         f = next(t for t in dfr if tuple(t.shape) == shp)
         choice["%dx%d" % shp] = ctx.autotune(f, prm, reps=3)[0]
+        transform["%dx%d" % shp] = ctx.autotune_transform(prm, shp[0], shp[1])
+    ctx.autotune_save(tune_cache)   # the servers' slots load the same choices
     torch.cuda.synchronize()
     ctx.detect_batch(dfr, prm)
     ctx.detect_batch(dfr, prm)
@@ -244,7 +278,7 @@ def bench_mixed(dog, torch, ctx, prm, k, frames, steps):
     def served(fr, reps=2):
         """Time the server on all frames submitted at once; the first pass
         warms its pinned request buffers and the slots' workspaces."""
-        sv = dog.Server(prm, max_batch_frames=32)
+        sv = dog.Server(prm, max_batch_frames=32, tune_cache=tune_cache)
         try:
             best, st = None, None
             for _ in range(reps):
@@ -266,6 +300,7 @@ def bench_mixed(dog, torch, ctx, prm, k, frames, steps):
     del dfr
     return {"frames": len(frames), "mpixel_scales": round(tot, 1),
             "autotuned_variant_per_shape": choice,
+            "autotuned_transform_min_taps_per_shape": transform,
             "batched_mpx_scales_per_s": round(tot / tb, 1),
             "per_frame_device_mpx_scales_per_s": round(tot / tp, 1),
             "batched_over_per_frame_device": round(tp / tb, 3),
@@ -294,8 +329,10 @@ def bench_paper_config(dog, torch, t_img, steps, nf):
     streams = [torch.cuda.Stream() for _ in range(nf)]
     try:
         v, _ = ctxs[0].autotune(t_img, prm, reps=3)
+        mt = ctxs[0].autotune_transform(prm, H, W)
         for c, st in zip(ctxs, streams):
             c.set_variant(v)
+            c.set_dct(mt)
             for _ in range(3):
                 c.detect_device(t_img, prm, stream=st)
         torch.cuda.synchronize()
@@ -311,15 +348,18 @@ def bench_paper_config(dog, torch, t_img, steps, nf):
         ctxs[0].set_profiling(True)
         for _ in range(20):
             ctxs[0].detect_device(t_img, prm)
-        kms, n = ctxs[0].kernel_times()
+        kms, n = ctxs[0].kernel_times_all()
         taps = int((2 * info["radii"] + 1).sum())
+        avg = [m / max(n, 1) for m in kms]
+        fl = blur_flops(info["radii"], H, W, mt, merged=avg[3] == 0.0 and avg[4] == 0.0)
         return {"ladder": "arithmetic n_bin=10, sigma 1..30, truncate 5, coalesce",
                 "dog_planes": k, "taps_per_pass": taps, "variant": v,
+                "transform_min_taps": mt,
                 "mpx_scales_per_s": round(H * W * k / dt / 1e6, 1),
                 "ms_per_frame": round(dt * 1e3, 4),
-                "kernel_avg_us": {nm: round(m / max(n, 1) * 1e3, 2)
-                                  for nm, m in zip(("pass1", "pass2", "nms"), kms)},
-                "blur_tflops": round(2.0 * taps * H * W / (kms[0] / max(n, 1) * 1e-3) / 1e12, 2),
+                "kernel_avg_us": {nm: round(m * 1e3, 2)
+                                  for nm, m in zip(dog.Context.KERNEL_NAMES, avg)},
+                "pass1_tflops": round(fl["pass1"] / (avg[0] * 1e-3) / 1e12, 2),
                 "blobs": int(len(blobs))}
     finally:
         for c in ctxs:
@@ -379,13 +419,14 @@ def bench_preprocess(dog, torch, img, prm, k, steps, nf):
             c.close()
 
 
-def bench_serving(dog, prm, k, pool, rate, seconds, budget=0):
+def bench_serving(dog, prm, k, pool, rate, seconds, budget=0, tune_cache=None):
     """The server fed by a Poisson stream: frames drawn in turn from the pool
     of uneven frames, submitted at their arrival times.  budget: the
-    admission budget in bytes (0: the server's default)."""
+    admission budget in bytes (0: the server's default); tune_cache: the
+    autotuner's choices for the slots (dog_autotune_save), or None."""
     import synth
     arrivals = synth.poisson_arrivals(rate=rate, duration=seconds)
-    sv = dog.Server(prm, max_batch_frames=16, hbm_budget_bytes=budget)
+    sv = dog.Server(prm, max_batch_frames=16, hbm_budget_bytes=budget, tune_cache=tune_cache)
     try:
         for f in pool[:8]:
             sv.wait(sv.submit(f))
@@ -440,6 +481,9 @@ def main() -> int:
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--variant", type=int, default=-1)
+    ap.add_argument("--dct", type=int, default=-1,
+                    help="transform threshold in kernel taps (0: every plane direct; "
+                         "-1: the autotuner's choice)")
     ap.add_argument("--inflight", type=int, default=3,
                     help="frames in flight in the timed steps (contexts and streams used in turn)")
     ap.add_argument("--pmc-workload", type=int, default=0,
@@ -476,10 +520,18 @@ def main() -> int:
     tune = None
     if args.variant >= 0:
         ctx.set_variant(args.variant)
-    elif not pmc:
+    if args.dct >= 0:
+        ctx.set_dct(args.dct)
+    if args.variant < 0 and not pmc:
         v, us = ctx.autotune(t_img, prm, reps=5)
         tune = {"variant": v, "geometry": dog.variant_info(v),
                 "kernel_us_per_variant": [round(u, 2) for u in us]}
+    variant = tune["variant"] if tune else args.variant
+    min_taps = ctx.autotune_transform(prm, H, W)   # the pinned one, else the tuned one
+    if tune:
+        tune["transform_min_taps"] = min_taps
+        tune["transform_planes"] = [int(p) for p in range(k + 1)
+                                    if min_taps > 0 and 2 * radii[p] + 1 >= min_taps]
 
     if args.only:
         # one section alone (for a profile of its kernels), as its JSON line
@@ -516,7 +568,8 @@ def main() -> int:
         return 2
     ctxs = [ctx] + [dog.Context(0) for _ in range(nf - 1)]
     for c in ctxs[1:]:
-        c.set_variant(tune["variant"] if tune else args.variant)
+        c.set_variant(variant)
+        c.set_dct(min_taps)
     streams = [torch.cuda.Stream(device=dev) for _ in range(nf)]
     torch.cuda.synchronize()
     for _ in range(args.warmup):
@@ -560,8 +613,16 @@ def main() -> int:
         ctx.detect_device(t_img, prm)
     torch.cuda.synchronize()
     dt_eager = time.perf_counter() - t1
-    kms, nseq = ctx.kernel_times()
+    kms, nseq = ctx.kernel_times_all()
+    # the same steps with every plane blurred directly (the direct stencil's
+    # roofline, beside the tuned configuration's)
+    ctx.set_dct(0)
+    ctx.set_profiling(True)
+    for _ in range(args.steps):
+        ctx.detect_device(t_img, prm)
+    kms_direct, nseq_direct = ctx.kernel_times_all()
     ctx.set_profiling(False)
+    ctx.set_dct(-1 if args.dct < 0 else args.dct)
 
     # ---- the host entry point on the same frame (host pixels: the upload
     # over PCIe is inside each call); reported beside, never as `value`
@@ -575,33 +636,54 @@ def main() -> int:
 
     mpx = H * W * k / 1e6
     value = mpx * args.steps / dt
-    names = ["pass1", "pass2", "nms"]
+    names = list(dog.Context.KERNEL_NAMES)
     avg_ms = [m / max(nseq, 1) for m in kms]
-    taps = int(np.sum(2 * radii + 1))
-    flops = {"pass1": 2.0 * taps * H * W, "pass2": 2.0 * taps * H * W,
-             "nms": 0.0}
-    dom = int(np.argmax(avg_ms[:2]))
-    dname = names[dom]
+    flops = blur_flops(radii, H, W, min_taps, merged=avg_ms[3] == 0.0 and avg_ms[4] == 0.0)
+    # the dominant blur launch (a pass, with the transform jobs it runs)
+    blur = [n for n in names if n != "nms"]
+    dname = max(blur, key=lambda n: avg_ms[names.index(n)])
+    dom = names.index(dname)
     achieved = flops[dname] / (avg_ms[dom] * 1e-3) / 1e12
-    traffic = measured_traffic(dname, tune["variant"] if tune else args.variant)
+    traffic = measured_traffic(dname, variant, min_taps)
     roofline = {"bound": "alu", "kernel": dname, "achieved": round(achieved, 3),
                 "peak": round(PEAK_FP32_TFLOPS, 1), "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
                 "kernel_avg_us": {n: round(m * 1e3, 2) for n, m in zip(names, avg_ms)},
-                "algorithmic_flop_per_launch": flops[dname]}
+                "algorithmic_flop_per_launch": flops[dname],
+                "transform_min_taps": min_taps}
     # every kernel against both ceilings: algorithmic flops and bytes per launch
     n_g = k + 1
     pitch = (H + 63) // 64 * 64
     plane_b = 4.0 * W * pitch
+    n_tr = sum(1 for p in range(n_g) if min_taps > 0 and 2 * radii[p] + 1 >= min_taps)
     algo_bytes = {"pass1": 4.0 * H * W + n_g * plane_b, "pass2": 2.0 * n_g * plane_b,
-                  "nms": n_g * plane_b}
+                  "nms": n_g * plane_b,
+                  "fft1": 4.0 * H * W + n_tr * plane_b, "fft2": 2.0 * n_tr * plane_b}
+    if flops["merged"]:
+        algo_bytes["pass1"] = 4.0 * H * W + n_g * plane_b
+        algo_bytes["pass2"] = 2.0 * n_g * plane_b
+    else:
+        algo_bytes["pass1"] = 4.0 * H * W + (n_g - n_tr) * plane_b
+        algo_bytes["pass2"] = 2.0 * (n_g - n_tr) * plane_b
     roofline["per_kernel"] = {
         n: {"us": round(m * 1e3, 2),
             "tflops": round(flops[n] / (m * 1e-3) / 1e12, 2),
             "frac_fp32_peak": round(flops[n] / (m * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
             "algorithmic_gbs": round(algo_bytes[n] / (m * 1e-3) / 1e9, 1),
             "frac_hbm_peak": round(algo_bytes[n] / (m * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
-        for n, m in zip(names, avg_ms)}
+        for n, m in zip(names, avg_ms) if m > 0}
+    avg_direct = [m / max(nseq_direct, 1) for m in kms_direct]
+    fl_d = blur_flops(radii, H, W, 0, merged=False)
+    d_dom = int(np.argmax(avg_direct[:2]))
+    d_ach = fl_d[names[d_dom]] / (avg_direct[d_dom] * 1e-3) / 1e12
+    roofline_direct = {"bound": "alu", "kernel": names[d_dom], "achieved": round(d_ach, 3),
+                       "peak": round(PEAK_FP32_TFLOPS, 1), "unit": "TFLOP/s",
+                       "frac": round(d_ach / PEAK_FP32_TFLOPS, 4),
+                       "traffic": measured_traffic(names[d_dom], variant, 0),
+                       "kernel_avg_us": {n: round(m * 1e3, 2)
+                                         for n, m in zip(names[:3], avg_direct[:3])},
+                       "algorithmic_flop_per_launch": fl_d[names[d_dom]],
+                       "kernel_ms_per_frame": round(sum(avg_direct), 4)}
     kernel_sum_ms = sum(avg_ms)
 
     out = {"metric": "Mpixel-scales/s for DoG+NMS on 1 GPU; p99 frame latency, batched vs per-frame",
@@ -615,6 +697,7 @@ def main() -> int:
                       "width": W, "dog_planes": k, "parallelism": "single GPU",
                       "frames_in_flight": nf},
            "roofline": roofline,
+           "roofline_direct_blur": roofline_direct,
            "latency_ms": {"p50": round(pct(lat, 50) * 1e3, 4), "p99": round(pct(lat, 99) * 1e3, 4)},
            "sync_ms_per_step": round(dt_sync / args.steps * 1e3, 4),
            "sync_mpx_scales_per_s": round(mpx * args.steps / dt_sync, 1),
@@ -676,17 +759,26 @@ def main() -> int:
                           "batched_frame_latency_ms": round(tb * 1e3, 3)}
         del dfr
 
+    # the autotuner's choices, for the servers' slot contexts
+    import tempfile
+    tune_cache = os.path.join(tempfile.gettempdir(), "dog_bench_tune_%d.json" % os.getpid())
+    ctx.autotune_save(tune_cache)
     if not args.no_mixed:
-        out["mixed128"] = bench_mixed(dog, torch, ctx, prm, k, mixed_frames, args.batch_steps)
+        out["mixed128"] = bench_mixed(dog, torch, ctx, prm, k, mixed_frames, args.batch_steps,
+                                      tune_cache)
     if not args.no_serve:
         out["serving"] = bench_serving(dog, prm, k, mixed_frames, args.serve_rate,
-                                       args.serve_seconds)
+                                       args.serve_seconds, tune_cache=tune_cache)
         # the same stream under a budget of 2.5 footprints of the largest
         # frame of the pool, so admission by HBM footprint binds
         big = max(mixed_frames, key=lambda f: f.size)
         budget = int(2.5 * dog.footprint(prm, [big.shape]))
         out["serving_tight_budget"] = bench_serving(dog, prm, k, mixed_frames, args.serve_rate,
-                                                    args.tight_serve_seconds, budget)
+                                                    args.tight_serve_seconds, budget, tune_cache)
+    try:
+        os.remove(tune_cache)
+    except OSError:
+        pass
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(img, prm, k)

@@ -317,23 +317,33 @@ int dog_num_variants(void);
 int dog_variant_info(int variant, int32_t* S, int32_t* waves, int32_t* strips, int32_t* nms_rows);
 int dog_set_variant(dog_context* ctx, int variant);
 
-/* Autotuner.  dog_autotune times every variant on the device image d_image
- * (height x width floats, row_stride >= width elements apart, on the
- * context's device) with the per-kernel event timing below: one untimed
- * launch then `reps` timed ones (reps = 0 means 5), and records the variant
- * with the least summed kernel time as the choice for (height, width, the
- * blur radii of params); the built-in default is kept when it is within 2 %
- * of that time, so repeated tuning does not flip between near-equal variants.  us_out (may be NULL) receives the mean microseconds
- * of every variant (dog_num_variants() doubles); *variant_out (may be NULL)
- * the winner.  A launch whose dominant shape (most pixels) was not tuned uses
- * the choice of the tuned shape with the same radii nearest in pixel count.
- * The variant pinned with dog_set_variant is restored afterwards.
+/* Autotuner.  dog_autotune times, with the per-kernel event timing below,
+ * one untimed launch then `reps` timed ones (reps = 0 means 5) of the device
+ * image d_image (height x width floats, row_stride >= width elements apart,
+ * on the context's device) per configuration: every variant with every plane
+ * blurred directly; then, on frames whose sides are powers of two in
+ * [64, 2048], that variant with the widest plane, the two widest, ... in the
+ * transform domain (dog_set_dct); then, if a transform threshold won, every
+ * variant again at that threshold.  The built-in default variant and the
+ * direct blur each stand unless beaten by more than 2 %, so repeated tuning
+ * gives the same choice.  It records the variant and the threshold for
+ * frames of this shape and ladder, and writes the winning variant to
+ * *variant_out and each variant's mean microseconds per frame (all kernels,
+ * at the chosen threshold) to us_out[dog_num_variants()] (either may be
+ * NULL).  Variants give bitwise the same results; the threshold changes the
+ * planes it moves to the transform domain within the plane tolerance and is
+ * applied per frame by the frame's own shape.  A launch whose dominant shape
+ * (most pixels) was not tuned uses the variant of the tuned shape with the
+ * same radii nearest in pixel count; an untuned shape is blurred directly.
+ * The variant pinned with dog_set_variant and a threshold pinned with
+ * dog_set_dct are restored afterwards (and, while pinned, used instead).
  * dog_autotune_save writes the choices as JSON to `path`; dog_autotune_load
  * adds those of a file written for the same architecture and kernel build
  * (a file of another build loads nothing and is not an error).
  * dog_autotune_choice reports the variant automatic selection would take for
- * one frame of the given shape.  Errors: DOG_EINVAL (NULL pointer, bad shape
- * or parameters, unreadable or unwritable file), DOG_EBUSY (a launch of
+ * one frame of the given shape, dog_autotune_transform the threshold (0: all
+ * planes direct).  Errors: DOG_EINVAL (NULL pointer, bad shape or
+ * parameters, unreadable or unwritable file), DOG_EBUSY (a launch of
  * dog_detect_device_async not finished), device errors. */
 int dog_autotune(dog_context* ctx, const dog_params* params, const float* d_image, int64_t height,
                  int64_t width, int64_t row_stride, int32_t reps, int32_t* variant_out,
@@ -342,6 +352,8 @@ int dog_autotune_save(dog_context* ctx, const char* path);
 int dog_autotune_load(dog_context* ctx, const char* path);
 int dog_autotune_choice(dog_context* ctx, const dog_params* params, int64_t height, int64_t width,
                         int32_t* variant_out);
+int dog_autotune_transform(dog_context* ctx, const dog_params* params, int64_t height,
+                           int64_t width, int32_t* min_taps_out);
 
 /* Launch mode: on (default) = the launch sequence of a table layout (frame
  * table upload, the three kernels, candidate readback) is captured once into
@@ -376,8 +388,12 @@ int dog_kernel_times_all(dog_context* ctx, double* ms_out, int32_t cap, int64_t*
  * one forward one in the second (fp32 FFTs of the lines in LDS, FP64
  * transfer functions of the kernels rounded once to fp32).  The planes agree
  * with the direct blur within the detector's plane tolerance, not bit for
- * bit.  min_taps 0 (the default) blurs every plane directly.  DOG_EINVAL for
- * min_taps < 0. */
+ * bit.  min_taps 0 blurs every plane directly; -1 (the default) takes the
+ * threshold dog_autotune chose for each frame's shape (0 for shapes it has
+ * not tuned).  A pass whose transform-domain lines all have one length of
+ * 128 to 1024 runs them in the direct blur's launch (variants with room for
+ * them in the ring), else in launches of their own.  DOG_EINVAL for
+ * min_taps < -1. */
 int dog_set_dct(dog_context* ctx, int32_t min_taps);
 
 

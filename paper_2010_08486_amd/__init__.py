@@ -177,6 +177,7 @@ def lib() -> ctypes.CDLL:
         "dog_autotune_save": (i32, [vp, ctypes.c_char_p]),
         "dog_autotune_load": (i32, [vp, ctypes.c_char_p]),
         "dog_autotune_choice": (i32, [vp, ctypes.POINTER(dog_params), i64, i64, ctypes.POINTER(i32)]),
+        "dog_autotune_transform": (i32, [vp, ctypes.POINTER(dog_params), i64, i64, ctypes.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -312,6 +313,13 @@ class Context:
     def autotune_load(self, path: str) -> None:
         _check(lib().dog_autotune_load(self._h, os.fsencode(path)))
 
+    def autotune_transform(self, params: Params, height: int, width: int) -> int:
+        """The transform threshold (kernel taps) used for frames of this shape."""
+        v = ctypes.c_int32(0)
+        prm = params.c()
+        _check(lib().dog_autotune_transform(self._h, ctypes.byref(prm), height, width, ctypes.byref(v)))
+        return v.value
+
     def autotune_choice(self, params: Params, height: int, width: int) -> int:
         v = ctypes.c_int32(-1)
         prm = params.c()
@@ -347,7 +355,8 @@ class Context:
 
     def set_dct(self, min_taps: int) -> None:
         """dog_set_dct: planes whose kernels have at least min_taps taps are
-        blurred in the cosine-transform domain (power-of-two frames); 0 = never."""
+        blurred in the cosine-transform domain (power-of-two frames); 0 = never,
+        -1 = the autotuner's choice per frame shape (the default)."""
         _check(lib().dog_set_dct(self._h, int(min_taps)))
 
     def detect_device(self, image, params: Params, stream=None) -> np.ndarray:

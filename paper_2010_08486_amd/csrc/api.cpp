@@ -192,15 +192,17 @@ int dog_set_profiling(dog_context* ctx, int32_t on)
 
 int dog_set_dct(dog_context* ctx, int32_t min_taps)
 {
-    if (!ctx || min_taps < 0) {
+    if (!ctx || min_taps < -1) {
         set_error("invalid argument");
         return DOG_EINVAL;
     }
     if (ctx->pending)
         return ctx_idle(ctx);
-    if (ctx->dct_min_taps != min_taps)
+    const bool forced = min_taps >= 0;
+    if (ctx->dct_forced != forced || (forced && ctx->dct_min_taps != min_taps))
         drop_graph(ctx);
-    ctx->dct_min_taps = min_taps;
+    ctx->dct_forced = forced;
+    ctx->dct_min_taps = forced ? min_taps : 0;
     return DOG_OK;
 }
 

@@ -1,10 +1,15 @@
-// Autotuner: for a frame shape and ladder, time every kernel variant (tile
-// geometry S / R / waves, local-maximum rows) on a representative device frame
+// Autotuner: for a frame shape and ladder, time the kernel variants (tile
+// geometry S / R / waves, local-maximum rows) and, on frames whose sides are
+// powers of two, the transform threshold (how many of the widest planes are
+// blurred in the cosine-transform domain) on a representative device frame
 // with the library's own per-kernel event timing, and keep the fastest.
 // Choices are kept per (shape, radii) in the context and can be saved to and
 // loaded from a JSON cache keyed by architecture and kernel source, so a
 // production process starts tuned.  Every variant computes bitwise identical
-// results (taps are summed in the same order), so tuning never changes output.
+// results (taps are summed in the same order); the transform threshold
+// changes the planes it moves to the transform domain within the plane
+// tolerance, and is applied per frame by its own shape, so a frame gives the
+// same result alone and in any batch.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -80,6 +85,16 @@ int choose_variant(const dog_context* c, const std::vector<FrameIn>& frames, con
     return v;
 }
 
+int frame_min_taps(const dog_context* c, int H, int W, const Plan& P)
+{
+    if (c->dct_forced)
+        return c->dct_min_taps;
+    if (c->tuned_dct.empty())
+        return 0;
+    const auto it = c->tuned_dct.find(shape_key(H, W, P));
+    return it == c->tuned_dct.end() ? 0 : it->second;
+}
+
 }  // namespace dog
 
 using namespace dog;
@@ -113,54 +128,100 @@ int dog_autotune(dog_context* ctx, const dog_params* params, const float* d_imag
     const int saved_variant = ctx->variant;
     const bool saved_forced = ctx->variant_forced;
     const bool saved_prof = ctx->profiling;
+    const bool saved_dct_forced = ctx->dct_forced;
+    const int saved_dct = ctx->dct_min_taps;
     ctx->variant_forced = true;
     ctx->profiling = true;
-    int best = -1;
-    double best_us = 1e300;
+    ctx->dct_forced = true;
     std::vector<std::vector<dog_blob>> out;
-    std::vector<double> times(dogk_num_variants(), 1e300);
-    for (int v = 0; v < dogk_num_variants(); ++v) {
-        if ((rc = ctx_set_variant(ctx, v)) != DOG_OK)
-            break;
+    // mean kernel microseconds of one frame with variant v and threshold mt
+    auto time_it = [&](int v, int mt, double* us) -> int {
+        int r = ctx_set_variant(ctx, v);
+        if (r != DOG_OK)
+            return r;
+        ctx->dct_min_taps = mt;
         // one untimed launch (tables, first touch), then reps timed ones
-        if ((rc = run_frames(ctx, plan, fr, ctx->stream, &out, false, nullptr, nullptr, nullptr)) !=
+        if ((r = run_frames(ctx, plan, fr, ctx->stream, &out, false, nullptr, nullptr, nullptr)) !=
             DOG_OK)
-            break;
+            return r;
         for (double& m : ctx->kernel_ms)
             m = 0.0;
         ctx->kernel_launches = 0;
-        for (int i = 0; i < reps && rc == DOG_OK; ++i)
-            rc = run_frames(ctx, plan, fr, ctx->stream, &out, false, nullptr, nullptr, nullptr);
-        if (rc != DOG_OK)
-            break;
+        for (int i = 0; i < reps && r == DOG_OK; ++i)
+            r = run_frames(ctx, plan, fr, ctx->stream, &out, false, nullptr, nullptr, nullptr);
+        if (r != DOG_OK)
+            return r;
         double ms = 0.0;
         for (double m : ctx->kernel_ms)
             ms += m;
-        const double us = ms * 1e3 / (double)std::max<int64_t>(1, ctx->kernel_launches);
-        times[v] = us;
-        if (us_out)
-            us_out[v] = us;
-        if (us < best_us) {
-            best_us = us;
-            best = v;
+        *us = ms * 1e3 / (double)std::max<int64_t>(1, ctx->kernel_launches);
+        return DOG_OK;
+    };
+    // every variant at a threshold; the built-in default stands unless
+    // another variant beats it by more than the timing noise (2 %), so
+    // repeated tuning gives the same choice
+    std::vector<double> times(dogk_num_variants(), 1e300);
+    auto best_variant = [&](int mt, int* best) -> int {
+        double best_us = 1e300;
+        *best = -1;
+        for (int v = 0; v < dogk_num_variants(); ++v) {
+            const int r = time_it(v, mt, &times[v]);
+            if (r != DOG_OK)
+                return r;
+            if (times[v] < best_us) {
+                best_us = times[v];
+                *best = v;
+            }
         }
+        if (*best != ctx->variant_auto && times[ctx->variant_auto] <= best_us * 1.02)
+            *best = ctx->variant_auto;
+        return DOG_OK;
+    };
+    int best = -1, best_mt = 0;
+    rc = best_variant(0, &best);
+    if (rc == DOG_OK && frame_dct_ok((int)height, (int)width)) {
+        // thresholds: none, then the widest plane, the two widest, ...
+        std::vector<int> cand;
+        for (int p = plan.n_g - 1; p >= 0; --p) {
+            const int taps = 2 * plan.r[p] + 1;
+            if (cand.empty() || cand.back() != taps)
+                cand.push_back(taps);
+        }
+        double us0 = times[best], best_us = us0;
+        for (int mt : cand) {
+            double us = 0.0;
+            if ((rc = time_it(best, mt, &us)) != DOG_OK)
+                break;
+            if (us < best_us) {
+                best_us = us;
+                best_mt = mt;
+            }
+        }
+        // the direct blur (bitwise the same for every variant) stands
+        // unless the transform domain is clearly faster
+        if (rc == DOG_OK && best_mt > 0 && us0 <= best_us * 1.02)
+            best_mt = 0;
+        if (rc == DOG_OK && best_mt > 0)
+            rc = best_variant(best_mt, &best);   // the geometry for the planes left direct
     }
-    // the built-in default stands unless another variant beats it by more
-    // than the timing noise (2 %), so repeated tuning gives the same choice
-    if (rc == DOG_OK && best >= 0 && best != ctx->variant_auto &&
-        times[ctx->variant_auto] <= best_us * 1.02)
-        best = ctx->variant_auto;
     ctx->profiling = saved_prof;
     ctx->variant_forced = saved_forced;
+    ctx->dct_forced = saved_dct_forced;
+    ctx->dct_min_taps = saved_dct;
     for (double& m : ctx->kernel_ms)
         m = 0.0;
     ctx->kernel_launches = 0;
+    drop_graph(ctx);
     const int rc2 = ctx_set_variant(ctx, saved_variant);
     if (rc != DOG_OK)
         return rc;
     if (rc2 != DOG_OK)
         return rc2;
+    if (us_out)
+        for (int v = 0; v < dogk_num_variants(); ++v)
+            us_out[v] = times[v];
     ctx->tuned[shape_key(height, width, plan)] = best;
+    ctx->tuned_dct[shape_key(height, width, plan)] = best_mt;
     if (variant_out)
         *variant_out = best;
     return DOG_OK;
@@ -183,8 +244,12 @@ int dog_autotune_save(dog_context* ctx, const char* path)
     for (const auto& kv : ctx->tuned) {
         const std::string& k = kv.first;
         const size_t bar = k.find('|');
-        std::fprintf(fp, "    {\"shape\": \"%s\", \"radii\": \"%s\", \"variant\": %d}%s\n",
+        const auto d = ctx->tuned_dct.find(k);
+        std::fprintf(fp,
+                     "    {\"shape\": \"%s\", \"radii\": \"%s\", \"variant\": %d, "
+                     "\"min_taps\": %d}%s\n",
                      k.substr(0, bar).c_str(), k.substr(bar + 1).c_str(), kv.second,
+                     d == ctx->tuned_dct.end() ? 0 : d->second,
                      ++i < ctx->tuned.size() ? "," : "");
     }
     std::fprintf(fp, "  ]\n}\n");
@@ -220,16 +285,40 @@ int dog_autotune_load(dog_context* ctx, const char* path)
     const int nv = dogk_num_variants();
     while (std::getline(in, line)) {
         char shape[64], radii[1024];
-        int v = -1;
+        int v = -1, mt = 0;
         const size_t p = line.find("{\"shape\"");
         if (p == std::string::npos)
             continue;
-        if (std::sscanf(line.c_str() + p,
-                        "{\"shape\": \"%63[^\"]\", \"radii\": \"%1023[^\"]\", \"variant\": %d", shape,
-                        radii, &v) == 3 &&
-            v >= 0 && v < nv)
-            ctx->tuned[std::string(shape) + "|" + radii] = v;
+        const int got = std::sscanf(
+            line.c_str() + p,
+            "{\"shape\": \"%63[^\"]\", \"radii\": \"%1023[^\"]\", \"variant\": %d, \"min_taps\": %d",
+            shape, radii, &v, &mt);
+        if (got >= 3 && v >= 0 && v < nv && mt >= 0) {
+            const std::string key = std::string(shape) + "|" + radii;
+            ctx->tuned[key] = v;
+            ctx->tuned_dct[key] = got == 4 ? mt : 0;
+        }
     }
+    return DOG_OK;
+}
+
+int dog_autotune_transform(dog_context* ctx, const dog_params* params, int64_t height,
+                           int64_t width, int32_t* min_taps_out)
+{
+    if (!ctx || !params || !min_taps_out) {
+        set_error("invalid argument");
+        return DOG_EINVAL;
+    }
+    Plan P;
+    std::string err;
+    const int rc = build_plan(*params, &P, &err);
+    if (rc != DOG_OK) {
+        set_error(err);
+        return rc;
+    }
+    *min_taps_out = frame_dct_ok((int)height, (int)width)
+                        ? frame_min_taps(ctx, (int)height, (int)width, P)
+                        : 0;
     return DOG_OK;
 }
 

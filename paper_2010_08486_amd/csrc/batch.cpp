@@ -114,6 +114,8 @@ static int run_grouped(dog_context* ctx, const Plan& P, const std::vector<FrameI
         l->tuned = ctx->tuned;
         l->use_graphs = ctx->use_graphs;
         l->dct_min_taps = ctx->dct_min_taps;
+        l->dct_forced = ctx->dct_forced;
+        l->tuned_dct = ctx->tuned_dct;
         if (ctx->variant_forced) {
             int rc = ctx_set_variant(l, ctx->variant);
             if (rc != DOG_OK)

@@ -8,15 +8,21 @@
 
 namespace dog {
 
-constexpr int kFftLines = 4;        // lines per job (two complex sequences)
+constexpr int kFftLines = 2;        // lines per job (one complex sequence)
 constexpr int kFftMaxN = 2048;      // longest line
 constexpr int kFftMaxPlanes = 16;   // planes one job produces from one forward transform
 
+// Outputs and transfer functions of the planes a group of jobs produces.
+struct FftPlaneSet {
+    float* out[kFftMaxPlanes];
+    const float* h[kFftMaxPlanes];   // per plane: transfer function H[k] / N, k = 0..N-1
+};
+
 // Blur of kFftLines consecutive lines of length N (a power of two) by the
-// kernels of n_planes planes.  Lines are columns of the input: element n of
+// kernels of n_planes planes (none: a padding job that does nothing).  Lines are columns of the input: element n of
 // line l is in[n * in_pitch + line0 + l].  Output line l of plane q is the
-// row out[q] + (line0 + l) * out_pitch (out_rows) or the column
-// out[q][n * out_pitch + line0 + l].
+// row planes->out[q] + (line0 + l) * out_pitch (out_rows) or the column
+// planes->out[q][n * out_pitch + line0 + l].
 struct FftJob {
     const float* in;         // NULL: the pixels of frame `frame` of the launch
     const float2* tw;        // N/2 twiddles exp(-2 pi i t / N)
@@ -29,8 +35,7 @@ struct FftJob {
     int32_t n_planes;
     int32_t out_rows;
     int32_t out_pitch;
-    float* out[kFftMaxPlanes];
-    const float* h[kFftMaxPlanes];   // per plane: transfer function H[k] / N, k = 0..N-1
+    const FftPlaneSet* planes;   // the n_planes planes' outputs and transfer functions
 };
 
 }  // namespace dog
@@ -38,8 +43,8 @@ struct FftJob {
 extern "C" {
 size_t dogk_fft_lds_bytes(int N);
 // n_jobs jobs whose lines all have 2^logn values (6 <= logn <= 11).  vec:
-// every job's input rows hold its lines at 16-byte aligned addresses (pitch
-// and line0 multiples of 4, base 16-byte aligned); else 4-byte loads.
+// every job's input rows hold its lines at 8-byte aligned addresses (pitch
+// and line0 even, base 8-byte aligned); else 4-byte loads.
 // ev (may be NULL): start and end events of the dispatch.
 hipError_t dogk_fft_blur(const dog::LaunchArgs* args, const dog::FftJob* d_jobs, int n_jobs,
                          int logn, int vec, hipStream_t stream, hipEvent_t* ev);

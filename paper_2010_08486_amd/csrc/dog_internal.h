@@ -20,6 +20,7 @@
 #define DOG_MAX_GAUSS 64              // n_g limit (k <= 63 DoG planes)
 #define DOG_WPAD 16                   // per-plane weight vectors padded to a multiple of this
 #define DOG_NMS_COLS 62               // output columns per wave of the local-maximum kernel
+#define DOG_FFT_MERGED 4              // blur kernels with transform jobs of lines of 2^7 .. 2^10
 
 namespace dog {
 
@@ -82,6 +83,8 @@ struct CandHeader {
     uint32_t pad_[3];
 };
 
+struct FftJob;   // transform-domain job (dct.h)
+
 // Arguments of one launch sequence (all pointers are device pointers).
 struct LaunchArgs {
     const FrameDesc* frames;    // frame table, or NULL: the one frame is f0
@@ -96,19 +99,23 @@ struct LaunchArgs {
                                 // end of its record range (the count is the max)
     uint32_t cap;               // record capacity
     uint32_t n_host;
-    int n1, n2, n3;             // tiles (= workgroups) of each kernel
+    int n1, n2, n3;             // tiles of each kernel
     int pad_;
     FrameDesc f0;               // the frame of a one-frame launch (frames == NULL)
+    const FftJob* fft_jobs[2];  // transform-domain jobs run by blur pass 1 / 2
+    int n_fft[2];               // their count (a multiple of DOG_NXCD), or 0
 };
 
 // The transform-domain blur's launches of a sequence: for pass 1 (along y)
 // and pass 2 (along x), one launch per line length (log2 N = 6..11) with its
 // job table (device) and count, and whether every job's input allows
-// 16-byte loads.
+// 8-byte loads; or, when a pass's jobs all have one line length the blur
+// kernels can take, none (the jobs run in the blur pass's launch).
 struct FftLaunch {
     const void* jobs[2][6];
     int n[2][6];
     int vec[2];
+    int merged_logn[2];         // > 0: the pass's jobs run in the blur launch (LaunchArgs)
     int total(int pass) const
     {
         int t = 0;

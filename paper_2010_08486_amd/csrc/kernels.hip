@@ -30,6 +30,7 @@
 #include <hip/hip_ext.h>
 
 #include "dog_internal.h"
+#include "fft_job.h"
 
 // Pointers into the constant (scalar-load) address space.  The qualifier only
 // exists for the device compilation pass; the host pass of this file sees
@@ -354,7 +355,12 @@ __device__ __forceinline__ void lds_rows(float (&v)[S], const float* lds, int sl
 
 // PASS 1: blur down the columns of the input frame into T (transposed);
 // PASS 2: blur down the columns of T_p into L_p (same layout).
-template <int PASS, int S, int NW, int P, bool WIDE>
+// GROUP: a tile may take a run of planes (Tile::n_planes); else one plane
+// (the plane loop costs registers).  FFTLOGN > 0: the launch also runs the
+// pass's transform-domain jobs (lines of 2^FFTLOGN values, fft_job.h) in its
+// first a.n_fft[PASS - 1] workgroups, with the ring's LDS, before the direct
+// tiles.
+template <int PASS, int S, int NW, int P, bool WIDE, int FFTLOGN = 0, bool GROUP = false>
 __global__ void __launch_bounds__(64 * NW) k_blur_lds(LaunchArgs a)
 {
     using G = StageGeom<S, NW>;
@@ -367,11 +373,22 @@ __global__ void __launch_bounds__(64 * NW) k_blur_lds(LaunchArgs a)
     const int wv = __builtin_amdgcn_readfirstlane((int)(tid >> 6));
     if (PASS == 1 && blockIdx.x == 0 && tid == 0)
         a.cand->count = 0u;  // read by the local-maximum kernel of this sequence
-    const Tile tl = my_tile(PASS == 1 ? a.tiles1 : a.tiles2);
+    int wg = blockIdx.x;
+    if constexpr (FFTLOGN > 0) {
+        static_assert(FftGeom<FFTLOGN, 64 * NW>::LDS_BYTES <= sizeof(lds4), "job fits the ring");
+        const int nf = a.n_fft[PASS - 1];
+        if (wg < nf) {
+            fft_job<FFTLOGN, 64 * NW, PASS == 2 || WIDE>(a, a.fft_jobs[PASS - 1] + wg,
+                                                          reinterpret_cast<float2*>(lds4));
+            return;
+        }
+        wg -= nf;
+    }
+    const Tile tl = cst(PASS == 1 ? a.tiles1 : a.tiles2)[wg];
     const FrameDesc f = frame_of(a, tl.frame);
     // the tile's planes: tl.plane and the (tl.n_planes - 1) planes below it,
     // widest first, each over the same columns and band (one plane if 0)
-    const int n_pl = tl.n_planes > 1 ? tl.n_planes : 1;
+    const int n_pl = GROUP && tl.n_planes > 1 ? tl.n_planes : 1;
     for (int pi = 0; pi < n_pl; ++pi) {
         if (pi > 0)
             __syncthreads();   // the previous plane's last LDS reads are done
@@ -782,16 +799,60 @@ struct KernelSet {
     const void* nms[2];     // [debug planes]
     int S, R, NW, BI, BN, NWN;
     int group;              // staged blur: a tile takes several planes (cost-balanced)
+    // the blur passes with the transform-domain jobs of lines of 2^(7+i)
+    // values in the same launch (nullptr: the job does not fit the ring)
+    const void* pass1f[DOG_FFT_MERGED];
+    const void* pass1wf[DOG_FFT_MERGED];
+    const void* pass2f[DOG_FFT_MERGED];
 };
+
+// k_blur_lds with the transform jobs of lines of 2^LOGN values, if a job's
+// LDS fits the ring of this geometry.
+template <int PASS, int S, int NW, int P, bool WIDE, int LOGN>
+static const void* merged_fn()
+{
+    if constexpr (FftGeom<LOGN, 64 * NW>::LDS_BYTES <= (size_t)(NW + 2) * S * 256)
+        return reinterpret_cast<const void*>(&k_blur_lds<PASS, S, NW, P, WIDE, LOGN>);
+    else
+        return nullptr;
+}
+
+template <int S, int NW, int P>
+static void fill_merged(KernelSet& k)
+{
+    const void* f1[DOG_FFT_MERGED] = {merged_fn<1, S, NW, P, false, 7>(),
+                                      merged_fn<1, S, NW, P, false, 8>(),
+                                      merged_fn<1, S, NW, P, false, 9>(),
+                                      merged_fn<1, S, NW, P, false, 10>()};
+    const void* f1w[DOG_FFT_MERGED] = {merged_fn<1, S, NW, P, true, 7>(),
+                                       merged_fn<1, S, NW, P, true, 8>(),
+                                       merged_fn<1, S, NW, P, true, 9>(),
+                                       merged_fn<1, S, NW, P, true, 10>()};
+    const void* f2[DOG_FFT_MERGED] = {merged_fn<2, S, NW, P, true, 7>(),
+                                      merged_fn<2, S, NW, P, true, 8>(),
+                                      merged_fn<2, S, NW, P, true, 9>(),
+                                      merged_fn<2, S, NW, P, true, 10>()};
+    for (int i = 0; i < DOG_FFT_MERGED; ++i) {
+        k.pass1f[i] = f1[i];
+        k.pass1wf[i] = f1w[i];
+        k.pass2f[i] = f2[i];
+    }
+}
 
 template <int S, int NW, int P, int BN, int NWN, int GROUP = 0>
 static KernelSet make_lds_set()
 {
     KernelSet k;
     k.group = GROUP;
-    k.pass1 = reinterpret_cast<const void*>(&k_blur_lds<1, S, NW, P, false>);
-    k.pass1w = reinterpret_cast<const void*>(&k_blur_lds<1, S, NW, P, true>);
-    k.pass2 = reinterpret_cast<const void*>(&k_blur_lds<2, S, NW, P, true>);
+    if (GROUP) {
+        for (int i = 0; i < DOG_FFT_MERGED; ++i)
+            k.pass1f[i] = k.pass1wf[i] = k.pass2f[i] = nullptr;
+    } else {
+        fill_merged<S, NW, P>(k);
+    }
+    k.pass1 = reinterpret_cast<const void*>(&k_blur_lds<1, S, NW, P, false, 0, GROUP != 0>);
+    k.pass1w = reinterpret_cast<const void*>(&k_blur_lds<1, S, NW, P, true, 0, GROUP != 0>);
+    k.pass2 = reinterpret_cast<const void*>(&k_blur_lds<2, S, NW, P, true, 0, GROUP != 0>);
     k.nms[0] = reinterpret_cast<const void*>(&k_nms<BN, NWN, false>);
     k.nms[1] = reinterpret_cast<const void*>(&k_nms<BN, NWN, true>);
     k.S = S;
@@ -808,6 +869,8 @@ static KernelSet make_set()
 {
     KernelSet k;
     k.group = 0;
+    for (int i = 0; i < DOG_FFT_MERGED; ++i)
+        k.pass1f[i] = k.pass1wf[i] = k.pass2f[i] = nullptr;
     k.pass1w = nullptr;
     k.pass1 = reinterpret_cast<const void*>(&k_pass1<S, R, NW, BI>);
     k.pass2 = reinterpret_cast<const void*>(&k_pass2<S, R, NW, BI>);
@@ -870,17 +933,29 @@ int dogk_variant_ring(int v) { return dog::kSets[v].R; }
 int dogk_variant_group(int v) { return dog::kSets[v].group; }
 
 // Launch blur pass `pass` (1 or 2) on `stream`, one workgroup per tile of
-// its table; a pass with no tiles is not launched.  Pass 1 also clears the
-// candidate count, so without pass-1 tiles a fill kernel does.  wide1: every
-// frame's rows are 16-byte aligned and its width is a multiple of 64, so
-// pass 1 may use 16-byte loads.  If ev is non-NULL, ev[0] and ev[1] take the
-// start and end of the pass's execution (the dispatch's own timestamps, so
-// the launch gap before a kernel is not counted).
+// its table, after args->n_fft[pass - 1] workgroups of transform-domain jobs
+// of lines of 2^fft_logn values when fft_logn > 0 (the launch must then have
+// such jobs and the variant a merged kernel for them); a pass with no
+// workgroups is not launched.  Pass 1 also clears the candidate count, so
+// without pass-1 workgroups a fill kernel does.  wide1: every frame's rows
+// are 16-byte aligned and its width is a multiple of 64, so pass 1 may use
+// 16-byte loads.  If ev is non-NULL, ev[0] and ev[1] take the start and end
+// of the pass's execution (the dispatch's own timestamps, so the launch gap
+// before a kernel is not counted).
 hipError_t dogk_launch_pass(int variant, const dog::LaunchArgs* args, int pass, int grid,
-                            int wide1, hipStream_t stream, hipEvent_t* ev)
+                            int fft_logn, int wide1, hipStream_t stream, hipEvent_t* ev)
 {
     const dog::KernelSet& k = dog::kSets[variant];
     const void* fn = pass == 1 ? (wide1 && k.pass1w ? k.pass1w : k.pass1) : k.pass2;
+    if (fft_logn > 0) {
+        const int i = fft_logn - 7;
+        if (i < 0 || i >= DOG_FFT_MERGED)
+            return hipErrorInvalidValue;
+        fn = pass == 1 ? (wide1 ? k.pass1wf[i] : k.pass1f[i]) : k.pass2f[i];
+        if (!fn)
+            return hipErrorInvalidValue;
+        grid += args->n_fft[pass - 1];
+    }
     void* params[] = {const_cast<dog::LaunchArgs*>(args)};
     if (pass == 1 && grid <= 0) {
         hipLaunchKernelGGL(dog::k_fill_u32, dim3(1), dim3(64), 0, stream, &args->cand->count, 1, 0u);
@@ -893,6 +968,17 @@ hipError_t dogk_launch_pass(int variant, const dog::LaunchArgs* args, int pass, 
     return ev ? hipExtLaunchKernel(fn, dim3(grid), dim3(64 * k.NW), params, 0, stream, ev[0],
                                    ev[1], 0)
               : hipLaunchKernel(fn, dim3(grid), dim3(64 * k.NW), params, 0, stream);
+}
+
+// Whether variant v's blur passes can run transform-domain jobs of lines of
+// 2^logn values in their own launches.
+int dogk_variant_merges_fft(int v, int logn)
+{
+    const int i = logn - 7;
+    if (i < 0 || i >= DOG_FFT_MERGED)
+        return 0;
+    const dog::KernelSet& k = dog::kSets[v];
+    return k.pass1f[i] && k.pass1wf[i] && k.pass2f[i] ? 1 : 0;
 }
 
 // The local-maximum kernel (timed by ev[0], ev[1] when ev is non-NULL).

@@ -218,8 +218,9 @@ static long long reflect_index(long long t, long long n)
 
 // ---- transform-domain blur: shapes, job sizes, kernel transfer functions
 
-// Frames whose sides are powers of two in [64, 2048] take the transform path.
-static bool dct_shape_ok(int H, int W)
+// Frames whose sides are powers of two in [64, 2048] may take the transform
+// path.
+bool frame_dct_ok(int H, int W)
 {
     auto p2 = [](int v) { return v >= 64 && v <= 2048 && (v & (v - 1)) == 0; };
     return p2(H) && p2(W);
@@ -414,7 +415,8 @@ static hipError_t enqueue_sequence(dog_context* c, hipStream_t st, const FrameDe
     // each pass: the direct planes' tiles, then the transform-domain planes'
     // jobs (events: pass 1, pass 2, local maxima, transform 1, transform 2)
     for (int pass = 1; pass <= 2 && e == hipSuccess; ++pass) {
-        e = dogk_launch_pass(c->variant, &a, pass, pass == 1 ? a.n1 : a.n2, c->wide1 ? 1 : 0, st,
+        e = dogk_launch_pass(c->variant, &a, pass, pass == 1 ? a.n1 : a.n2,
+                             c->fft.merged_logn[pass - 1], c->wide1 ? 1 : 0, st,
                              ev ? ev + 2 * (pass - 1) : nullptr);
         const int i = pass - 1;
         for (int lg = 0; lg < 6 && e == hipSuccess; ++lg)
@@ -443,8 +445,8 @@ void drop_graph(dog_context* c)
 
 // Everything that fixes the launch tables, the buffers they point into and
 // the captured sequence, apart from the frames' pixel pointers.
-static std::vector<long long> launch_key(const dog_context* c, const std::vector<FrameIn>& frames,
-                                         bool dbg_D)
+static std::vector<long long> launch_key(const dog_context* c, const Plan& P,
+                                         const std::vector<FrameIn>& frames, bool dbg_D)
 {
     bool wide = true;
     for (const FrameIn& f : frames)
@@ -457,7 +459,7 @@ static std::vector<long long> launch_key(const dog_context* c, const std::vector
     k.push_back((long long)c->plan_gen);
     k.push_back(dbg_D ? 1 : 0);
     k.push_back(c->profiling ? 1 : 0);
-    k.push_back(c->dct_min_taps);
+    k.push_back(c->dct_forced ? 1 : 0);
     k.push_back((long long)(uintptr_t)c->planes.p);
     k.push_back((long long)(uintptr_t)c->tables.p);
     k.push_back((long long)(uintptr_t)c->cand.p);
@@ -469,6 +471,7 @@ static std::vector<long long> launch_key(const dog_context* c, const std::vector
         k.push_back(f.H);
         k.push_back(f.W);
         k.push_back(f.stride);
+        k.push_back(frame_min_taps(c, f.H, f.W, P));
     }
     return k;
 }
@@ -498,10 +501,11 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
     // at least dct_min_taps taps, on frames whose sides are powers of two
     std::vector<std::vector<int>> dctp(n);
     for (int f = 0; f < n; ++f) {
-        if (!dct_shape_ok(frames[f].H, frames[f].W) || c->dct_min_taps <= 0)
+        const int mt = frame_min_taps(c, frames[f].H, frames[f].W, P);
+        if (!frame_dct_ok(frames[f].H, frames[f].W) || mt <= 0)
             continue;
         for (int p = 0; p < n_g; ++p)
-            if (2 * P.r[p] + 1 >= c->dct_min_taps)
+            if (2 * P.r[p] + 1 >= mt)
                 dctp[f].push_back(p);
     }
 
@@ -557,7 +561,7 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
     // issues the same sequence directly.  A layout is captured into a graph
     // the second time in a row it is seen (a stream of ever-changing batch
     // compositions is launched directly instead of re-capturing each time).
-    std::vector<long long> key = launch_key(c, frames, dbg_D);
+    std::vector<long long> key = launch_key(c, P, frames, dbg_D);
     const bool have_graph = c->graph_exec != nullptr && key == c->graph_key;
     // one frame goes inline in the kernel arguments and is launched directly
     // (its pixel pointer would otherwise be baked into a graph)
@@ -679,21 +683,29 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
             size_t at;
         };
         std::vector<TabRef> tw_at, h_at;
+        if (c->fft_cache_gen != c->plan_gen) {
+            c->fft_transfer.clear();
+            c->fft_cache_gen = c->plan_gen;
+        }
         auto twiddles = [&](int N) {
             for (const TabRef& t : tw_at)
                 if (t.N == N)
                     return t.at;
+            std::vector<float>& v = c->fft_twiddles[N];
+            if (v.empty()) {
+                for (int t = 0; t < N / 2; ++t) {
+                    const double a = -2.0 * M_PI * (double)t / (double)N;
+                    v.push_back((float)std::cos(a));
+                    v.push_back((float)std::sin(a));
+                }
+                for (int k = 0; k < N; ++k) {
+                    const double a = -M_PI * (double)k / (2.0 * (double)N);
+                    v.push_back((float)std::cos(a));
+                    v.push_back((float)std::sin(a));
+                }
+            }
             const size_t at = dtab.size();
-            for (int t = 0; t < N / 2; ++t) {
-                const double a = -2.0 * M_PI * (double)t / (double)N;
-                dtab.push_back((float)std::cos(a));
-                dtab.push_back((float)std::sin(a));
-            }
-            for (int k = 0; k < N; ++k) {
-                const double a = -M_PI * (double)k / (2.0 * (double)N);
-                dtab.push_back((float)std::cos(a));
-                dtab.push_back((float)std::sin(a));
-            }
+            dtab.insert(dtab.end(), v.begin(), v.end());
             while (dtab.size() % 64)
                 dtab.push_back(0.0f);
             tw_at.push_back({N, 0, at});
@@ -703,23 +715,33 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
             for (const TabRef& t : h_at)
                 if (t.N == N && t.p == p)
                     return t.at;
+            std::vector<float>& v = c->fft_transfer[{N, p}];
+            if (v.empty()) {
+                const std::vector<double> h = dct_transfer(P.half64[p], N);
+                for (int k = 0; k < N; ++k)
+                    v.push_back((float)(h[k] / (double)N));
+            }
             const size_t at = dtab.size();
-            const std::vector<double> h = dct_transfer(P.half64[p], N);
-            for (int k = 0; k < N; ++k)
-                dtab.push_back((float)(h[k] / (double)N));
+            dtab.insert(dtab.end(), v.begin(), v.end());
             while (dtab.size() % 64)
                 dtab.push_back(0.0f);
             h_at.push_back({N, p, at});
             return at;
         };
         // table pointers are fixed up once the device table's offset is known
+        // jobs name their twiddles and plane set by offset until the device
+        // table's layout is known; plane sets name their transfer functions
         struct Fix {
             int pass, lg;
-            size_t job, tw;
+            size_t job, tw, set;
+        };
+        struct SetFix {
             int n_h;
             size_t h[kFftMaxPlanes];
         };
         std::vector<Fix> fixes;
+        std::vector<FftPlaneSet> psets;
+        std::vector<SetFix> set_fixes;
         const bool wide_src = key[0] != 0;   // frames' rows allow 16-byte loads
         FftLaunch fl{};
         fl.vec[0] = wide_src ? 1 : 0;
@@ -736,6 +758,18 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
             // up to kFftMaxPlanes planes per forward transform
             for (size_t g0 = 0; g0 < dctp[f].size(); g0 += kFftMaxPlanes) {
                 const int ng = (int)std::min<size_t>(kFftMaxPlanes, dctp[f].size() - g0);
+                FftPlaneSet ps{};
+                SetFix sf{ng, {}};
+                for (int q = 0; q < ng; ++q) {
+                    const int p = dctp[f][g0 + q];
+                    ps.out[q] = T0 + (size_t)p * plane;
+                    sf.h[q] = transfer(H, p);
+                }
+                const size_t set = psets.size();
+                psets.push_back(ps);
+                set_fixes.push_back(sf);
+                const int lg = ilog2(H) - 6;
+                const size_t tw = twiddles(H);
                 for (int l0 = 0; l0 < W; l0 += kFftLines) {
                     FftJob j{};
                     j.in = nullptr;
@@ -746,20 +780,22 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
                     j.n_planes = ng;
                     j.out_rows = 1;
                     j.out_pitch = (int)pt;
-                    const int lg = ilog2(H) - 6;
-                    Fix fx{0, lg, djobs[0][lg].size(), twiddles(H), ng, {}};
-                    for (int q = 0; q < ng; ++q) {
-                        const int p = dctp[f][g0 + q];
-                        j.out[q] = T0 + (size_t)p * plane;
-                        fx.h[q] = transfer(H, p);
-                    }
-                    fixes.push_back(fx);
+                    fixes.push_back({0, lg, djobs[0][lg].size(), tw, set});
                     djobs[0][lg].push_back(j);
                 }
             }
             // pass 2: per plane, the columns of T_p (lines along x, N = W) ->
             // columns of L_p
             for (int p : dctp[f]) {
+                FftPlaneSet ps{};
+                ps.out[0] = L0 + (size_t)p * plane;
+                SetFix sf{1, {}};
+                sf.h[0] = transfer(W, p);
+                const size_t set = psets.size();
+                psets.push_back(ps);
+                set_fixes.push_back(sf);
+                const int lg = ilog2(W) - 6;
+                const size_t tw = twiddles(W);
                 for (int l0 = 0; l0 < H; l0 += kFftLines) {
                     FftJob j{};
                     j.in = T0 + (size_t)p * plane;
@@ -771,18 +807,28 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
                     j.n_planes = 1;
                     j.out_rows = 0;
                     j.out_pitch = (int)pt;
-                    j.out[0] = L0 + (size_t)p * plane;
-                    const int lg = ilog2(W) - 6;
-                    Fix fx{1, lg, djobs[1][lg].size(), twiddles(W), 1, {}};
-                    fx.h[0] = transfer(W, p);
-                    fixes.push_back(fx);
+                    fixes.push_back({1, lg, djobs[1][lg].size(), tw, set});
                     djobs[1][lg].push_back(j);
                 }
             }
         }
-        for (int i = 0; i < 2; ++i)
+        // a pass whose jobs all have one line length the variant's blur
+        // kernels take runs them in its own launch, first, XCD-local, padded
+        // with empty jobs to whole rounds of the XCDs (so the tiles after
+        // them keep their XCD placement)
+        std::vector<FftJob> mjobs[2];
+        for (int i = 0; i < 2; ++i) {
+            int only = -1, kinds = 0;
             for (int lg = 0; lg < 6; ++lg)
-                fl.n[i][lg] = (int)djobs[i][lg].size();
+                if (!djobs[i][lg].empty()) {
+                    only = lg;
+                    ++kinds;
+                }
+            if (kinds == 1 && dogk_variant_merges_fft(c->variant, only + 6))
+                fl.merged_logn[i] = only + 6;
+            for (int lg = 0; lg < 6; ++lg)
+                fl.n[i][lg] = fl.merged_logn[i] == lg + 6 ? 0 : (int)djobs[i][lg].size();
+        }
 
         const long long t1 = (long long)tb1.size(), t2 = (long long)tb2.size(),
                         t3 = (long long)tb3.size();
@@ -799,12 +845,17 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
         const size_t o_t3 = align_up(o_t2 + sizeof(Tile) * tb2.size(), 256);
         const size_t o_rows = align_up(o_t3 + sizeof(Tile) * tb3.size(), 256);
         const size_t o_dtab = align_up(o_rows + sizeof(int) * rowtab.size(), 256);
+        const size_t o_psets = align_up(o_dtab + sizeof(float) * dtab.size(), 256);
         size_t o_djobs[2][6];
-        size_t o_end = align_up(o_dtab + sizeof(float) * dtab.size(), 256);
+        size_t o_end = align_up(o_psets + sizeof(FftPlaneSet) * psets.size(), 256);
         for (int i = 0; i < 2; ++i)
             for (int lg = 0; lg < 6; ++lg) {
                 o_djobs[i][lg] = o_end;
-                o_end = align_up(o_end + sizeof(FftJob) * djobs[i][lg].size(), 256);
+                const size_t nj = djobs[i][lg].size();
+                const size_t padded = fl.merged_logn[i] == lg + 6
+                                          ? (nj + DOG_NXCD - 1) / DOG_NXCD * DOG_NXCD
+                                          : nj;
+                o_end = align_up(o_end + sizeof(FftJob) * padded, 256);
             }
         const size_t tbytes = o_end;
         if ((rc = ctx_alloc(c, &c->tables, tbytes, "launch tables")) != DOG_OK)
@@ -813,7 +864,7 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
             return rc;
         if ((rc = ctx_pin(&c->h_ends, sizeof(uint32_t) * tb3.size())) != DOG_OK)
             return rc;
-        key = launch_key(c, frames, dbg_D);  // buffers may have moved
+        key = launch_key(c, P, frames, dbg_D);  // buffers may have moved
         c->seen_key = key;
         char* dt = static_cast<char*>(c->tables.p);
         char* h = static_cast<char*>(c->h_tables.p);
@@ -837,16 +888,25 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
         std::memcpy(h + o_dtab, dtab.data(), sizeof(float) * dtab.size());
         {
             const float* dt_f = reinterpret_cast<const float*>(dt + o_dtab);
+            const FftPlaneSet* d_sets = reinterpret_cast<const FftPlaneSet*>(dt + o_psets);
+            for (size_t q = 0; q < psets.size(); ++q)
+                for (int i = 0; i < set_fixes[q].n_h; ++i)
+                    psets[q].h[i] = dt_f + set_fixes[q].h[i];
+            std::memcpy(h + o_psets, psets.data(), sizeof(FftPlaneSet) * psets.size());
             for (const Fix& fx : fixes) {
                 FftJob& j = djobs[fx.pass][fx.lg][fx.job];
                 j.tw = reinterpret_cast<const float2*>(dt_f + fx.tw);
                 j.post = reinterpret_cast<const float2*>(dt_f + fx.tw + (size_t)j.N);
-                for (int q = 0; q < fx.n_h; ++q)
-                    j.h[q] = dt_f + fx.h[q];
+                j.planes = d_sets + fx.set;
             }
             for (int i = 0; i < 2; ++i)
                 for (int lg = 0; lg < 6; ++lg) {
                     djobs[i][lg] = xcd_order(djobs[i][lg]);
+                    if (fl.merged_logn[i] == lg + 6) {
+                        while (djobs[i][lg].size() % DOG_NXCD)
+                            djobs[i][lg].push_back(FftJob{});   // no planes: does nothing
+                        mjobs[i] = djobs[i][lg];
+                    }
                     std::memcpy(h + o_djobs[i][lg], djobs[i][lg].data(),
                                 sizeof(FftJob) * djobs[i][lg].size());
                     fl.jobs[i][lg] = dt + o_djobs[i][lg];
@@ -869,6 +929,11 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
         a.n1 = (int)t1;
         a.n2 = (int)t2;
         a.n3 = (int)t3;
+        for (int i = 0; i < 2; ++i) {
+            const int lg = fl.merged_logn[i] - 6;
+            a.fft_jobs[i] = lg >= 0 ? static_cast<const FftJob*>(fl.jobs[i][lg]) : nullptr;
+            a.n_fft[i] = lg >= 0 ? (int)mjobs[i].size() : 0;
+        }
         c->n_gauss = n_g;
         c->debug_planes = dbg_D;
         c->wide1 = key[0] != 0;
@@ -962,9 +1027,11 @@ int collect_frames(dog_context* c, const Plan& P, std::vector<std::vector<dog_bl
         count = std::max(count, ends[i]);
     }
     if (c->profiling) {
-        // kernels that were launched: pass 1 and 2 when they had tiles, the
-        // local maxima, the transform-domain launches that had jobs
-        const bool ran[DOG_NKERNELS] = {c->args.n1 > 0, c->args.n2 > 0, true,
+        // kernels that were launched: pass 1 and 2 when they had tiles or
+        // transform jobs of their own, the local maxima, the transform-domain
+        // launches that had jobs
+        const bool ran[DOG_NKERNELS] = {c->args.n1 + c->args.n_fft[0] > 0,
+                                        c->args.n2 + c->args.n_fft[1] > 0, true,
                                         c->fft.total(0) > 0, c->fft.total(1) > 0};
         for (int i = 0; i < DOG_NKERNELS; ++i) {
             if (!ran[i])

@@ -105,7 +105,8 @@ void dogk_variant_geometry(int v, int* S, int* NW, int* BI, int* BN, int* NWN);
 int dogk_variant_ring(int v);
 int dogk_variant_group(int v);
 hipError_t dogk_launch_pass(int variant, const dog::LaunchArgs* args, int pass, int grid,
-                            int wide1, hipStream_t stream, hipEvent_t* ev);
+                            int fft_logn, int wide1, hipStream_t stream, hipEvent_t* ev);
+int dogk_variant_merges_fft(int v, int logn);
 hipError_t dogk_launch_nms_ev(int variant, const dog::LaunchArgs* args, int grid3, int debug,
                               hipStream_t stream, hipEvent_t* ev);
 hipError_t dogk_launch_nms(int variant, const dog::LaunchArgs* args, int grid3, int max_gauss,
@@ -136,6 +137,7 @@ struct dog_context {
     int variant_auto = 0;          // built-in default
     bool variant_forced = false;   // pinned by dog_set_variant
     std::map<std::string, int> tuned;  // "HxW|radii" -> autotuned variant
+    std::map<std::string, int> tuned_dct;  // "HxW|radii" -> autotuned transform threshold (taps)
     int occ[3] = {0, 0, 0};        // workgroups per CU of each kernel (active variant)
 
     // device memory accounting: allocations are checked against `budget`
@@ -214,10 +216,16 @@ struct dog_context {
     // transform-domain blur: planes whose kernels have at least this many
     // taps, on frames whose sides are powers of two in [64, 4096]; 0: never
     int dct_min_taps = 0;
-    bool dct_forced = false;     // set by dog_set_dct (else the tuned choice)
+    bool dct_forced = false;     // dct_min_taps set by dog_set_dct (else the tuned choice per shape)
 
     bool have_plan = false;
     uint64_t plan_gen = 0;
+    // transform-domain tables of the current plan, kept across table
+    // rebuilds: per line length the twiddles and post-twiddles, per (line
+    // length, plane) the transfer function over N (fp32)
+    uint64_t fft_cache_gen = ~0ull;
+    std::map<int, std::vector<float>> fft_twiddles;
+    std::map<std::pair<int, int>, std::vector<float>> fft_transfer;
     dog::Plan plan;
     uint32_t last_count = 0;       // candidates found by the previous launch (readback guess)
 };
@@ -243,6 +251,11 @@ int ctx_plan(dog_context* c, const dog_params* prm, const Plan** out);
 int ctx_set_variant(dog_context* c, int v);
 void drop_graph(dog_context* c);
 int choose_variant(const dog_context* c, const std::vector<FrameIn>& frames, const Plan& P);
+// Transform threshold (kernel taps; 0 = every plane direct) for frames of
+// this shape: the one set by dog_set_dct, else the autotuned one, else 0.
+int frame_min_taps(const dog_context* c, int H, int W, const Plan& P);
+// Whether frames of this shape can take the transform-domain blur.
+bool frame_dct_ok(int H, int W);
 
 // Run the three kernels over `frames` (device pixels) with plan P and read
 // back the candidate records, grouped per frame and sorted by (y, x, scale).

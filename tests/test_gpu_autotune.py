@@ -87,3 +87,48 @@ def test_server_loads_tune_cache(dog, torch_mod, tmp_path):
             assert blobs.tobytes() == ref.tobytes()
     finally:
         sv.close()
+
+
+def test_autotune_transform_threshold(dog, torch_mod, tmp_path):
+    # a power-of-two frame: the tuner may move the widest planes to the
+    # transform domain; whatever it picks, the detector stays within the
+    # plane tolerance of the oracle, the local-maximum decision is exact on
+    # its own cube, a frame gives the same blobs alone and in a batch, and
+    # the choice survives a save/load round trip
+    import oracle
+    from parity import check_candidates_exact, check_planes
+    torch = torch_mod
+    prm = dog.Params(**CAMERA)
+    img = synth.camera_frame(seed=33, H=512, W=512, n_blobs=150)
+    other = synth.camera_frame(seed=34, H=384, W=448, n_blobs=60)
+    t, t2 = _dev(torch, img), _dev(torch, other)
+    radii = dog.plan_info(prm)["radii"]
+    with dog.Context(0) as c:
+        direct = c.detect_device(t, prm)
+        assert c.autotune_transform(prm, 512, 512) == 0      # untuned: direct
+        v, us = c.autotune(t, prm, reps=2)
+        mt = c.autotune_transform(prm, 512, 512)
+        assert mt == 0 or mt in [2 * r + 1 for r in radii], mt
+        assert c.autotune_transform(prm, 384, 448) == 0      # not a power of two
+        print("tuned 512x512: variant %d, transform threshold %d taps" % (v, mt), flush=True)
+        L_g, D_g = c.debug_planes(t, prm)
+        L_o, D_o, sig = oracle.planes(img, 1.0, 30.0, 1.6, 4.0)
+        check_planes(L_g.cpu().numpy(), D_g.cpu().numpy(), L_o, D_o, sig, float(img.max()))
+        raw = c.debug_candidates(t, prm)
+        check_candidates_exact(raw, D_g.cpu().numpy(), prm.threshold)
+        alone = c.detect_device(t, prm)
+        alone2 = c.detect_device(t2, prm)
+        got, _ = c.detect_batch([t2, t, t2], prm)
+        assert got[1].tobytes() == alone.tobytes()
+        assert got[0].tobytes() == alone2.tobytes() and got[2].tobytes() == alone2.tobytes()
+        c.set_dct(0)                                          # pinned: every plane direct
+        assert c.detect_device(t, prm).tobytes() == direct.tobytes()
+        c.set_dct(-1)
+        path = str(tmp_path / "tune.json")
+        c.autotune_save(path)
+    doc = json.load(open(path))
+    assert doc["entries"][0]["min_taps"] == mt
+    with dog.Context(0) as c2:
+        c2.autotune_load(path)
+        assert c2.autotune_transform(prm, 512, 512) == mt
+        assert c2.detect_device(t, prm).tobytes() == alone.tobytes()

@@ -123,17 +123,23 @@ def test_batches_graphs_and_other_shapes(dog, torch_mod):
                 assert alone[i].tobytes() == plain.detect_device(dev[i], prm).tobytes()
 
 
-def test_transform_kernel_times(dog, torch_mod):
+@pytest.mark.parametrize("min_taps", [200, 1])
+def test_transform_kernel_times(dog, torch_mod, min_taps):
+    # min_taps 1: every plane in the transform domain, so the blur passes
+    # have no direct tiles and time only the transform jobs they run
     prm = dog.Params(**CAMERA)
     img = synth.camera_frame(seed=1)
     t = torch_mod.from_numpy(img).cuda()
     with dog.Context(0) as c:
-        c.set_dct(200)
+        c.set_dct(min_taps)
         c.set_profiling(True)
         for _ in range(5):
             c.detect_device(t, prm)
         ms, n = c.kernel_times_all()
     assert n == 5
     us = {k: round(m / n * 1e3, 2) for k, m in zip(dog.Context.KERNEL_NAMES, ms)}
-    print("kernel us with the transform path:", us, flush=True)
-    assert all(m > 0 for m in ms)
+    print("kernel us with the transform path (min_taps %d):" % min_taps, us, flush=True)
+    # the transform jobs run in the blur passes' launches when the variant's
+    # kernels take their line length, else in launches of their own
+    assert us["pass1"] + us["fft1"] > 0 and us["pass2"] + us["fft2"] > 0 and us["nms"] > 0
+    assert all(m >= 0 for m in ms)
