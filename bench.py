@@ -366,10 +366,11 @@ def bench_paper_config(dog, torch, t_img, steps, nf):
             c.close()
 
 
-def bench_preprocess(dog, torch, img, prm, k, steps, nf):
+def bench_preprocess(dog, torch, img, prm, k, steps, nf, variant, min_taps):
     """Sec. 4.1's optional first step on raw camera counts of the headline
     frame: smoothing (sigma 1) and a 0.35 % contrast stretch alone, then the
-    whole pipeline (preprocess + detector) with nf frames in flight."""
+    whole pipeline (preprocess + detector, with the headline's blur variant,
+    8 if none was tuned, and transform threshold) with nf frames in flight."""
     import numpy as np
     counts = torch.from_numpy((img * 65535.0).astype(np.float32)).cuda()
     H, W = counts.shape
@@ -387,7 +388,8 @@ def bench_preprocess(dog, torch, img, prm, k, steps, nf):
         torch.cuda.synchronize()
         t_pre = (time.perf_counter() - t0) / steps
         for c, st, o in zip(ctxs, streams, outs):
-            c.set_variant(8)
+            c.set_variant(variant if variant >= 0 else 8)
+            c.set_dct(min_taps)
             for _ in range(3):
                 c.preprocess(counts, 1.0, 0.0035, out=o, stream=st)
                 c.detect_device(o, prm, stream=st)
@@ -539,7 +541,7 @@ def main() -> int:
         if args.only == "paper":
             sec = bench_paper_config(dog, torch, t_img, args.steps, nf)
         else:
-            sec = bench_preprocess(dog, torch, img, prm, k, args.steps, nf)
+            sec = bench_preprocess(dog, torch, img, prm, k, args.steps, nf, variant, min_taps)
         ctx.close()
         print(json.dumps({"section": args.only, args.only: sec}))
         return 0
@@ -712,7 +714,8 @@ def main() -> int:
     out["prune"] = bench_prune(dog, torch, ctx, t_img, prm)
     if not args.no_paper:
         out["paper_config"] = bench_paper_config(dog, torch, t_img, args.steps, nf)
-        out["preprocess"] = bench_preprocess(dog, torch, img, prm, k, args.steps, nf)
+        out["preprocess"] = bench_preprocess(dog, torch, img, prm, k, args.steps, nf,
+                                             variant, min_taps)
 
     # ---- uniform batch of 64 frames: batched entry point vs frame by frame
     if not args.no_batch:
