@@ -34,7 +34,7 @@ def kernel_hash() -> str:
     """First 16 hex digits of the SHA-256 of the kernel source and its shared
     header; names the kernel build in autotuner caches."""
     h = hashlib.sha256()
-    for name in ("kernels.hip", "dct.hip", "dct.h", "fft_job.h", "dog_internal.h"):
+    for name in ("kernels.hip", "dct.hip", "dct.h", "fft_job.h", "fft_wave.h", "dog_internal.h"):
         with open(os.path.join(CSRC, name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -25,14 +25,18 @@
 // Twiddles and transfer functions are FP64 values rounded once to fp32, from
 // host tables.
 //
-// A job (fft_job.h) blurs two lines that are consecutive columns of its
-// input (one complex sequence) and produces, from one forward transform, the
-// lines of every plane it lists.  The two passes of a frame:
-//   pass 1: the columns of the frame X[y][x] (lines along y), one forward
+// A job blurs two lines that are consecutive rows or columns of its input
+// (one complex sequence) and produces, from one forward transform, the lines
+// of every plane it lists.  Lines of 512 and 1024 values run one job per
+// wavefront, the FFT in registers with two exchanges through the wave's own
+// LDS (fft_wave.h); other lengths one job per workgroup, the FFT in the
+// workgroup's LDS (fft_job.h).  The separable passes of a transform-domain
+// plane run along x first, so that every job writes whole rows:
+//   pass 1: the rows of the frame X[y][x] (lines along x), one forward
 //           transform, then every transform-domain plane p, each output line
-//           a row of T_p (the transposed layout of the direct pass 1);
-//   pass 2: per plane, the columns of T_p (lines along x), output lines
-//           columns of L_p, the layout of the direct pass 2.
+//           a row of U_p[y][x] (kept in the slot of the plane's T_p);
+//   pass 2: per plane, the columns of U_p (lines along y), output lines rows
+//           of L_p[x][y], the layout of the direct pass 2.
 // The jobs of a pass run either in a launch of their own (this file) or in
 // the launch of the direct blur pass, before its tiles (kernels.hip).
 #include <hip/hip_ext.h>
@@ -40,6 +44,7 @@
 
 #include "dct.h"
 #include "fft_job.h"
+#include "fft_wave.h"
 
 namespace dog {
 
@@ -47,12 +52,19 @@ namespace {
 constexpr int kNT = 256;   // threads per job
 }  // namespace
 
-// One workgroup per job.
+// One workgroup per job, or per kFftWaveJobs wave jobs.
 template <int LOGN, bool VEC>
 __global__ void __launch_bounds__(kNT) k_fft_blur(LaunchArgs a, const FftJob* __restrict__ jobs)
 {
     extern __shared__ __align__(16) float2 lds[];
-    fft_job<LOGN, kNT, VEC>(a, jobs + blockIdx.x, lds);
+    if constexpr (fft_wave_len(LOGN)) {
+        static_assert(kNT == 64 * kFftWaveJobs, "one job per wavefront");
+        const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+        fft_wave_job<LOGN, VEC>(a, jobs + (size_t)blockIdx.x * kFftWaveJobs + w,
+                                reinterpret_cast<float*>(lds) + w * WaveGeom<LOGN>::BUF);
+    } else {
+        fft_job<LOGN, kNT, VEC>(a, jobs + blockIdx.x, lds);
+    }
 }
 
 // The k_fft_blur instance for lines of 2^LOGN values.
@@ -69,6 +81,10 @@ extern "C" {
 
 size_t dogk_fft_lds_bytes(int N)
 {
+    if (N == 512)
+        return dog::WaveGeom<9>::LDS_BYTES;
+    if (N == 1024)
+        return dog::WaveGeom<10>::LDS_BYTES;
     return ((size_t)N + (size_t)N / 16 + (size_t)N / 2 + (size_t)N) * sizeof(float2);
 }
 
@@ -77,26 +93,29 @@ hipError_t dogk_fft_blur(const dog::LaunchArgs* args, const dog::FftJob* d_jobs,
 {
     if (n_jobs <= 0)
         return hipSuccess;
-    if (logn < 6 || logn > 11)
+    if (logn < 6 || logn > 11 || n_jobs % dog::fft_jobs_per_group(logn) != 0)
         return hipErrorInvalidValue;
+    const int grid = n_jobs / dog::fft_jobs_per_group(logn);
     const void* const table[6] = {dog::fft_fn<6>(vec),  dog::fft_fn<7>(vec),
                                   dog::fft_fn<8>(vec),  dog::fft_fn<9>(vec),
                                   dog::fft_fn<10>(vec), dog::fft_fn<11>(vec)};
     const void* fn = table[logn - 6];
     const size_t lds_bytes = dogk_fft_lds_bytes(1 << logn);
-    static size_t allowed[6][2] = {};   // dynamic LDS each instance has been allowed
-    if (lds_bytes > allowed[logn - 6][vec ? 1 : 0]) {
+    // dynamic LDS each instance has been allowed
+    static size_t allowed[6][2] = {};
+    size_t& ok = allowed[logn - 6][vec ? 1 : 0];
+    if (lds_bytes > ok) {
         const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  (int)lds_bytes);
         if (e != hipSuccess)
             return e;
-        allowed[logn - 6][vec ? 1 : 0] = lds_bytes;
+        ok = lds_bytes;
     }
     const dog::FftJob* jobs = d_jobs;
     void* params[] = {const_cast<dog::LaunchArgs*>(args), &jobs};
-    return ev ? hipExtLaunchKernel(fn, dim3(n_jobs), dim3(256), params, lds_bytes, stream,
-                                   ev[0], ev[1], 0)
-              : hipLaunchKernel(fn, dim3(n_jobs), dim3(256), params, lds_bytes, stream);
+    return ev ? hipExtLaunchKernel(fn, dim3(grid), dim3(256), params, lds_bytes, stream, ev[0],
+                                   ev[1], 0)
+              : hipLaunchKernel(fn, dim3(grid), dim3(256), params, lds_bytes, stream);
 }
 
 }  // extern "C"

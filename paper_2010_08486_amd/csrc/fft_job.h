@@ -3,8 +3,8 @@
 // such jobs in the same launch as their direct tiles.  Not part of the
 // public C ABI.
 //
-// A job blurs two lines u1, u2 of N = 2^LOGN values (consecutive columns of
-// its input) by the kernels of its planes, as products in the type-II cosine
+// A job blurs two lines u1, u2 of N = 2^LOGN values (consecutive rows or
+// columns of its input) by the kernels of its planes, as products in the type-II cosine
 // transform domain (exact for the half-sample symmetric border; the module
 // comment of dct.hip gives the transforms):
 //   1. load both lines as z = v1 + i v2, v the even/odd reordering of u, at
@@ -13,7 +13,7 @@
 //   3. for each pair of frequencies (k, N-k), the cosine coefficients of both
 //      lines, kept in registers;
 //   4. per plane: scale by the plane's transfer function (H/N), form the
-//      inverse sequence, inverse FFT, store both lines.
+//      inverse sequence, inverse FFT, store both lines as rows of the plane.
 // Every global load of a phase is issued before the first is waited for
 // (loop bounds are compile-time constants; loads past the end read a valid
 // element again, so no load sits in a branch).
@@ -24,12 +24,16 @@
 #include "dct.h"
 #include "dog_internal.h"
 
-// Pointers into the global address space.  The qualifier only exists for
-// the device compilation pass; the host pass sees plain pointers.
+// Pointers into the global address space, and into memory no kernel
+// writes (loads through the latter may go through the scalar cache when
+// every lane reads the same address).  The qualifiers only exist for the
+// device compilation pass; the host pass sees plain pointers.
 #if defined(__HIP_DEVICE_COMPILE__)
 #define DOG_GLOBAL_AS __attribute__((address_space(1)))
+#define DOG_CONST_AS __attribute__((address_space(4)))   // read-only for the kernel
 #else
 #define DOG_GLOBAL_AS
+#define DOG_CONST_AS
 #endif
 
 namespace dog {
@@ -153,8 +157,8 @@ struct FftGeom {
 };
 
 // The job at jp, run by the NT threads of the workgroup with `lds` (at least
-// FftGeom::LDS_BYTES, 8-byte aligned).  VEC: the input rows hold the two
-// lines at 8-byte aligned addresses.  Returns at once for a job with no
+// FftGeom::LDS_BYTES, 8-byte aligned).  VEC: the input rows hold a column
+// job's two lines at 8-byte aligned addresses.  Returns at once for a job with no
 // planes (padding); every barrier is reached by all NT threads otherwise.
 template <int LOGN, int NT, bool VEC>
 __device__ __forceinline__ void fft_job(const LaunchArgs& a, const FftJob* __restrict__ jp,
@@ -179,7 +183,7 @@ __device__ __forceinline__ void fft_job(const LaunchArgs& a, const FftJob* __res
         pitch = f.src_stride;
     }
     const uint32_t line0 = (uint32_t)jp->line0;
-    const bool out_rows = jp->out_rows != 0;
+    const bool in_rows = jp->in_rows != 0;
     const size_t out_pitch = (size_t)jp->out_pitch;
     const auto tw_g = gptr(jp->tw);
     const auto post_g = gptr(jp->post);
@@ -194,11 +198,16 @@ __device__ __forceinline__ void fft_job(const LaunchArgs& a, const FftJob* __res
 #pragma unroll
     for (int q = 0; q < G::LOADS; ++q) {
         const uint32_t n = min(tid + (uint32_t)q * NT, N - 1u);
-        const size_t o = (size_t)n * pitch + line0;
-        if (VEC)
-            v[q] = *reinterpret_cast<const DOG_GLOBAL_AS float2*>(in_g + o);
-        else
-            v[q] = make_float2(in_g[o], in_g[o + 1]);
+        if (in_rows) {
+            const size_t o = (size_t)line0 * pitch + n;
+            v[q] = make_float2(in_g[o], in_g[o + pitch]);
+        } else {
+            const size_t o = (size_t)n * pitch + line0;
+            if (VEC)
+                v[q] = *reinterpret_cast<const DOG_GLOBAL_AS float2*>(in_g + o);
+            else
+                v[q] = make_float2(in_g[o], in_g[o + 1]);
+        }
     }
     float2 twr[G::TW], pr[G::LOADS];
 #pragma unroll
@@ -283,30 +292,17 @@ __device__ __forceinline__ void fft_job(const LaunchArgs& a, const FftJob* __res
         __syncthreads();
         fft_seq<true, LOGN, NT>(buf, tw);
 
-        // ---- store: u[2n] = v[n], u[2n+1] = v[N-1-n] per line
-        if (out_rows) {
-            // the two lines are rows line0 and line0 + 1 of the plane
+        // ---- store: u[2n] = v[n], u[2n+1] = v[N-1-n] per line; the two
+        // lines are rows line0 and line0 + 1 of the plane
 #pragma unroll
-            for (int q = 0; q < G::LOADS; ++q) {
-                const uint32_t n = tid + (uint32_t)q * NT;
-                if (n < half) {
-                    const float2 x = buf[pd(n)], y = buf[pd(N - 1u - n)];
-                    const size_t o = (size_t)line0 * out_pitch + 2 * n;
-                    *reinterpret_cast<DOG_GLOBAL_AS float2*>(out + o) = make_float2(x.x, y.x);
-                    *reinterpret_cast<DOG_GLOBAL_AS float2*>(out + o + out_pitch) =
-                        make_float2(x.y, y.y);
-                }
-            }
-        } else {
-            // position n of the two lines is one 8-byte piece of row n
-#pragma unroll
-            for (int q = 0; q < G::LOADS; ++q) {
-                const uint32_t n = tid + (uint32_t)q * NT;
-                if (n < N) {
-                    const uint32_t idx = (n & 1u) ? N - 1u - (n >> 1) : (n >> 1);
-                    *reinterpret_cast<DOG_GLOBAL_AS float2*>(out + (size_t)n * out_pitch +
-                                                             line0) = buf[pd(idx)];
-                }
+        for (int q = 0; q < G::LOADS; ++q) {
+            const uint32_t n = tid + (uint32_t)q * NT;
+            if (n < half) {
+                const float2 x = buf[pd(n)], y = buf[pd(N - 1u - n)];
+                const size_t o = (size_t)line0 * out_pitch + 2 * n;
+                *reinterpret_cast<DOG_GLOBAL_AS float2*>(out + o) = make_float2(x.x, y.x);
+                *reinterpret_cast<DOG_GLOBAL_AS float2*>(out + o + out_pitch) =
+                    make_float2(x.y, y.y);
             }
         }
         __syncthreads();   // the buffer is refilled by the next plane

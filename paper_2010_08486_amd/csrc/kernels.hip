@@ -31,6 +31,7 @@
 
 #include "dog_internal.h"
 #include "fft_job.h"
+#include "fft_wave.h"
 
 // Pointers into the constant (scalar-load) address space.  The qualifier only
 // exists for the device compilation pass; the host pass of this file sees
@@ -375,11 +376,19 @@ __global__ void __launch_bounds__(64 * NW) k_blur_lds(LaunchArgs a)
         a.cand->count = 0u;  // read by the local-maximum kernel of this sequence
     int wg = blockIdx.x;
     if constexpr (FFTLOGN > 0) {
-        static_assert(FftGeom<FFTLOGN, 64 * NW>::LDS_BYTES <= sizeof(lds4), "job fits the ring");
+        static_assert(fft_merged_lds<FFTLOGN, NW>() <= sizeof(lds4), "jobs fit the ring");
         const int nf = a.n_fft[PASS - 1];
         if (wg < nf) {
-            fft_job<FFTLOGN, 64 * NW, PASS == 2 || WIDE>(a, a.fft_jobs[PASS - 1] + wg,
-                                                          reinterpret_cast<float2*>(lds4));
+            if constexpr (fft_wave_len(FFTLOGN)) {
+                // one job per wavefront of the first kFftWaveJobs
+                if (wv < kFftWaveJobs)
+                    fft_wave_job<FFTLOGN, PASS == 2 || WIDE>(
+                        a, a.fft_jobs[PASS - 1] + (size_t)wg * kFftWaveJobs + wv,
+                        reinterpret_cast<float*>(lds4) + wv * WaveGeom<FFTLOGN>::BUF);
+            } else {
+                fft_job<FFTLOGN, 64 * NW, PASS == 2 || WIDE>(a, a.fft_jobs[PASS - 1] + wg,
+                                                              reinterpret_cast<float2*>(lds4));
+            }
             return;
         }
         wg -= nf;
@@ -811,7 +820,7 @@ struct KernelSet {
 template <int PASS, int S, int NW, int P, bool WIDE, int LOGN>
 static const void* merged_fn()
 {
-    if constexpr (FftGeom<LOGN, 64 * NW>::LDS_BYTES <= (size_t)(NW + 2) * S * 256)
+    if constexpr (fft_merged_lds<LOGN, NW>() <= (size_t)(NW + 2) * S * 256)
         return reinterpret_cast<const void*>(&k_blur_lds<PASS, S, NW, P, WIDE, LOGN>);
     else
         return nullptr;

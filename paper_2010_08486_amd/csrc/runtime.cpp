@@ -352,6 +352,33 @@ static std::vector<T> xcd_order(const std::vector<T>& v)
     return out;
 }
 
+// Transform jobs in launch order when each workgroup takes g consecutive
+// jobs: padded with empty jobs to whole groups, the groups in XCD-local order
+// (xcd_order), their count padded with empty groups to a multiple of `round`.
+static size_t grouped_jobs(size_t n, int g, int round)
+{
+    size_t groups = (n + (size_t)g - 1) / (size_t)g;
+    groups = (groups + (size_t)round - 1) / (size_t)round * (size_t)round;
+    return groups * (size_t)g;
+}
+
+static std::vector<FftJob> group_jobs(const std::vector<FftJob>& v, int g, int round)
+{
+    std::vector<size_t> ids((v.size() + (size_t)g - 1) / (size_t)g);
+    for (size_t i = 0; i < ids.size(); ++i)
+        ids[i] = i;
+    ids = xcd_order(ids);
+    std::vector<FftJob> out;
+    out.reserve(grouped_jobs(v.size(), g, round));
+    for (size_t id : ids)
+        for (int k = 0; k < g; ++k) {
+            const size_t i = id * (size_t)g + (size_t)k;
+            out.push_back(i < v.size() ? v[i] : FftJob{});   // no planes: does nothing
+        }
+    out.resize(grouped_jobs(v.size(), g, round), FftJob{});
+    return out;
+}
+
 static constexpr size_t kRecBytes = sizeof(CandRec);
 static constexpr uint32_t kUnpublished = 0xffffffffu;  // host-side count before a launch
 
@@ -703,6 +730,23 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
                     v.push_back((float)std::cos(a));
                     v.push_back((float)std::sin(a));
                 }
+                // wave jobs' per-lane factors: W_N^(l 2^i) for 2^i < E, then
+                // W_64^((l mod B) 2^i) for 2^i < A, rows of 64 lanes
+                const int lgn = ilog2(N);
+                if (fft_wave_len(lgn)) {
+                    const int E = N / 64, A = E >= 16 ? 16 : 8, B = 64 / A;
+                    auto push = [&](long long t, long long period) {
+                        const double a = -2.0 * M_PI * (double)(t % period) / (double)period;
+                        v.push_back((float)std::cos(a));
+                        v.push_back((float)std::sin(a));
+                    };
+                    for (int k = 1; k < E; k *= 2)
+                        for (int l = 0; l < 64; ++l)
+                            push((long long)l * k, N);
+                    for (int c = 1; c < A; c *= 2)
+                        for (int l = 0; l < 64; ++l)
+                            push((long long)(l % B) * c, 64);
+                }
             }
             const size_t at = dtab.size();
             dtab.insert(dtab.end(), v.begin(), v.end());
@@ -745,7 +789,7 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
         const bool wide_src = key[0] != 0;   // frames' rows allow 16-byte loads
         FftLaunch fl{};
         fl.vec[0] = wide_src ? 1 : 0;
-        fl.vec[1] = 1;                       // T planes: pitch a multiple of 64
+        fl.vec[1] = 1;                       // U planes: row pitch W, a power of two
         for (int f = 0; f < n; ++f) {
             if (dctp[f].empty())
                 continue;
@@ -754,43 +798,25 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
             const size_t plane = (size_t)W * (size_t)pt;
             float* T0 = planes + off[f];
             float* L0 = T0 + (size_t)n_g * plane;
-            // pass 1: the frame's columns (lines along y, N = H) -> rows of T_p,
-            // up to kFftMaxPlanes planes per forward transform
-            for (size_t g0 = 0; g0 < dctp[f].size(); g0 += kFftMaxPlanes) {
-                const int ng = (int)std::min<size_t>(kFftMaxPlanes, dctp[f].size() - g0);
+            // the transform-domain planes blur along x first: pass 1 takes the
+            // frame's rows (N = W) to rows of U_p, U_p[y][x] at row pitch W
+            // in the slot of T_p (H W <= W pt floats); pass 2 takes the
+            // columns of U_p (N = H) to rows of L_p, the transposed layout of
+            // the direct blur.  Every store writes whole rows; only pass 2
+            // reads across rows.  Pass 1 shares one forward transform among
+            // up to kFftMaxPlanes planes (one for lines that run one job per
+            // wavefront: the repeated forward transform costs less than
+            // holding the coefficients across the inverse ones).
+            const int per_job = fft_wave_len(ilog2(W)) ? 1 : kFftMaxPlanes;
+            for (size_t g0 = 0; g0 < dctp[f].size(); g0 += per_job) {
+                const int ng = (int)std::min<size_t>(per_job, dctp[f].size() - g0);
                 FftPlaneSet ps{};
                 SetFix sf{ng, {}};
                 for (int q = 0; q < ng; ++q) {
                     const int p = dctp[f][g0 + q];
                     ps.out[q] = T0 + (size_t)p * plane;
-                    sf.h[q] = transfer(H, p);
+                    sf.h[q] = transfer(W, p);
                 }
-                const size_t set = psets.size();
-                psets.push_back(ps);
-                set_fixes.push_back(sf);
-                const int lg = ilog2(H) - 6;
-                const size_t tw = twiddles(H);
-                for (int l0 = 0; l0 < W; l0 += kFftLines) {
-                    FftJob j{};
-                    j.in = nullptr;
-                    j.N = H;
-                    j.logn = ilog2(H);
-                    j.line0 = l0;
-                    j.frame = f;
-                    j.n_planes = ng;
-                    j.out_rows = 1;
-                    j.out_pitch = (int)pt;
-                    fixes.push_back({0, lg, djobs[0][lg].size(), tw, set});
-                    djobs[0][lg].push_back(j);
-                }
-            }
-            // pass 2: per plane, the columns of T_p (lines along x, N = W) ->
-            // columns of L_p
-            for (int p : dctp[f]) {
-                FftPlaneSet ps{};
-                ps.out[0] = L0 + (size_t)p * plane;
-                SetFix sf{1, {}};
-                sf.h[0] = transfer(W, p);
                 const size_t set = psets.size();
                 psets.push_back(ps);
                 set_fixes.push_back(sf);
@@ -798,14 +824,36 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
                 const size_t tw = twiddles(W);
                 for (int l0 = 0; l0 < H; l0 += kFftLines) {
                     FftJob j{};
-                    j.in = T0 + (size_t)p * plane;
-                    j.in_pitch = (int)pt;
+                    j.in = nullptr;
+                    j.in_rows = 1;
                     j.N = W;
-                    j.logn = ilog2(W);
+                    j.line0 = l0;
+                    j.frame = f;
+                    j.n_planes = ng;
+                    j.out_pitch = W;
+                    fixes.push_back({0, lg, djobs[0][lg].size(), tw, set});
+                    djobs[0][lg].push_back(j);
+                }
+            }
+            for (int p : dctp[f]) {
+                FftPlaneSet ps{};
+                ps.out[0] = L0 + (size_t)p * plane;
+                SetFix sf{1, {}};
+                sf.h[0] = transfer(H, p);
+                const size_t set = psets.size();
+                psets.push_back(ps);
+                set_fixes.push_back(sf);
+                const int lg = ilog2(H) - 6;
+                const size_t tw = twiddles(H);
+                for (int l0 = 0; l0 < W; l0 += kFftLines) {
+                    FftJob j{};
+                    j.in = T0 + (size_t)p * plane;
+                    j.in_pitch = W;
+                    j.in_rows = 0;
+                    j.N = H;
                     j.line0 = l0;
                     j.frame = f;
                     j.n_planes = 1;
-                    j.out_rows = 0;
                     j.out_pitch = (int)pt;
                     fixes.push_back({1, lg, djobs[1][lg].size(), tw, set});
                     djobs[1][lg].push_back(j);
@@ -851,10 +899,9 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
         for (int i = 0; i < 2; ++i)
             for (int lg = 0; lg < 6; ++lg) {
                 o_djobs[i][lg] = o_end;
-                const size_t nj = djobs[i][lg].size();
-                const size_t padded = fl.merged_logn[i] == lg + 6
-                                          ? (nj + DOG_NXCD - 1) / DOG_NXCD * DOG_NXCD
-                                          : nj;
+                const size_t padded =
+                    grouped_jobs(djobs[i][lg].size(), fft_jobs_per_group(lg + 6),
+                                 fl.merged_logn[i] == lg + 6 ? DOG_NXCD : 1);
                 o_end = align_up(o_end + sizeof(FftJob) * padded, 256);
             }
         const size_t tbytes = o_end;
@@ -901,12 +948,15 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
             }
             for (int i = 0; i < 2; ++i)
                 for (int lg = 0; lg < 6; ++lg) {
-                    djobs[i][lg] = xcd_order(djobs[i][lg]);
-                    if (fl.merged_logn[i] == lg + 6) {
-                        while (djobs[i][lg].size() % DOG_NXCD)
-                            djobs[i][lg].push_back(FftJob{});   // no planes: does nothing
+                    // merged: whole rounds of the XCDs, so the tiles after
+                    // the jobs keep their XCD placement
+                    const bool merged = fl.merged_logn[i] == lg + 6;
+                    djobs[i][lg] = group_jobs(djobs[i][lg], fft_jobs_per_group(lg + 6),
+                                              merged ? DOG_NXCD : 1);
+                    if (merged)
                         mjobs[i] = djobs[i][lg];
-                    }
+                    else
+                        fl.n[i][lg] = (int)djobs[i][lg].size();
                     std::memcpy(h + o_djobs[i][lg], djobs[i][lg].data(),
                                 sizeof(FftJob) * djobs[i][lg].size());
                     fl.jobs[i][lg] = dt + o_djobs[i][lg];
@@ -932,7 +982,7 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
         for (int i = 0; i < 2; ++i) {
             const int lg = fl.merged_logn[i] - 6;
             a.fft_jobs[i] = lg >= 0 ? static_cast<const FftJob*>(fl.jobs[i][lg]) : nullptr;
-            a.n_fft[i] = lg >= 0 ? (int)mjobs[i].size() : 0;
+            a.n_fft[i] = lg >= 0 ? (int)mjobs[i].size() / fft_jobs_per_group(lg + 6) : 0;
         }
         c->n_gauss = n_g;
         c->debug_planes = dbg_D;
