@@ -314,27 +314,30 @@ __device__ __forceinline__ void fft_wave_job(const LaunchArgs& a, const FftJob* 
             x[E - 1 - m] = make_float2(wfft::bperm(mirror, p1[m].y), wfft::bperm(mirror, p2[m].y));
         }
     } else {
+        // (32-bit offsets: a column job's input is a plane of at most
+        // 2048 x 2048 values)
+        const uint32_t pt = (uint32_t)pitch;
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             const uint32_t n = l + 64u * m;
             const uint32_t r = n < half ? 2u * n : 2u * N - 1u - 2u * n;
-            const size_t o = (size_t)r * pitch + line0;
+            const uint32_t o = r * pt + line0;
             if (VEC)
                 x[m] = *reinterpret_cast<const DOG_GLOBAL_AS float2*>(in_g + o);
             else
                 x[m] = make_float2(in_g[o], in_g[o + 1]);
         }
     }
-    // the transfer function H[k] / N at k = l + 64 j
-    float hk[E];
-#pragma unroll
-    for (int j = 0; j < E; ++j)
-        hk[j] = hg[l + 64u * j];
     // exp(-i pi k / (2N)) at k = l + 64 j is post[l] post[64 j]; the second
     // factor is the same for every lane (scalar loads)
     const float2 el = post_g[l];
     const auto post_c = (const DOG_CONST_AS float2*)(jp->post);
     wfft::fft_wave<LOGN, false>(x, buf, t1, t2, l);
+    // the transfer function H[k] / N at k = l + 64 j
+    float hk[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j)
+        hk[j] = hg[l + 64u * j];
 
     // ---- P[k] = H_k C_k per line, C[k] = Re(exp(-i pi k / (2N)) V[k]) the
     // cosine coefficients, V1 = (Z[k] + conj Z[N-k]) / 2, V2 = (Z[k] -
