@@ -807,7 +807,13 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
             // up to kFftMaxPlanes planes (one for lines that run one job per
             // wavefront: the repeated forward transform costs less than
             // holding the coefficients across the inverse ones).
+            // Jobs go row pair by row pair, the plane groups of a pair side
+            // by side, so the groups re-reading a pair run on one XCD.
             const int per_job = fft_wave_len(ilog2(W)) ? 1 : kFftMaxPlanes;
+            const int lg1 = ilog2(W) - 6;
+            const size_t tw1 = twiddles(W);
+            std::vector<size_t> sets1;
+            std::vector<int> sizes1;
             for (size_t g0 = 0; g0 < dctp[f].size(); g0 += per_job) {
                 const int ng = (int)std::min<size_t>(per_job, dctp[f].size() - g0);
                 FftPlaneSet ps{};
@@ -817,24 +823,24 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
                     ps.out[q] = T0 + (size_t)p * plane;
                     sf.h[q] = transfer(W, p);
                 }
-                const size_t set = psets.size();
+                sets1.push_back(psets.size());
+                sizes1.push_back(ng);
                 psets.push_back(ps);
                 set_fixes.push_back(sf);
-                const int lg = ilog2(W) - 6;
-                const size_t tw = twiddles(W);
-                for (int l0 = 0; l0 < H; l0 += kFftLines) {
+            }
+            for (int l0 = 0; l0 < H; l0 += kFftLines)
+                for (size_t g = 0; g < sets1.size(); ++g) {
                     FftJob j{};
                     j.in = nullptr;
                     j.in_rows = 1;
                     j.N = W;
                     j.line0 = l0;
                     j.frame = f;
-                    j.n_planes = ng;
+                    j.n_planes = sizes1[g];
                     j.out_pitch = W;
-                    fixes.push_back({0, lg, djobs[0][lg].size(), tw, set});
-                    djobs[0][lg].push_back(j);
+                    fixes.push_back({0, lg1, djobs[0][lg1].size(), tw1, sets1[g]});
+                    djobs[0][lg1].push_back(j);
                 }
-            }
             for (int p : dctp[f]) {
                 FftPlaneSet ps{};
                 ps.out[0] = L0 + (size_t)p * plane;
