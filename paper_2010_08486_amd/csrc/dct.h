@@ -13,6 +13,11 @@ constexpr int kFftMaxN = 2048;      // longest line
 constexpr int kFftMaxPlanes = 16;   // planes one job produces from one forward transform
 constexpr int kFftWaveJobs = 4;     // wave jobs per workgroup (one per wavefront, one plane each)
 
+// FftJob::flags of the first of kFftWaveJobs wave jobs that are four column
+// jobs of one input with line pairs line0, + 2, + 4, + 6 from a multiple of 8
+// (16-byte aligned row pieces): one workgroup loads their lines together.
+constexpr int kFftGroupCols = 1;
+
 // Line lengths (log2) whose jobs run one per wavefront (fft_wave.h); the
 // others run one per workgroup of 256 threads (fft_job.h).
 constexpr bool fft_wave_len(int logn) { return logn == 9 || logn == 10; }
@@ -47,7 +52,7 @@ struct FftJob {
     int32_t line0;
     int32_t frame;
     int32_t n_planes;
-    int32_t reserved;
+    int32_t flags;           // first job of a group: kFftGroupCols or 0
     int32_t out_pitch;
     const FftPlaneSet* planes;   // the n_planes planes' outputs and transfer functions
 };

@@ -60,8 +60,15 @@ __global__ void __launch_bounds__(kNT) k_fft_blur(LaunchArgs a, const FftJob* __
     if constexpr (fft_wave_len(LOGN)) {
         static_assert(kNT == 64 * kFftWaveJobs, "one job per wavefront");
         const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-        fft_wave_job<LOGN, VEC>(a, jobs + (size_t)blockIdx.x * kFftWaveJobs + w,
-                                reinterpret_cast<float*>(lds) + w * WaveGeom<LOGN>::BUF);
+        const FftJob* g = jobs + (size_t)blockIdx.x * kFftWaveJobs;
+        float* bufs = reinterpret_cast<float*>(lds);
+        float2 x[WaveGeom<LOGN>::E];
+        if (g->flags == kFftGroupCols) {
+            fft_wave_load_cols<LOGN>(g, bufs, x);
+            fft_wave_job<LOGN, VEC, true>(a, g + w, bufs + w * WaveGeom<LOGN>::BUF, x);
+        } else {
+            fft_wave_job<LOGN, VEC>(a, g + w, bufs + w * WaveGeom<LOGN>::BUF, x);
+        }
     } else {
         fft_job<LOGN, kNT, VEC>(a, jobs + blockIdx.x, lds);
     }

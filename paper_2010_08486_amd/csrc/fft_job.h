@@ -52,6 +52,7 @@ __device__ __forceinline__ DOG_GLOBAL_AS T* gptr_w(T* p)
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b)
 {
+#pragma clang fp contract(on)
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 

@@ -73,6 +73,7 @@ constexpr int log2c(int r) { return r <= 1 ? 0 : 1 + log2c(r / 2); }
 template <bool INV>
 __device__ __forceinline__ float2 rot16(float2 v, int e)
 {
+#pragma clang fp contract(on)
     if (e == 0)
         return v;
     if (e == 4)
@@ -88,6 +89,7 @@ __device__ __forceinline__ float2 rot16(float2 v, int e)
 template <int R, bool INV>
 __device__ __forceinline__ void dft(float2* x)
 {
+#pragma clang fp contract(on)
     constexpr int LB = log2c(R);
     float2 t[R];
 #pragma unroll
@@ -121,6 +123,10 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Multiply-adds in this file are fused only within one expression (clang fp
+// contract on), so every kernel that inlines a job rounds alike: a frame's
+// planes are bitwise the same whichever launch runs its jobs.
+
 // A wave-uniform value the compiler cannot see through: loads addressed
 // from it stay where they are written (inside a loop, rather than hoisted out
 // of it and held in registers across the loop).
@@ -149,6 +155,7 @@ __device__ __forceinline__ float bperm(int addr, float v)
 template <int R, bool INV>
 __device__ __forceinline__ void apply_powers(float2* v, const DOG_GLOBAL_AS float2* t, uint32_t l)
 {
+#pragma clang fp contract(on)
     constexpr int LB = log2c(R);
     float2 p[LB];
 #pragma unroll
@@ -176,6 +183,7 @@ __device__ __forceinline__ void fft_wave(float2 (&x)[WaveGeom<LOGN>::E], float* 
                                          const DOG_GLOBAL_AS float2* t1,
                                          const DOG_GLOBAL_AS float2* t2, uint32_t l)
 {
+#pragma clang fp contract(on)
     using G = WaveGeom<LOGN>;
     constexpr int E = G::E, A = G::A, B = G::B, G2 = G::G2, G3 = G::G3;
     constexpr int R1 = 64 + G::P1, R2 = E * A + G::P2;
@@ -255,18 +263,21 @@ __device__ __forceinline__ void fft_wave(float2 (&x)[WaveGeom<LOGN>::E], float* 
 // The job at jp, run by one wavefront with its own `buf` (WaveGeom::BUF
 // floats of LDS): one plane (a job with no planes is padding and returns at
 // once).  VEC: the input's pairs of values (a row job's u[2n], u[2n+1]; a
-// column job's two lines) are 8-byte aligned.  jp->post is followed by the
+// column job's two lines) are 8-byte aligned.  PRE: x already holds the
+// job's lines in the layout fft_wave takes (fft_wave_load_cols); else the
+// job loads them into x.  jp->post is followed by the
 // factor tables of fft_wave: log2 E rows of 64, then log2 A rows of 64.
-template <int LOGN, bool VEC>
+template <int LOGN, bool VEC, bool PRE = false>
 __device__ __forceinline__ void fft_wave_job(const LaunchArgs& a, const FftJob* __restrict__ jp,
-                                             float* buf)
+                                             float* buf, float2 (&x)[WaveGeom<LOGN>::E])
 {
+#pragma clang fp contract(on)
     using namespace fftd;
     using G = WaveGeom<LOGN>;
     constexpr uint32_t N = G::N, half = N / 2;
     constexpr int E = G::E;
     static_assert(kFftLines == 2, "one complex sequence per job");
-    if (jp->n_planes <= 0)
+    if (!PRE && jp->n_planes <= 0)   // (a group loaded together has no padding)
         return;
     const float* in = jp->in;
     long long pitch = jp->in_pitch;
@@ -291,9 +302,10 @@ __device__ __forceinline__ void fft_wave_job(const LaunchArgs& a, const FftJob* 
     // m < E/2 (consecutive lanes, consecutive pairs); u[2n+1] is element
     // N - 1 - n, which lane 63 - l holds (index E - 1 - m).
     const int mirror = (int)((63u - l) << 2);
-    float2 x[E];
     const auto in_g = gptr(in);
-    if (in_rows) {
+    if (PRE) {
+        // x already holds the lines (fft_wave_load_cols)
+    } else if (in_rows) {
         const auto r1 = in_g + (size_t)line0 * pitch;
         const auto r2 = r1 + pitch;
         float2 p1[E / 2], p2[E / 2];
@@ -394,6 +406,64 @@ __device__ __forceinline__ void fft_wave_job(const LaunchArgs& a, const FftJob* 
         *reinterpret_cast<DOG_GLOBAL_AS float2*>(row1 + o) = make_float2(x[j].x, ox);
         *reinterpret_cast<DOG_GLOBAL_AS float2*>(row2 + o) = make_float2(x[j].y, oy);
     }
+}
+
+// Loads the lines of the four column jobs at g (marked kFftGroupCols) for
+// the four wavefronts of a workgroup of 256 threads, wave w taking lines
+// line0 + 2w, + 2w + 1: chunks of 256 input rows, each row's 8 values read
+// with two 16-byte loads (32 rows per load instruction, where the waves'
+// own 8-byte loads would touch 64) into the workgroup's LDS (rows padded to
+// 9 floats), then each wave's elements of the chunk from there.  Every
+// thread of the workgroup calls it (workgroup barriers); `lds` holds
+// 256 x 9 floats; x receives what fft_wave_job's own column loads would.
+template <int LOGN>
+__device__ __forceinline__ void fft_wave_load_cols(const FftJob* __restrict__ g, float* lds,
+                                                   float2 (&x)[WaveGeom<LOGN>::E])
+{
+    constexpr uint32_t N = 1u << LOGN, half = N / 2;
+    constexpr int E = WaveGeom<LOGN>::E, CH = 256, RS = 9;
+    static_assert(CH * RS <= kFftWaveJobs * WaveGeom<LOGN>::BUF, "chunk fits the wave buffers");
+    const auto in = fftd::gptr(g->in);
+    const uint32_t pitch = (uint32_t)g->in_pitch, col0 = (uint32_t)g->line0;
+    const uint32_t t = threadIdx.x, w = t >> 6, l = t & 63u;
+    const uint32_t tr = t >> 1, th = (t & 1u) * 4u;
+#pragma unroll
+    for (int c = 0; c < (int)N / CH; ++c) {
+        float4 v[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+            v[i] = *reinterpret_cast<const DOG_GLOBAL_AS float4*>(
+                in + (c * CH + tr + 128u * i) * pitch + col0 + th);
+        if (c > 0)
+            __syncthreads();   // the previous chunk's reads are done
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            float* d = lds + (tr + 128u * i) * RS + th;
+            d[0] = v[i].x;
+            d[1] = v[i].y;
+            d[2] = v[i].z;
+            d[3] = v[i].w;
+        }
+        __syncthreads();
+        // this chunk's elements: m = 2c, 2c + 1 (rows 2n) and E - 2 - 2c,
+        // E - 1 - 2c (rows 2N - 1 - 2n)
+        const int ms[4] = {2 * c, 2 * c + 1, E - 2 - 2 * c, E - 1 - 2 * c};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t n = l + 64u * ms[q];
+            const uint32_t r = n < half ? 2u * n : 2u * N - 1u - 2u * n;
+            const float* s = lds + (r - c * CH) * RS + 2u * w;
+            x[ms[q]] = make_float2(s[0], s[1]);
+        }
+        // the chunk's values in registers before the next barrier: a read
+        // left behind it (the compiler may sink loads past s_barrier, which
+        // it does not count as a memory operation) would race with the
+        // next chunk's writes or with another wave's exchanges
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            asm volatile("" : "+v"(x[ms[q]].x), "+v"(x[ms[q]].y));
+    }
+    __syncthreads();   // the buffers are the waves' own again
 }
 
 // LDS bytes a workgroup of NW wavefronts needs to run the jobs of lines of

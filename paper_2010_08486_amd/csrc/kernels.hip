@@ -381,10 +381,17 @@ __global__ void __launch_bounds__(64 * NW) k_blur_lds(LaunchArgs a)
         if (wg < nf) {
             if constexpr (fft_wave_len(FFTLOGN)) {
                 // one job per wavefront of the first kFftWaveJobs
-                if (wv < kFftWaveJobs)
+                const FftJob* g = a.fft_jobs[PASS - 1] + (size_t)wg * kFftWaveJobs;
+                float* bufs = reinterpret_cast<float*>(lds4);
+                float2 x[WaveGeom<FFTLOGN>::E];
+                if (NW == kFftWaveJobs && g->flags == kFftGroupCols) {
+                    fft_wave_load_cols<FFTLOGN>(g, bufs, x);
+                    fft_wave_job<FFTLOGN, true, true>(a, g + wv,
+                                                      bufs + wv * WaveGeom<FFTLOGN>::BUF, x);
+                } else if (wv < kFftWaveJobs) {
                     fft_wave_job<FFTLOGN, PASS == 2 || WIDE>(
-                        a, a.fft_jobs[PASS - 1] + (size_t)wg * kFftWaveJobs + wv,
-                        reinterpret_cast<float*>(lds4) + wv * WaveGeom<FFTLOGN>::BUF);
+                        a, g + wv, bufs + wv * WaveGeom<FFTLOGN>::BUF, x);
+                }
             } else {
                 fft_job<FFTLOGN, 64 * NW, PASS == 2 || WIDE>(a, a.fft_jobs[PASS - 1] + wg,
                                                               reinterpret_cast<float2*>(lds4));

@@ -379,6 +379,26 @@ static std::vector<FftJob> group_jobs(const std::vector<FftJob>& v, int g, int r
     return out;
 }
 
+// Marks the groups of kFftWaveJobs wave jobs whose lines a workgroup loads
+// together (fft_wave_load_cols): four column jobs of one input plane with
+// one pitch, line pairs line0, + 2, + 4, + 6 from a multiple of 8 (16-byte
+// aligned row pieces: the plane and its rows start at multiples of 64
+// floats).
+static void mark_column_groups(std::vector<FftJob>& v)
+{
+    for (size_t g = 0; g + kFftWaveJobs <= v.size(); g += kFftWaveJobs) {
+        const FftJob& f = v[g];
+        bool ok = f.n_planes > 0 && !f.in_rows && f.in && f.line0 % 8 == 0 && f.in_pitch % 4 == 0 &&
+                  ((uintptr_t)f.in % 16) == 0;
+        for (int k = 1; ok && k < kFftWaveJobs; ++k) {
+            const FftJob& e = v[g + k];
+            ok = e.n_planes > 0 && !e.in_rows && e.in == f.in && e.in_pitch == f.in_pitch &&
+                 e.line0 == f.line0 + 2 * k;
+        }
+        v[g].flags = ok ? kFftGroupCols : 0;
+    }
+}
+
 static constexpr size_t kRecBytes = sizeof(CandRec);
 static constexpr uint32_t kUnpublished = 0xffffffffu;  // host-side count before a launch
 
@@ -959,6 +979,8 @@ int launch_frames(dog_context* c, const Plan& P, const std::vector<FrameIn>& fra
                     const bool merged = fl.merged_logn[i] == lg + 6;
                     djobs[i][lg] = group_jobs(djobs[i][lg], fft_jobs_per_group(lg + 6),
                                               merged ? DOG_NXCD : 1);
+                    if (fft_wave_len(lg + 6))
+                        mark_column_groups(djobs[i][lg]);
                     if (merged)
                         mjobs[i] = djobs[i][lg];
                     else

@@ -143,3 +143,24 @@ def test_transform_kernel_times(dog, torch_mod, min_taps):
     # kernels take their line length, else in launches of their own
     assert us["pass1"] + us["fft1"] > 0 and us["pass2"] + us["fft2"] > 0 and us["nms"] > 0
     assert all(m >= 0 for m in ms)
+
+
+@pytest.mark.parametrize("H,W", [(512, 1024), (1024, 512), (1024, 1024)])
+def test_merged_and_separate_launches_agree(dog, torch_mod, H, W):
+    # the transform jobs inside the blur launches (variant 8) and in launches
+    # of their own (variant 14) give bitwise the same planes, every plane in
+    # the transform domain and with the direct planes beside; a workgroup
+    # that loads its four column jobs' lines together must not let a wave
+    # overwrite the staging buffer before every wave has read it
+    prm = dog.Params(**CAMERA)
+    img = synth.mixed_frame(2, H, W)
+    t = torch_mod.from_numpy(img).cuda()
+    for min_taps in (1, 200):
+        out = []
+        for v in (8, 14):
+            with dog.Context(0) as c:
+                c.set_variant(v)
+                c.set_dct(min_taps)
+                L, _ = c.debug_planes(t, prm)
+                out.append(L.cpu().numpy())
+        assert out[0].tobytes() == out[1].tobytes(), (H, W, min_taps)
