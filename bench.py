@@ -145,12 +145,13 @@ def blur_flops(radii, H, W, min_taps, merged):
     """Algorithmic FP32 flops per launch of the blur kernels of one H x W
     frame: 2 per tap and output pixel for the planes blurred directly; for
     the planes taken in the cosine-transform domain (kernels of at least
-    min_taps taps) the transforms' flops, counted per job of two lines of N
-    values as 5 N log2 N per complex FFT (one forward per job, one inverse
+    min_taps taps) the transforms' flops, counted per pair of lines of N
+    values as 5 N log2 N per complex FFT (one forward per pair, one inverse
     per plane) plus 8 N for the cosine coefficients and 14 N per plane for
-    the inverse sequence.  Pass 1's jobs take the frame's columns (N = H,
-    W / 2 jobs, every transform plane from one forward transform); pass 2's
-    the planes' rows (N = W, H / 2 jobs per plane).  merged: the jobs run in
+    the inverse sequence.  Pass 1 takes the frame's rows (N = W, H / 2
+    pairs, every transform plane from one forward transform: the forward
+    transforms the kernels repeat per plane are not counted); pass 2 the
+    planes' columns (N = H, W / 2 pairs per plane).  merged: the jobs run in
     the blur passes' launches (their flops count there), else in fft1 / fft2."""
     import math
     taps = [2 * int(r) + 1 for r in radii]
@@ -161,8 +162,8 @@ def blur_flops(radii, H, W, min_taps, merged):
     def job(N, planes):
         return 5.0 * N * math.log2(N) * (1 + planes) + 8.0 * N + 14.0 * N * planes
 
-    f1 = (W / 2) * job(H, n_tr) if n_tr else 0.0
-    f2 = n_tr * (H / 2) * job(W, 1) if n_tr else 0.0
+    f1 = (H / 2) * job(W, n_tr) if n_tr else 0.0
+    f2 = n_tr * (W / 2) * job(H, 1) if n_tr else 0.0
     out = {"pass1": direct, "pass2": direct, "nms": 0.0, "fft1": f1, "fft2": f2,
            "merged": merged}
     if merged:
