@@ -148,19 +148,22 @@ def test_transform_kernel_times(dog, torch_mod, min_taps):
 @pytest.mark.parametrize("H,W", [(512, 1024), (1024, 512), (1024, 1024)])
 def test_merged_and_separate_launches_agree(dog, torch_mod, H, W):
     # the transform jobs inside the blur launches (variant 8) and in launches
-    # of their own (variant 14) give bitwise the same planes, every plane in
-    # the transform domain and with the direct planes beside; a workgroup
-    # that loads its four column jobs' lines together must not let a wave
-    # overwrite the staging buffer before every wave has read it
+    # of their own (variant 13: two waves per workgroup, too few for the jobs'
+    # groups; variant 14: cost-balanced direct tiles) give bitwise the same
+    # planes, every plane in the transform domain and with the direct planes
+    # beside; a workgroup that loads its four column jobs' lines together
+    # must not let a wave overwrite the staging buffer before every wave has
+    # read it
     prm = dog.Params(**CAMERA)
     img = synth.mixed_frame(2, H, W)
     t = torch_mod.from_numpy(img).cuda()
     for min_taps in (1, 200):
         out = []
-        for v in (8, 14):
+        for v in (8, 13, 14):
             with dog.Context(0) as c:
                 c.set_variant(v)
                 c.set_dct(min_taps)
                 L, _ = c.debug_planes(t, prm)
                 out.append(L.cpu().numpy())
-        assert out[0].tobytes() == out[1].tobytes(), (H, W, min_taps)
+        for i in (1, 2):
+            assert out[0].tobytes() == out[i].tobytes(), (H, W, min_taps, i)
