@@ -87,7 +87,7 @@ extern "C" {
 
 const char* dog_last_error(void) { return dog::last_error(); }
 
-const char* dog_version(void) { return "dog-mi355x 0.2 (gfx950, LDS-staged separable stencil kernels)"; }
+const char* dog_version(void) { return "dog-mi355x 0.3 (gfx950, LDS-staged separable stencil and wave-level cosine-transform kernels)"; }
 
 void dog_blobs_free(dog_blob* blobs) { std::free(blobs); }
 
