@@ -141,6 +141,32 @@ def cpu_model() -> str:
     return "unknown"
 
 
+def roofline_entry(name, flop, nbytes, ms, traffic):
+    """Roofline of one launch from its algorithmic flops and bytes and its
+    mean duration: bound by HBM when its arithmetic intensity is below the
+    ridge point (FP32 peak / HBM peak, 19.7 flop per byte), by FP32
+    arithmetic above; the other ceiling's fraction rides along."""
+    t = ms * 1e-3
+    ai = flop / nbytes
+    ridge = PEAK_FP32_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
+    tf = flop / t / 1e12
+    gbs = nbytes / t / 1e9
+    r = {"kernel": name, "traffic": traffic, "algorithmic_flop_per_launch": flop,
+         "algorithmic_bytes_per_launch": nbytes, "arithmetic_intensity": round(ai, 2),
+         "ridge_point": round(ridge, 2), "frac_fp32_peak": round(tf / PEAK_FP32_TFLOPS, 4),
+         "frac_hbm_peak": round(gbs / PEAK_HBM_GBS, 4)}
+    if ai < ridge:
+        r.update({"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                  "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4)})
+    else:
+        r.update({"bound": "alu", "achieved": round(tf, 3), "peak": round(PEAK_FP32_TFLOPS, 1),
+                  "unit": "TFLOP/s", "frac": round(tf / PEAK_FP32_TFLOPS, 4)})
+    return {k: r[k] for k in ("bound", "kernel", "achieved", "peak", "unit", "frac", "traffic",
+                              "arithmetic_intensity", "ridge_point", "frac_fp32_peak",
+                              "frac_hbm_peak", "algorithmic_flop_per_launch",
+                              "algorithmic_bytes_per_launch")}
+
+
 def blur_flops(radii, H, W, min_taps, merged):
     """Algorithmic FP32 flops per launch of the blur kernels of one H x W
     frame: 2 per tap and output pixel for the planes blurred directly; for
@@ -646,14 +672,7 @@ def main() -> int:
     blur = [n for n in names if n != "nms"]
     dname = max(blur, key=lambda n: avg_ms[names.index(n)])
     dom = names.index(dname)
-    achieved = flops[dname] / (avg_ms[dom] * 1e-3) / 1e12
     traffic = measured_traffic(dname, variant, min_taps)
-    roofline = {"bound": "alu", "kernel": dname, "achieved": round(achieved, 3),
-                "peak": round(PEAK_FP32_TFLOPS, 1), "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
-                "kernel_avg_us": {n: round(m * 1e3, 2) for n, m in zip(names, avg_ms)},
-                "algorithmic_flop_per_launch": flops[dname],
-                "transform_min_taps": min_taps}
     # every kernel against both ceilings: algorithmic flops and bytes per launch
     n_g = k + 1
     pitch = (H + 63) // 64 * 64
@@ -668,6 +687,9 @@ def main() -> int:
     else:
         algo_bytes["pass1"] = 4.0 * H * W + (n_g - n_tr) * plane_b
         algo_bytes["pass2"] = 2.0 * (n_g - n_tr) * plane_b
+    roofline = roofline_entry(dname, flops[dname], algo_bytes[dname], avg_ms[dom], traffic)
+    roofline.update({"kernel_avg_us": {n: round(m * 1e3, 2) for n, m in zip(names, avg_ms)},
+                     "transform_min_taps": min_taps})
     roofline["per_kernel"] = {
         n: {"us": round(m * 1e3, 2),
             "tflops": round(flops[n] / (m * 1e-3) / 1e12, 2),
@@ -678,15 +700,12 @@ def main() -> int:
     avg_direct = [m / max(nseq_direct, 1) for m in kms_direct]
     fl_d = blur_flops(radii, H, W, 0, merged=False)
     d_dom = int(np.argmax(avg_direct[:2]))
-    d_ach = fl_d[names[d_dom]] / (avg_direct[d_dom] * 1e-3) / 1e12
-    roofline_direct = {"bound": "alu", "kernel": names[d_dom], "achieved": round(d_ach, 3),
-                       "peak": round(PEAK_FP32_TFLOPS, 1), "unit": "TFLOP/s",
-                       "frac": round(d_ach / PEAK_FP32_TFLOPS, 4),
-                       "traffic": measured_traffic(names[d_dom], variant, 0),
-                       "kernel_avg_us": {n: round(m * 1e3, 2)
-                                         for n, m in zip(names[:3], avg_direct[:3])},
-                       "algorithmic_flop_per_launch": fl_d[names[d_dom]],
-                       "kernel_ms_per_frame": round(sum(avg_direct), 4)}
+    d_bytes = 4.0 * H * W + n_g * plane_b if d_dom == 0 else 2.0 * n_g * plane_b
+    roofline_direct = roofline_entry(names[d_dom], fl_d[names[d_dom]], d_bytes,
+                                     avg_direct[d_dom], measured_traffic(names[d_dom], variant, 0))
+    roofline_direct.update({"kernel_avg_us": {n: round(m * 1e3, 2)
+                                              for n, m in zip(names[:3], avg_direct[:3])},
+                            "kernel_ms_per_frame": round(sum(avg_direct), 4)})
     kernel_sum_ms = sum(avg_ms)
 
     out = {"metric": "Mpixel-scales/s for DoG+NMS on 1 GPU; p99 frame latency, batched vs per-frame",
