@@ -101,14 +101,19 @@ def test_uneven_batch_full_sizes(dog, torch_mod):
                                                                      len(res[f]), exempt), flush=True)
 
 
-def test_three_in_flight_full_size(dog, torch_mod):
+@pytest.mark.parametrize("min_taps", [0, 53, 1])
+def test_three_in_flight_full_size(dog, torch_mod, min_taps):
     # the benchmark's timed configuration: three contexts, each on its own
-    # stream, steps queued before the previous ones are collected
+    # stream, steps queued before the previous ones are collected; every
+    # plane direct, the five widest planes in the transform domain (the
+    # threshold the autotuner picks for this frame), and every plane there
     torch = torch_mod
     prm = dog.Params(**CAMERA)
     imgs = [synth.camera_frame(seed=s) for s in (1, 2, 3, 4, 5)]
     dev = [torch.from_numpy(a).cuda() for a in imgs]
     ctxs = [dog.Context(0) for _ in range(3)]
+    for c in ctxs:
+        c.set_dct(min_taps)
     streams = [torch.cuda.Stream() for _ in range(3)]
     try:
         ref = [ctxs[0].detect_device(t, prm) for t in dev]
@@ -123,7 +128,7 @@ def test_three_in_flight_full_size(dog, torch_mod):
             got.append(ctxs[(i - nf + 1) % nf].finish())
         for i, b in enumerate(got):
             assert b.tobytes() == ref[i % 5].tobytes(), i
-        raw, D_o, sig, exempt = _oracle_check(ctxs[0], dev[1], imgs[1], prm)
+        raw, D_o, sig, exempt = _oracle_check(ctxs[0], dev[1], imgs[1], prm, planes=min_taps > 0)
         check_pruned(ref[1], raw, D_o, prm.threshold, sig, prm.overlap, exempt)
     finally:
         for c in ctxs:
