@@ -20,7 +20,7 @@ constexpr int kFftGroupCols = 1;
 
 // Line lengths (log2) whose jobs run one per wavefront (fft_wave.h); the
 // others run one per workgroup of 256 threads (fft_job.h).
-constexpr bool fft_wave_len(int logn) { return logn == 9 || logn == 10; }
+constexpr bool fft_wave_len(int logn) { return logn >= 9 && logn <= 11; }
 // Jobs per workgroup of the transform launches for lines of 2^logn values.
 constexpr int fft_jobs_per_group(int logn) { return fft_wave_len(logn) ? kFftWaveJobs : 1; }
 // float2 entries of the per-lane factor tables a wave job reads after the

@@ -27,8 +27,8 @@
 //
 // A job blurs two lines that are consecutive rows or columns of its input
 // (one complex sequence) and produces, from one forward transform, the lines
-// of every plane it lists.  Lines of 512 and 1024 values run one job per
-// wavefront, the FFT in registers with two exchanges through the wave's own
+// of every plane it lists.  Lines of 512, 1024 and 2048 values run one job
+// per wavefront, the FFT in registers with two exchanges through the wave's own
 // LDS (fft_wave.h); other lengths one job per workgroup, the FFT in the
 // workgroup's LDS (fft_job.h).  The separable passes of a transform-domain
 // plane run along x first, so that every job writes whole rows:
@@ -92,6 +92,8 @@ size_t dogk_fft_lds_bytes(int N)
         return dog::WaveGeom<9>::LDS_BYTES;
     if (N == 1024)
         return dog::WaveGeom<10>::LDS_BYTES;
+    if (N == 2048)
+        return dog::WaveGeom<11>::LDS_BYTES;
     return ((size_t)N + (size_t)N / 16 + (size_t)N / 2 + (size_t)N) * sizeof(float2);
 }
 

@@ -1,13 +1,13 @@
-// Transform-domain job run by one wavefront (device code), for lines of 512
-// and 1024 values; shared by the transform kernel of dct.hip and the blur
+// Transform-domain job run by one wavefront (device code), for lines of 512,
+// 1024 and 2048 values; shared by the transform kernel of dct.hip and the blur
 // kernels of kernels.hip.  Not part of the public C ABI.
 //
 // The job computes what fft_job.h computes (two lines u1, u2 blurred by the
 // kernels of its planes as products in the type-II cosine transform domain;
 // the module comment of dct.hip gives the transforms), with the complex FFT
 // of length N = 64 E laid out over the 64 lanes of one wavefront, E values
-// per lane, and factored as N = E x A x B with A B = 64 (E = 16: 16 x 16 x 4;
-// E = 8: 8 x 8 x 8):
+// per lane, and factored as N = E x A x B with A B = 64 (E = 32: 32 x 16 x 4;
+// E = 16: 16 x 16 x 4; E = 8: 8 x 8 x 8):
 //   pass 1: lane l holds x[l + 64 m], m < E, and takes the E-point DFT over m
 //           in registers, then multiplies by W_N^(l k1);
 //   pass 2: after an exchange through the wave's LDS buffer, each lane takes
@@ -37,7 +37,7 @@ namespace dog {
 // Factors and buffer sizes of a wave job with lines of 2^LOGN values.
 template <int LOGN>
 struct WaveGeom {
-    static_assert(fft_wave_len(LOGN), "wave jobs take lines of 512 or 1024 values");
+    static_assert(fft_wave_len(LOGN), "wave jobs take lines of 512, 1024 or 2048 values");
     static constexpr int N = 1 << LOGN;
     static constexpr int E = N / 64;                  // values per lane
     static constexpr int A = E >= 16 ? 16 : 8;        // pass-2 points
@@ -54,9 +54,39 @@ struct WaveGeom {
 
 namespace wfft {
 
-constexpr float kC1 = 0.92387953251128674f;   // cos(pi / 8)
-constexpr float kS1 = 0.38268343236508977f;   // sin(pi / 8)
-constexpr float kR = 0.70710678118654752f;    // cos(pi / 4)
+// cos and sin of 2 pi e / 32, e = 0..15 (the 32nd roots of unity)
+constexpr float kCos32[16] = {1.0f,
+                              0.98078528040323043f,    // cos(pi / 16)
+                              0.92387953251128674f,    // cos(pi / 8)
+                              0.83146961230254524f,    // cos(3 pi / 16)
+                              0.70710678118654752f,    // cos(pi / 4)
+                              0.55557023301960218f,    // cos(5 pi / 16)
+                              0.38268343236508977f,    // cos(3 pi / 8)
+                              0.19509032201612825f,    // cos(7 pi / 16)
+                              0.0f,
+                              -0.19509032201612825f,
+                              -0.38268343236508977f,
+                              -0.55557023301960218f,
+                              -0.70710678118654752f,
+                              -0.83146961230254524f,
+                              -0.92387953251128674f,
+                              -0.98078528040323043f};
+constexpr float kSin32[16] = {0.0f,
+                              0.19509032201612825f,
+                              0.38268343236508977f,
+                              0.55557023301960218f,
+                              0.70710678118654752f,
+                              0.83146961230254524f,
+                              0.92387953251128674f,
+                              0.98078528040323043f,
+                              1.0f,
+                              0.98078528040323043f,
+                              0.92387953251128674f,
+                              0.83146961230254524f,
+                              0.70710678118654752f,
+                              0.55557023301960218f,
+                              0.38268343236508977f,
+                              0.19509032201612825f};
 
 constexpr int bit_rev(int i, int bits)
 {
@@ -67,25 +97,24 @@ constexpr int bit_rev(int i, int bits)
 }
 constexpr int log2c(int r) { return r <= 1 ? 0 : 1 + log2c(r / 2); }
 
-// v exp(-2 pi i e / 16) (INV: exp(+2 pi i e / 16)), e in [0, 8); e is a
+// v exp(-2 pi i e / 32) (INV: exp(+2 pi i e / 32)), e in [0, 16); e is a
 // constant once the loops around the call are unrolled, so only one branch
 // remains, and the factors 1 and -i (+i) are applied exactly.
 template <bool INV>
-__device__ __forceinline__ float2 rot16(float2 v, int e)
+__device__ __forceinline__ float2 rot32(float2 v, int e)
 {
 #pragma clang fp contract(on)
     if (e == 0)
         return v;
-    if (e == 4)
+    if (e == 8)
         return INV ? make_float2(-v.y, v.x) : make_float2(v.y, -v.x);
-    const float c = e == 1 ? kC1 : e == 2 ? kR : e == 3 ? kS1 : e == 5 ? -kS1 : e == 6 ? -kR : -kC1;
-    const float s0 = e == 1 ? kS1 : e == 2 ? kR : e == 3 ? kC1 : e == 5 ? kC1 : e == 6 ? kR : kS1;
-    const float s = INV ? s0 : -s0;   // the factor is c + i s
+    const float c = kCos32[e];
+    const float s = INV ? kSin32[e] : -kSin32[e];   // the factor is c + i s
     return make_float2(v.x * c - v.y * s, v.x * s + v.y * c);
 }
 
-// R-point DFT (R = 4, 8, 16) of x[0..R-1] in registers, natural order in
-// and out: radix-2 decimation in time over a bit-reversed copy.
+// R-point DFT (R = 4, 8, 16, 32) of x[0..R-1] in registers, natural order
+// in and out: radix-2 decimation in time over a bit-reversed copy.
 template <int R, bool INV>
 __device__ __forceinline__ void dft(float2* x)
 {
@@ -102,7 +131,7 @@ __device__ __forceinline__ void dft(float2* x)
 #pragma unroll
             for (int j = 0; j < len / 2; ++j) {
                 const float2 u = t[i + j];
-                const float2 v = rot16<INV>(t[i + j + len / 2], j * (16 / len));
+                const float2 v = rot32<INV>(t[i + j + len / 2], j * (32 / len));
                 t[i + j] = make_float2(u.x + v.x, u.y + v.y);
                 t[i + j + len / 2] = make_float2(u.x - v.x, u.y - v.y);
             }
@@ -149,9 +178,9 @@ __device__ __forceinline__ float bperm(int addr, float v)
     return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
 }
 
-// v[k] *= w^k for k = 1..R-1 (R = 4, 8, 16), the lane's w^(2^i) read from
-// row i of t (64 lanes per row); every other power is a product of at most
-// three of them.  INV conjugates the factors.
+// v[k] *= w^k for k = 1..R-1 (R = 4, 8, 16, 32), the lane's w^(2^i) read
+// from row i of t (64 lanes per row); every other power is a product of at
+// most log2 R - 1 of them.  INV conjugates the factors.
 template <int R, bool INV>
 __device__ __forceinline__ void apply_powers(float2* v, const DOG_GLOBAL_AS float2* t, uint32_t l)
 {

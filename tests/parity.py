@@ -43,10 +43,11 @@ def check_candidates_exact(gpu_raw, D_gpu, thr):
     return len(yxi)
 
 
-def check_exempt_bound(exempt, n_raw):
+def check_exempt_bound(exempt, n_raw, reference=0):
     """Near-tie exemptions on a frame of natural shape: at most 1 % of the
-    candidates, rounded up to a whole voxel."""
-    allowed = math.ceil(MAX_EXEMPT_FRACTION * max(n_raw, 1))
+    candidates, rounded up to a whole voxel, or `reference` (the count of
+    another path on the same frame, whose own near ties bound the frame's)."""
+    allowed = max(math.ceil(MAX_EXEMPT_FRACTION * max(n_raw, 1)), reference)
     assert exempt <= allowed, "%d of %d candidates exempt (at most %d)" % (exempt, n_raw, allowed)
 
 

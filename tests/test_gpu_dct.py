@@ -36,6 +36,7 @@ def _parity(dog, torch, img, prm, min_taps, natural=True):
     max_abs = float(np.abs(img).max())
     with dog.Context(0) as c:
         L_d, _ = c.debug_planes(t, prm)             # every plane direct
+        raw_d = c.debug_candidates(t, prm)
         c.set_dct(min_taps)
         L_g, D_g = c.debug_planes(t, prm)
         torch.cuda.synchronize()
@@ -45,7 +46,10 @@ def _parity(dog, torch, img, prm, min_taps, natural=True):
         check_candidates_exact(raw, D_g, prm.threshold)
         exempt = check_candidates(raw, D_o, prm.threshold, sig, max_abs)
         if natural:
-            check_exempt_bound(exempt, len(raw))
+            # near ties are a property of the frame: at most 1 % of the
+            # candidates, or as many as the direct blur has on the same frame
+            exempt_d = check_candidates(raw_d, D_o, prm.threshold, sig, max_abs)
+            check_exempt_bound(exempt, len(raw), exempt_d)
         blobs = c.detect_device(t, prm)
         check_pruned(blobs, raw, D_o, prm.threshold, sig, prm.overlap, exempt)
         ms, n = c.kernel_times_all()
@@ -57,7 +61,7 @@ def _parity(dog, torch, img, prm, min_taps, natural=True):
     return raw, blobs, exempt, eL, eD, taken
 
 
-@pytest.mark.parametrize("H,W", [(1024, 1024), (512, 1024), (2048, 1024), (256, 256)])
+@pytest.mark.parametrize("H,W", [(1024, 1024), (512, 1024), (2048, 1024), (1024, 2048), (256, 256)])
 def test_transform_planes_camera_frames(dog, torch_mod, H, W):
     prm = dog.Params(**CAMERA)
     img = synth.camera_frame(seed=H * 7 + W, H=H, W=W, n_blobs=max(20, H * W // 2000))
