@@ -573,10 +573,11 @@ __device__ __forceinline__ float lane_next(float v)
 // -inf in dog_rows) and the row offset is forced into a scalar register.
 template <int BN>
 __device__ __forceinline__ void load_plane_rows(float (&v)[BN + 2], const FrameDesc& f, int p,
-                                                int x0, unsigned voff)
+                                                int x0, unsigned voff, bool live = true)
 {
+    // !live: a buffer of 0 bytes, so the loads return 0 and touch no memory
     const __amdgpu_buffer_rsrc_t rs = plane_rsrc(f.L + (long long)p * f.W * f.pitch,
-                                                 (unsigned)((long long)f.W * f.pitch * 4));
+                                                 live ? (unsigned)((long long)f.W * f.pitch * 4) : 0u);
     const int stride4 = (int)(f.pitch * 4);
 #pragma unroll
     for (int j = 0; j < BN + 2; ++j) {
@@ -612,8 +613,8 @@ __device__ __forceinline__ void dog_rows(const float (&La)[BN + 2], const float 
 #define DOG_LDS_RECS 512
 
 // Workgroup-local candidate buffer: survivors are appended in LDS and
-// flushed with one global atomic per tile; on LDS overflow a record goes
-// straight to the global list.
+// flushed with one global atomic per tile (a tile that overflows it is
+// walked again, its records going straight to the global list).
 struct CandSink {
     uint32_t* s_n;
     CandRec* s_rec;
@@ -625,15 +626,28 @@ struct CandSink {
 };
 
 // Append the voxels of one band row whose flag is set (wave ballot, prefix
-// popcount, one LDS atomic per wave).
-__device__ __forceinline__ void emit_row(const CandSink& snk, const FrameDesc& f, int lane, int y,
-                                         int x, int i, bool flag, float d)
+// popcount, one atomic per wave).  LDS mode: to the workgroup's LDS buffer,
+// counting (not storing) records beyond its capacity, so the walk issues no
+// global memory operation besides its plane loads.  GLOBAL mode (a tile whose
+// records overflowed the buffer, walked a second time): straight to the device
+// list and, below lim_h, to the pinned host copy; *s_end keeps the largest end.
+template <bool GLOBAL>
+__device__ __forceinline__ void emit_rec(const CandSink& snk, uint32_t* s_end,
+                                         const FrameDesc& f, int lane, int y, int x, int i,
+                                         bool flag, float d)
 {
     const unsigned long long bal = __ballot(flag);
     if (bal != 0ull) {
+        const unsigned cnt = (unsigned)__popcll(bal);
         unsigned base = 0;
-        if (lane == 0)
-            base = atomicAdd(snk.s_n, (unsigned)__popcll(bal));
+        if (lane == 0) {
+            if (GLOBAL) {
+                base = atomicAdd(&snk.cand->count, cnt);
+                atomicMax(s_end, base + cnt);
+            } else {
+                base = atomicAdd(snk.s_n, cnt);
+            }
+        }
         base = __shfl(base, 0);
         if (flag) {
             CandRec rec;
@@ -643,17 +657,13 @@ __device__ __forceinline__ void emit_row(const CandSink& snk, const FrameDesc& f
             rec.scale = i;
             rec.response = d;
             const unsigned idx = base + (unsigned)__popcll(bal & ((1ull << lane) - 1ull));
-            if (idx < DOG_LDS_RECS) {
+            if (GLOBAL) {
+                if (idx < snk.cap)
+                    snk.recs[idx] = rec;
+                if (idx < snk.lim_h)
+                    snk.host_recs[idx] = rec;
+            } else if (idx < DOG_LDS_RECS) {
                 snk.s_rec[idx] = rec;
-            } else {
-                // LDS buffer full: straight to the global list, and to the
-                // pinned host copy like every record below lim_h, since the
-                // host reads records [0, n_host) from there only
-                const unsigned g = atomicAdd(&snk.cand->count, 1u);
-                if (g < snk.cap)
-                    snk.recs[g] = rec;
-                if (g < snk.lim_h)
-                    snk.host_recs[g] = rec;
             }
         }
     }
@@ -663,9 +673,10 @@ __device__ __forceinline__ void emit_row(const CandSink& snk, const FrameDesc& f
 // of its 3x3x3 neighbourhood and exceeds the threshold.  One ballot decides
 // whether any row has a survivor; rows are then appended one by one.  The
 // debug build also stores the DoG plane.
-template <int BN, bool DBG>
-__device__ __forceinline__ void emit_plane(const CandSink& snk, const FrameDesc& f, int lane, int y,
-                                           int x0, int i, bool yout, const float (&dc)[BN],
+template <int BN, bool DBG, bool GLOBAL>
+__device__ __forceinline__ void test_plane(const CandSink& snk, uint32_t* s_end,
+                                           const FrameDesc& f, int lane, int y, int x0, int i,
+                                           bool yout, const float (&dc)[BN],
                                            const float (&s3m)[BN], const float (&s3c)[BN],
                                            const float (&s3n)[BN], float thr, long long plane_sz)
 {
@@ -684,85 +695,48 @@ __device__ __forceinline__ void emit_plane(const CandSink& snk, const FrameDesc&
     if (__ballot(any) != 0ull) {
 #pragma unroll
         for (int j = 0; j < BN; ++j)
-            emit_row(snk, f, lane, y, x0 + j, i, flag[j], dc[j]);
+            emit_rec<GLOBAL>(snk, s_end, f, lane, y, x0 + j, i, flag[j], dc[j]);
     }
 }
 
-// Flush the workgroup's LDS records with one global atomic.
-// The workgroup's records go to the device list and, for the first n_host
-// slots, also straight into pinned host memory, together with the end of the
-// workgroup's range; the host takes the count as the largest end once the
-// kernel has completed, so no readback copy is needed.
-__device__ __forceinline__ void flush_sink(const CandSink& snk, uint32_t* s_base,
-                                           const LaunchArgs& a)
+// One wave's walk over all scales of its BN band rows (rows x0 .. x0+BN-1 of
+// the transposed planes, lane = column y).  The band rows of the planes are
+// held in a ring of NB buffers, plane p in buffer p mod NB: step i forms
+// D_{i+1} from planes i+1 and i+2 while plane i+NB is loaded into the buffer
+// that plane i left, so NB-2 planes are in flight ahead of the one the step
+// waits for.  The loop is unrolled NB times so that every buffer index is a
+// constant: the ring rotates by renaming, not by register moves (a move would
+// wait for the load just issued).  Past the last plane the loads still issue,
+// from a buffer of 0 bytes (they return 0 and fetch nothing), so every path
+// issues the same loads and the waits count exactly.
+template <int BN, int NB, bool DBG, bool GLOBAL>
+__device__ __forceinline__ void nms_walk(const CandSink& snk, uint32_t* s_end,
+                                         const FrameDesc& f, const DOG_CONSTANT_AS LadderDesc* ld,
+                                         int lane, int y, bool ycol, bool yout, unsigned voff,
+                                         int x0)
 {
-    __syncthreads();
-    const uint32_t n = *snk.s_n < DOG_LDS_RECS ? *snk.s_n : DOG_LDS_RECS;
-    if (threadIdx.x == 0)
-        *s_base = n ? atomicAdd(&snk.cand->count, n) : 0u;
-    __syncthreads();
-    const uint32_t gbase = *s_base;
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-        const uint32_t g = gbase + i;
-        if (g < snk.cap)
-            snk.recs[g] = snk.s_rec[i];
-        if (g < snk.lim_h)
-            snk.host_recs[g] = snk.s_rec[i];
-    }
-    if (threadIdx.x == 0)
-        a.host_ends[blockIdx.x] = gbase + n;
-}
-
-// Local maxima of the DoG cube with threshold, compacted into records.
-// Tile = 62 output columns (y; lanes 1..62, lanes 0 and 63 are the halo)
-// x (BN*NW) rows (x) of one frame; every wave walks all scales.
-// Plane i+3 is loaded while plane i+1's DoG is formed, so loads overlap the
-// comparisons (measured faster than loading every plane up front, also for
-// short ladders).  DBG also writes the DoG planes (parity tests only).
-template <int BN, int NW, bool DBG>
-__global__ void __launch_bounds__(64 * NW) k_nms(LaunchArgs a)
-{
-    __shared__ uint32_t s_n;
-    __shared__ uint32_t s_base;
-    __shared__ CandRec s_rec[DOG_LDS_RECS];
-    const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    if (threadIdx.x == 0)
-        s_n = 0u;
-    __syncthreads();
-    const CandSink snk{&s_n, s_rec, a.cand, reinterpret_cast<CandRec*>(a.cand + 1), a.cap,
-                       a.host_recs, a.cap < a.n_host ? a.cap : a.n_host};
-    const Tile tl = my_tile(a.tiles3);
-    const FrameDesc f = frame_of(a, tl.frame);
-    const DOG_CONSTANT_AS LadderDesc* ld = cst(a.ladders) + f.ladder;
     const int k = ld->n_g - 1;
     const float thr = ld->thr;
-    const int y = tl.cb * DOG_NMS_COLS - 1 + lane;
-    const bool ycol = y >= 0 && y < f.H;
-    const bool yout = ycol && lane >= 1 && lane <= DOG_NMS_COLS;
-    const unsigned voff = (unsigned)(ycol ? y : 0) * 4u;
-    const int x0 = tl.band * (BN * NW) + wv * BN;
     const long long plane_sz = (long long)f.W * f.pitch;
-    if (x0 < f.W) {  // wave-uniform
-        float s3m[BN], s3c[BN], s3n[BN], dc[BN], dn[BN];
+    float s3m[BN], s3c[BN], s3n[BN], dc[BN], dn[BN];
 #pragma unroll
-        for (int j = 0; j < BN; ++j)
-            s3m[j] = -INFINITY;
-        float La[BN + 2], Lb[BN + 2], Lc[BN + 2], Ld[BN + 2];
-        load_plane_rows<BN>(La, f, 0, x0, voff);
-        load_plane_rows<BN>(Lb, f, 1, x0, voff);
-        load_plane_rows<BN>(Lc, f, k >= 2 ? 2 : 1, x0, voff);
-        dog_rows<BN>(La, Lb, ld->sigma[0], x0, f.W, ycol, s3c, dc);
-        for (int i = 0; i < k; ++i) {
-            // Lb = L_{i+1}, Lc = L_{i+2} (when i + 2 <= k)
+    for (int j = 0; j < BN; ++j)
+        s3m[j] = -INFINITY;
+    float L[NB][BN + 2];
+#pragma unroll
+    for (int p = 0; p < NB; ++p)
+        load_plane_rows<BN>(L[p], f, p <= k ? p : k, x0, voff, p <= k);
+    dog_rows<BN>(L[0], L[1], ld->sigma[0], x0, f.W, ycol, s3c, dc);
+    for (int i0 = 0; i0 < k; i0 += NB) {
+#pragma unroll
+        for (int m = 0; m < NB; ++m) {
+            const int i = i0 + m;
+            if (i >= k)
+                break;
+            load_plane_rows<BN>(L[m], f, i + NB <= k ? i + NB : k, x0, voff, i + NB <= k);
             if (i + 1 < k) {
-                load_plane_rows<BN>(Ld, f, i + 3 <= k ? i + 3 : k, x0, voff);
-                dog_rows<BN>(Lb, Lc, ld->sigma[i + 1], x0, f.W, ycol, s3n, dn);
-#pragma unroll
-                for (int j = 0; j < BN + 2; ++j) {
-                    Lb[j] = Lc[j];
-                    Lc[j] = Ld[j];
-                }
+                dog_rows<BN>(L[(m + 1) % NB], L[(m + 2) % NB], ld->sigma[i + 1], x0, f.W, ycol,
+                             s3n, dn);
             } else {
 #pragma unroll
                 for (int j = 0; j < BN; ++j) {
@@ -770,8 +744,8 @@ __global__ void __launch_bounds__(64 * NW) k_nms(LaunchArgs a)
                     dn[j] = -INFINITY;
                 }
             }
-            emit_plane<BN, DBG>(snk, f, lane, y, x0, i, yout, dc, s3m, s3c, s3n, thr,
-                                plane_sz);
+            test_plane<BN, DBG, GLOBAL>(snk, s_end, f, lane, y, x0, i, yout, dc, s3m, s3c, s3n,
+                                        thr, plane_sz);
 #pragma unroll
             for (int j = 0; j < BN; ++j) {
                 s3m[j] = s3c[j];
@@ -780,7 +754,70 @@ __global__ void __launch_bounds__(64 * NW) k_nms(LaunchArgs a)
             }
         }
     }
-    flush_sink(snk, &s_base, a);
+}
+
+// Plane buffers of the local-maximum walk: one plane in flight ahead of the
+// step's two.  Measured on the 1024x1024 frame (9 planes): 10.5 us with 3
+// buffers, 11.0 with 4, 12.2 with 5, 12.3 with 6.
+constexpr int kNmsRing = 3;
+
+// Local maxima of the DoG cube with threshold, compacted into records.
+// Tile = 62 output columns (y; lanes 1..62, lanes 0 and 63 are the halo)
+// x (BN*NW) rows (x) of one frame; every wave walks all scales, appending its
+// survivors to the workgroup's LDS buffer, which is then flushed with one
+// global atomic.  A tile with more survivors than the buffer holds (plateaus
+// of equal values) is walked again with every record going straight to the
+// device list.  DBG also writes the DoG planes (parity tests only).
+template <int BN, int NW, bool DBG, int NB>
+__global__ void __launch_bounds__(64 * NW) k_nms(LaunchArgs a)
+{
+    static_assert(NB >= 3, "the ring holds two planes and the one in flight");
+    __shared__ uint32_t s_n;
+    __shared__ uint32_t s_base;
+    __shared__ CandRec s_rec[DOG_LDS_RECS];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (threadIdx.x == 0) {
+        s_n = 0u;
+        s_base = 0u;
+    }
+    __syncthreads();
+    const CandSink snk{&s_n, s_rec, a.cand, reinterpret_cast<CandRec*>(a.cand + 1), a.cap,
+                       a.host_recs, a.cap < a.n_host ? a.cap : a.n_host};
+    const Tile tl = my_tile(a.tiles3);
+    const FrameDesc f = frame_of(a, tl.frame);
+    const DOG_CONSTANT_AS LadderDesc* ld = cst(a.ladders) + f.ladder;
+    const int y = tl.cb * DOG_NMS_COLS - 1 + lane;
+    const bool ycol = y >= 0 && y < f.H;
+    const bool yout = ycol && lane >= 1 && lane <= DOG_NMS_COLS;
+    const unsigned voff = (unsigned)(ycol ? y : 0) * 4u;
+    const int x0 = tl.band * (BN * NW) + wv * BN;
+    if (x0 < f.W)  // wave-uniform
+        nms_walk<BN, NB, DBG, false>(snk, &s_base, f, ld, lane, y, ycol, yout, voff, x0);
+    __syncthreads();
+    const uint32_t n = s_n;
+    if (n <= DOG_LDS_RECS) {
+        if (threadIdx.x == 0)
+            s_base = n ? atomicAdd(&snk.cand->count, n) : 0u;
+        __syncthreads();
+        const uint32_t gbase = s_base;
+        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const uint32_t g = gbase + i;
+            if (g < snk.cap)
+                snk.recs[g] = s_rec[i];
+            if (g < snk.lim_h)
+                snk.host_recs[g] = s_rec[i];
+        }
+        if (threadIdx.x == 0)
+            a.host_ends[blockIdx.x] = gbase + n;
+    } else {
+        // s_base (0 here) now keeps the largest end of the records written
+        if (x0 < f.W)
+            nms_walk<BN, NB, DBG, true>(snk, &s_base, f, ld, lane, y, ycol, yout, voff, x0);
+        __syncthreads();
+        if (threadIdx.x == 0)
+            a.host_ends[blockIdx.x] = s_base;
+    }
 }
 
 // dst[(p*H + y)*W + x] = src[(p*W + x)*pitch + y]: back to row-major planes.
@@ -869,8 +906,8 @@ static KernelSet make_lds_set()
     k.pass1 = reinterpret_cast<const void*>(&k_blur_lds<1, S, NW, P, false, 0, GROUP != 0>);
     k.pass1w = reinterpret_cast<const void*>(&k_blur_lds<1, S, NW, P, true, 0, GROUP != 0>);
     k.pass2 = reinterpret_cast<const void*>(&k_blur_lds<2, S, NW, P, true, 0, GROUP != 0>);
-    k.nms[0] = reinterpret_cast<const void*>(&k_nms<BN, NWN, false>);
-    k.nms[1] = reinterpret_cast<const void*>(&k_nms<BN, NWN, true>);
+    k.nms[0] = reinterpret_cast<const void*>(&k_nms<BN, NWN, false, kNmsRing>);
+    k.nms[1] = reinterpret_cast<const void*>(&k_nms<BN, NWN, true, kNmsRing>);
     k.S = S;
     k.R = P;
     k.NW = NW;
@@ -890,8 +927,8 @@ static KernelSet make_set()
     k.pass1w = nullptr;
     k.pass1 = reinterpret_cast<const void*>(&k_pass1<S, R, NW, BI>);
     k.pass2 = reinterpret_cast<const void*>(&k_pass2<S, R, NW, BI>);
-    k.nms[0] = reinterpret_cast<const void*>(&k_nms<BN, NWN, false>);
-    k.nms[1] = reinterpret_cast<const void*>(&k_nms<BN, NWN, true>);
+    k.nms[0] = reinterpret_cast<const void*>(&k_nms<BN, NWN, false, kNmsRing>);
+    k.nms[1] = reinterpret_cast<const void*>(&k_nms<BN, NWN, true, kNmsRing>);
     k.S = S;
     k.R = R;
     k.NW = NW;
