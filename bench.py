@@ -552,7 +552,7 @@ def main() -> int:
     if args.dct >= 0:
         ctx.set_dct(args.dct)
     if args.variant < 0 and not pmc:
-        v, us = ctx.autotune(t_img, prm, reps=5)
+        v, us = ctx.autotune(t_img, prm, reps=7)
         tune = {"variant": v, "geometry": dog.variant_info(v),
                 "kernel_us_per_variant": [round(u, 2) for u in us]}
     variant = tune["variant"] if tune else args.variant

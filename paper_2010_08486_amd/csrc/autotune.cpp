@@ -134,7 +134,8 @@ int dog_autotune(dog_context* ctx, const dog_params* params, const float* d_imag
     ctx->profiling = true;
     ctx->dct_forced = true;
     std::vector<std::vector<dog_blob>> out;
-    // mean kernel microseconds of one frame with variant v and threshold mt
+    // median over reps of the kernel microseconds of one frame with variant v
+    // and threshold mt (a median, so one slow launch cannot flip a choice)
     auto time_it = [&](int v, int mt, double* us) -> int {
         int r = ctx_set_variant(ctx, v);
         if (r != DOG_OK)
@@ -144,17 +145,22 @@ int dog_autotune(dog_context* ctx, const dog_params* params, const float* d_imag
         if ((r = run_frames(ctx, plan, fr, ctx->stream, &out, false, nullptr, nullptr, nullptr)) !=
             DOG_OK)
             return r;
-        for (double& m : ctx->kernel_ms)
-            m = 0.0;
-        ctx->kernel_launches = 0;
-        for (int i = 0; i < reps && r == DOG_OK; ++i)
-            r = run_frames(ctx, plan, fr, ctx->stream, &out, false, nullptr, nullptr, nullptr);
-        if (r != DOG_OK)
-            return r;
-        double ms = 0.0;
-        for (double m : ctx->kernel_ms)
-            ms += m;
-        *us = ms * 1e3 / (double)std::max<int64_t>(1, ctx->kernel_launches);
+        std::vector<double> per;
+        for (int i = 0; i < reps; ++i) {
+            for (double& m : ctx->kernel_ms)
+                m = 0.0;
+            ctx->kernel_launches = 0;
+            if ((r = run_frames(ctx, plan, fr, ctx->stream, &out, false, nullptr, nullptr,
+                                nullptr)) != DOG_OK)
+                return r;
+            double ms = 0.0;
+            for (double m : ctx->kernel_ms)
+                ms += m;
+            per.push_back(ms * 1e3 / (double)std::max<int64_t>(1, ctx->kernel_launches));
+        }
+        std::sort(per.begin(), per.end());
+        const size_t n = per.size();
+        *us = n % 2 ? per[n / 2] : 0.5 * (per[n / 2 - 1] + per[n / 2]);
         return DOG_OK;
     };
     // every variant at a threshold; the built-in default stands unless

@@ -757,8 +757,10 @@ __device__ __forceinline__ void nms_walk(const CandSink& snk, uint32_t* s_end,
 }
 
 // Plane buffers of the local-maximum walk: one plane in flight ahead of the
-// step's two.  Measured on the 1024x1024 frame (9 planes): 10.5 us with 3
-// buffers, 11.0 with 4, 12.2 with 5, 12.3 with 6.
+// step's two.  Measured on the 1024x1024 frame (9 planes, 4 rows per wave):
+// 10.5 us with 3 buffers, 11.0 with 4, 12.2 with 5, 12.3 with 6.  With 3
+// buffers and 4 waves per workgroup, 6 rows per wave took 9.9 us (100 VGPRs);
+// 2, 4 and 8 rows 11.9, 10.5 and 12.6 us; 8 waves of 2 or 4 rows 11.6 and 11.8.
 constexpr int kNmsRing = 3;
 
 // Local maxima of the DoG cube with threshold, compacted into records.
@@ -954,15 +956,15 @@ static const KernelSet kSets[] = {
     make_set<20, 3, 4, 1, 4, 4>(),
     make_set<12, 8, 4, 1, 4, 4>(),
     make_set<24, 3, 4, 1, 8, 4>(),
-    make_lds_set<16, 4, 2, 4, 4>(),
-    make_lds_set<16, 4, 4, 4, 4>(),
-    make_lds_set<12, 4, 2, 4, 4>(),
-    make_lds_set<8, 8, 2, 4, 4>(),
-    make_lds_set<16, 8, 2, 4, 4>(),
-    make_lds_set<16, 2, 2, 4, 4>(),
-    make_lds_set<16, 4, 2, 4, 4, 1>(),
-    make_lds_set<16, 4, 4, 4, 4, 1>(),
-    make_lds_set<16, 2, 2, 4, 4, 1>(),
+    make_lds_set<16, 4, 2, 6, 4>(),
+    make_lds_set<16, 4, 4, 6, 4>(),
+    make_lds_set<12, 4, 2, 6, 4>(),
+    make_lds_set<8, 8, 2, 6, 4>(),
+    make_lds_set<16, 8, 2, 6, 4>(),
+    make_lds_set<16, 2, 2, 6, 4>(),
+    make_lds_set<16, 4, 2, 6, 4, 1>(),
+    make_lds_set<16, 4, 4, 6, 4, 1>(),
+    make_lds_set<16, 2, 2, 6, 4, 1>(),
 };
 
 }  // namespace dog
