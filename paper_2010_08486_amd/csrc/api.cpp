@@ -322,6 +322,8 @@ int dog_prune_device(dog_context* ctx, const dog_params* params, const dog_blob*
     }
     const size_t sig_bytes = sizeof(double) * (size_t)P->n_g;
     const size_t out_bytes = sizeof(PruneHead) + sizeof(dog_blob) * (size_t)ctx->prn_blobs;
+    if (ctx->prn.bytes < sig_bytes)
+        ctx->prn_sig_dev = nullptr;   // the buffer is replaced: upload the ladder again
     if ((rc = ctx_alloc(ctx, &ctx->prn, sig_bytes, "pruning ladder")) != DOG_OK)
         return rc;
     // pinned: the ladder's staging, then the kernel's output (written by the
@@ -335,10 +337,15 @@ int dog_prune_device(dog_context* ctx, const dog_params* params, const dog_blob*
     std::vector<int64_t> hist(P->k, 0);
     bool on_host = n > (int64_t)ctx->prn_blobs;
     if (!on_host) {
-        DOG_HIP(hipStreamSynchronize(st));   // the staging area is reused
-        std::memcpy(h, P->sigma.data(), sig_bytes);
+        if (ctx->prn_sig_dev != ctx->prn.p || ctx->prn_sig != P->sigma) {
+            // a new ladder (or buffer): staged, then copied in stream order
+            DOG_HIP(hipStreamSynchronize(st));   // the staging area is reused
+            std::memcpy(h, P->sigma.data(), sig_bytes);
+            DOG_HIP(hipMemcpyAsync(ctx->prn.p, h, sig_bytes, hipMemcpyHostToDevice, st));
+            ctx->prn_sig = P->sigma;
+            ctx->prn_sig_dev = ctx->prn.p;
+        }
         head->status = 0;
-        DOG_HIP(hipMemcpyAsync(ctx->prn.p, h, sig_bytes, hipMemcpyHostToDevice, st));
         PruneArgs a{};
         a.cand = nullptr;
         a.recs = d_blobs;

@@ -12,11 +12,13 @@
 //      of the radii, with the starting sigmas) is listed per first blob, in
 //      the order of the second, each with its overlap test already taken on
 //      the starting sigmas; blobs are scanned in parallel, one per thread;
-//   4. one thread visits the pairs in (y, x, scale) order exactly as the
-//      host step does (a blob removed stops its own scan; of an overlapping
-//      pair the smaller sigma goes, the later blob on a tie; coalescing gives
-//      the survivor the mean sigma), re-taking the overlap test only where a
-//      sigma has changed by coalescing.  Pairs whose disks do not touch have
+//   4. the pairs are visited in (y, x, scale) order exactly as the host
+//      step does (a blob removed stops its own scan; of an overlapping pair
+//      the smaller sigma goes, the later blob on a tie; coalescing gives the
+//      survivor the mean sigma), re-taking the overlap test only where a
+//      sigma has changed by coalescing: by one thread when coalescing, and
+//      for plain pruning by one wave, which visits only the blobs with a
+//      pair over the limit and takes their pairs 64 at a time.  Pairs whose disks do not touch have
 //      overlap 0, which never exceeds the limit, and radii only shrink under
 //      coalescing, so no other pair can ever overlap;
 //   5. survivors are written in order with their final sigma, and counted in
@@ -280,6 +282,7 @@ __global__ void __launch_bounds__(kNT) k_prune(PruneArgs a)
             const double sa = sg[i];
             const double reach = 1.4142135623730951 * sa + rmax;
             uint32_t o = off[i];
+            bool any_over = false;
             for (uint32_t j = i + 1; j < n; ++j) {
                 const uint64_t kb = key[j];
                 const int yb = key_y(kb), xb = key_x(kb);
@@ -288,19 +291,70 @@ __global__ void __launch_bounds__(kNT) k_prune(PruneArgs a)
                 if (!may_touch(ya, xa, sa, yb, xb, sg[j]))
                     continue;
                 const bool over = overlap_fraction(ya, xa, sa, yb, xb, sg[j]) > a.overlap;
-                pairs[o++] = (uint16_t)(j | (over ? 0x8000u : 0u));
+                // bit 15: over the limit; bit 14: the first blob has the
+                // smaller starting sigma (it goes, unless coalescing changes
+                // a sigma first)
+                pairs[o++] = (uint16_t)(j | (over ? 0x8000u : 0u) | (sa < sg[j] ? 0x4000u : 0u));
+                any_over = any_over || over;
             }
+            if (any_over)
+                alive[i] = 3;   // bit 1: the blob has a pair over the limit
         }
         __syncthreads();
 
-        // ---- 4. the greedy visits, in order, by one thread
-        if (tid == 0) {
+        // ---- 4. the greedy visits, in order
+        if (!a.coalesce) {
+            // Plain pruning: sigmas never change, so only the pairs over the
+            // limit act, and which blob of such a pair goes is fixed.  Wave 0
+            // visits the blobs that have such a pair, in order; a blob still
+            // alive takes its pairs 64 at a time: of the pairs over the limit
+            // whose second blob is alive, the second blobs before the first
+            // pair the blob loses go, and the blob goes at that pair (its
+            // scan stops), exactly as in the one-by-one visit.  Each second
+            // blob appears once in a blob's pairs, so the lanes' updates do
+            // not interact, and the wave's LDS accesses complete in order.
+            if (wv == 0) {
+                for (uint32_t base = 0; base < n; base += 64) {
+                    const uint32_t il = base + lane;
+                    unsigned long long todo = __ballot(il < n && (alive[il] & 2u));
+                    while (todo) {
+                        const uint32_t i = base + (uint32_t)__builtin_ctzll(todo);
+                        todo &= todo - 1ull;
+                        if (!(alive[i] & 1u))
+                            continue;
+                        const uint32_t e1 = off[i + 1];
+                        for (uint32_t eb = off[i]; eb < e1; eb += 64) {
+                            const uint32_t e = eb + lane;
+                            bool act = false, lose = false;
+                            uint32_t j = 0;
+                            if (e < e1) {
+                                const uint32_t w = pairs[e];
+                                j = w & 0x0fffu;
+                                act = (w & 0x8000u) && (alive[j] & 1u);
+                                lose = act && (w & 0x4000u);
+                            }
+                            const unsigned long long lb = __ballot(lose);
+                            const unsigned long long before = lb ? (lb & (0ull - lb)) - 1ull : ~0ull;
+                            if (act && !lose && ((before >> lane) & 1ull))
+                                alive[j] = (uint8_t)(alive[j] & 2u);
+                            if (lb) {
+                                if (lane == 0)
+                                    alive[i] = (uint8_t)(alive[i] & 2u);
+                                break;
+                            }
+                        }
+                    }
+                }
+            }
+        } else if (tid == 0) {
+            // coalescing: a sigma may change at any pair, so one thread
+            // visits every pair in order, re-taking the test where it has
             for (uint32_t i = 0; i < n; ++i) {
-                if (!alive[i])
+                if (!(alive[i] & 1u))
                     continue;
                 for (uint32_t e = off[i]; e < off[i + 1]; ++e) {
                     const uint32_t j = pairs[e] & 0x0fffu;
-                    if (!alive[j])
+                    if (!(alive[j] & 1u))
                         continue;
                     bool over = (pairs[e] & 0x8000u) != 0;
                     const double si = sg[i], sj = sg[j];
@@ -329,7 +383,7 @@ __global__ void __launch_bounds__(kNT) k_prune(PruneArgs a)
     // ---- 5. survivors in order, and their radius histogram
     for (uint32_t base = 0; base < n; base += kNT) {
         const uint32_t i = base + tid;
-        const bool keep = i < n && alive[i];
+        const bool keep = i < n && (alive[i] & 1u);
         const unsigned long long bal = __ballot(keep);
         if (lane == 0)
             s_wave[wv] = (uint32_t)__popcll(bal);

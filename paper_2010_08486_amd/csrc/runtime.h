@@ -162,6 +162,8 @@ struct dog_context {
     dog::PinBuf h_input;           // staging of host frames
     dog::DevBuf prep;              // preprocessing: select state, histograms, weights
     dog::DevBuf prn;               // device pruning: FP64 ladder sigmas
+    std::vector<double> prn_sig;   // the sigmas `prn` holds
+    void* prn_sig_dev = nullptr;   // the buffer they were uploaded to
     dog::PinBuf h_prn;             // device pruning: sigma staging, then the kernel's output
     uint32_t prn_blobs = 0;        // blobs one pruning workgroup holds (from the LDS limit)
     uint32_t prn_pairs = 0;        // touching pairs it holds
