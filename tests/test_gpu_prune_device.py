@@ -154,3 +154,35 @@ def test_device_prune_errors_and_large_lists(dog, ctx):
     raw = many[order]
     raw["sigma"] = np.asarray(_ladder(dog, prm)[0], np.float32)[raw["scale"]]
     _check(dog, ctx, prm, raw)
+
+
+@pytest.mark.parametrize("coalesce", [False, True])
+def test_device_prune_blob_with_more_than_64_pairs(dog, ctx, coalesce):
+    # Blob A (sigma 16.8) is visited first; 70 small blobs (sigma 1, 3 px
+    # apart, so they do not touch each other) inside its disk come next in
+    # visiting order, then blob B (sigma 26.8) overlapping A, then more small
+    # blobs.  A removes the 70 small ones (its pairs span two groups of 64)
+    # and is removed at its pair with B; B then removes the later small blobs
+    # inside its disk, and the last row, outside both disks, stays.  The
+    # result is the oracle's in both modes.
+    prm = dog.Params(**dict(CAMERA, coalesce=coalesce))
+    sig = _ladder(dog, prm)[0]
+    rows = [(100, 500, 6)]
+    rows += [(y, x, 0) for y in (101, 104, 107, 110, 113) for x in range(480, 522, 3)]
+    rows += [(115, 500, 7)]
+    rows += [(y, x, 0) for y in (116, 119, 160) for x in range(480, 522, 3)]
+    B = dog.BLOB_DTYPE
+    raw = np.zeros(len(rows), B)
+    raw["y"] = [r[0] for r in rows]
+    raw["x"] = [r[1] for r in rows]
+    raw["scale"] = [r[2] for r in rows]
+    raw["response"] = np.linspace(0.1, 1.0, len(rows), dtype=np.float32)
+    raw = raw[np.lexsort((raw["scale"], raw["x"], raw["y"]))]
+    raw["sigma"] = np.asarray(sig, np.float32)[raw["scale"]]
+    got = _check(dog, ctx, prm, raw, seed=11)
+    kept = {(int(r["y"]), int(r["x"]), int(r["scale"])) for r in got}
+    assert (100, 500, 6) not in kept and (115, 500, 7) in kept
+    assert all((160, x, 0) in kept for x in range(480, 522, 3))
+    if not coalesce:   # (coalescing shrinks A as it goes, so it stops removing)
+        assert not any((y, x, 0) in kept
+                       for y in (101, 104, 107, 110, 113) for x in range(480, 522, 3))
