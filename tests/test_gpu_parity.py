@@ -145,6 +145,31 @@ def test_overflow_of_one_tile_below_capacity(dog, torch_mod):
             assert blobs.tobytes() == raw.tobytes()
 
 
+def test_overflowing_and_normal_tiles_in_one_frame(dog, torch_mod):
+    # a camera frame with a 200 x 200 constant block: more than the widest
+    # radius (42) inside the block every plane is constant, so each DoG plane
+    # is constant there and ties across the whole interior; with a negative
+    # threshold every voxel of each plane that is a maximum across scales is
+    # a local maximum, so the tiles over the interior hold more records than
+    # their LDS buffers and are walked again straight to the global list,
+    # while the other tiles flush as usual.  The records are exactly the
+    # local maxima of the GPU's own DoG cube.
+    torch = torch_mod
+    img = synth.camera_frame(seed=21, H=384, W=384, n_blobs=70)
+    img[100:300, 20:220] = 0.25
+    prm = dog.Params(1, 8, 1.6, -1.0, 1.0)
+    with dog.Context(0) as c:
+        t = _dev(torch, img)
+        raw = c.debug_candidates(t, prm)
+        _, D_g = c.debug_planes(t, prm)
+        check_candidates_exact(raw, D_g.cpu().numpy(), prm.threshold)
+        inside = (raw["y"] >= 190) & (raw["y"] < 210) & (raw["x"] >= 110) & (raw["x"] < 130)
+        n_in = int(inside.sum())   # whole planes of the 20 x 20 centre
+        assert n_in >= 400 and n_in % 400 == 0
+        assert c.detect_device(t, prm).tobytes() == raw.tobytes()   # overlap 1: no pruning
+        assert c.debug_candidates(t, prm).tobytes() == raw.tobytes()
+
+
 def test_repeat_runs_bitwise_identical(dog, ctx, torch_mod):
     img = synth.camera_frame(seed=3, H=512, W=384, n_blobs=120)
     t = _dev(torch_mod, img)
