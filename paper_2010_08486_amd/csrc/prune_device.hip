@@ -133,6 +133,7 @@ __global__ void __launch_bounds__(kNT) k_prune(PruneArgs a)
     __shared__ uint32_t s_part[kNT];
     __shared__ uint32_t s_wave[kNT / 64];
     __shared__ uint32_t s_hist[DOG_MAX_GAUSS];
+    __shared__ double s_sig[DOG_MAX_GAUSS];   // the ladder's FP64 sigmas
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63, wv = tid >> 6;
@@ -144,8 +145,10 @@ __global__ void __launch_bounds__(kNT) k_prune(PruneArgs a)
         s_out = 0;
         s_status = 0;
     }
-    for (uint32_t i = tid; i < DOG_MAX_GAUSS; i += kNT)
+    for (uint32_t i = tid; i < DOG_MAX_GAUSS; i += kNT) {
         s_hist[i] = 0;
+        s_sig[i] = i < (uint32_t)a.k ? a.sig64[i] : 0.0;
+    }
     __syncthreads();
 
     // ---- 1. gather this frame's records
@@ -243,7 +246,7 @@ __global__ void __launch_bounds__(kNT) k_prune(PruneArgs a)
         }
     }
     for (uint32_t i = tid; i < n; i += kNT) {
-        sg[i] = a.sig64[key_scale(key[i])];
+        sg[i] = s_sig[key_scale(key[i])];
         alive[i] = 1;
     }
     __syncthreads();
@@ -348,32 +351,38 @@ __global__ void __launch_bounds__(kNT) k_prune(PruneArgs a)
             }
         } else if (tid == 0) {
             // coalescing: a sigma may change at any pair, so one thread
-            // visits every pair in order, re-taking the test where it has
+            // visits every pair in order, re-taking the test where it has.
+            // Only this loop writes sg, and sg[i] only in blob i's own scan,
+            // so the blob's values stay in registers through its scan.
             for (uint32_t i = 0; i < n; ++i) {
-                if (!(alive[i] & 1u))
+                const uint32_t e0 = off[i], e1 = off[i + 1];
+                if (e0 == e1 || !(alive[i] & 1u))
                     continue;
-                for (uint32_t e = off[i]; e < off[i + 1]; ++e) {
-                    const uint32_t j = pairs[e] & 0x0fffu;
+                const uint64_t ki = key[i];
+                const int yi = key_y(ki), xi = key_x(ki);
+                const double si0 = s_sig[key_scale(ki)];
+                double si = sg[i];
+                for (uint32_t e = e0; e < e1; ++e) {
+                    const uint32_t w = pairs[e];
+                    const uint32_t j = w & 0x0fffu;
                     if (!(alive[j] & 1u))
                         continue;
-                    bool over = (pairs[e] & 0x8000u) != 0;
-                    const double si = sg[i], sj = sg[j];
-                    if (a.coalesce && (si != a.sig64[key_scale(key[i])] ||
-                                       sj != a.sig64[key_scale(key[j])]))
-                        over = overlap_fraction(key_y(key[i]), key_x(key[i]), si, key_y(key[j]),
-                                                key_x(key[j]), sj) > a.overlap;
+                    bool over = (w & 0x8000u) != 0;
+                    const double sj = sg[j];
+                    const uint64_t kj = key[j];
+                    if (si != si0 || sj != s_sig[key_scale(kj)])
+                        over = overlap_fraction(yi, xi, si, key_y(kj), key_x(kj), sj) > a.overlap;
                     if (!over)
                         continue;
                     const double mean = 0.5 * (si + sj);
                     if (si < sj) {
                         alive[i] = 0;
-                        if (a.coalesce)
-                            sg[j] = mean;
+                        sg[j] = mean;
                         break;
                     }
                     alive[j] = 0;
-                    if (a.coalesce)
-                        sg[i] = mean;
+                    si = mean;
+                    sg[i] = mean;
                 }
             }
         }
@@ -399,17 +408,17 @@ __global__ void __launch_bounds__(kNT) k_prune(PruneArgs a)
             b.y = key_y(k);
             b.x = key_x(k);
             b.scale = s;
-            b.sigma = (float)(a.coalesce ? sg[i] : a.sig64[s]);
+            b.sigma = (float)(a.coalesce ? sg[i] : s_sig[s]);
             b.response = resp[key_slot(k)];
             ob[pos] = b;
             // nearest ladder sigma to the output sigma, the lower on a tie
             const double v = (double)b.sigma;
             int bin = 0;
-            while (bin < a.k && a.sig64[bin] < v)
+            while (bin < a.k && s_sig[bin] < v)
                 ++bin;
             if (bin == a.k)
                 bin = a.k - 1;
-            else if (bin > 0 && v - a.sig64[bin - 1] <= a.sig64[bin] - v)
+            else if (bin > 0 && v - s_sig[bin - 1] <= s_sig[bin] - v)
                 bin -= 1;
             atomicAdd(&s_hist[bin], 1u);
         }
